@@ -1,0 +1,390 @@
+"""CPU oracle for the accelerated Jacobi-type method with adaptive restart.
+
+TEST INFRASTRUCTURE ONLY.  This module is the plain, slow reference that the
+GPU path is checked against.  Only the test suite, the smoke check and the
+CPU-baseline leg of the benchmark may import it; the product path never does.
+It shares no code with the HIP library: every step below is written from the
+paper (Liang, Pang, Toh, Yang, "Nesterov's accelerated Jacobi-type methods for
+large-scale symmetric positive semidefinite linear systems", arXiv 2407.03272).
+
+What it computes
+----------------
+For a consistent system Q x = b with Q symmetric positive semidefinite
+(Section 1, eq. (eq-linear-sys)), Algorithm 3 (Section 3) runs Algorithm 2's
+accelerated, restarted template with the proximal matrix S = J - Q, which
+turns the proximal subproblem of Algorithm 1 into the Jacobi-type step
+
+    x^t = y^t + J^{-1} (b - Q y^t)            (Section 3, the displayed update)
+
+with J the diagonal of eq. (J-diag): J_kk = Q_kk + sum_{j != k} |Q_kj|.  The
+momentum step is y^{t+1} = x^t + beta_t (x^t - x^{t-1}) with
+beta_t = (alpha_t - 1)/alpha_{t+1} and alpha_{t+1} = (1 + sqrt(1 + 4 alpha_t^2))/2
+(Algorithm 1).  The restart test of Algorithm 2/3 fires when
+t > K_re + K_l and <Q y^t - b, x^t - x^{t-1}> >= 0; it sets K_re = t,
+K_{l+1} = 2 K_l, l = l + 1, alpha_{t+1} = 1, y^{t+1} = x^{t-1} and
+x^t = x^{t-1}.
+
+Readings where the paper leaves a choice open (all shared with the GPU path
+by specification, not by code):
+
+* x^0 defaults to 0; K_0 defaults to 2 (the paper only requires K_0 >= 2).
+* Stopping: the paper stops on a relative objective gap with f* known
+  (Section 4); here the stop is on the relative residual
+  ||b - Q x^t|| / ||b|| <= tol.  The residual at y^t, ||Q y^t - b||, comes
+  free with the step and is the monitor; when it is <= tol the residual at
+  x^t is computed (one extra product) and the run stops if that is <= tol.
+  After a failed confirmation the next one waits ``confirm_gap`` iterations.
+  At t = 1, y^1 = x^0, so a monitor <= tol returns x^0 with 0 iterations.
+* A restart iteration counts as an iteration (its product was spent).
+* The table of update rules in Section 4 writes Q x^t in the accelerated
+  Jacobi row; Algorithm 3 writes Q y^t, which is what is done here.
+* A row of Q that is entirely zero gives J_kk = 0; J_kk := 1 is used there.
+* The momentum step is formed as x + beta*d with d = x - x_prev (equal to
+  (1+beta) x - beta x_prev in exact arithmetic).
+* The diagonal of eq. (J-diag) equals the row absolute sum sum_j |Q_kj|
+  because Q_kk >= 0 for a positive semidefinite Q; it is computed that way.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from decimal import Decimal, getcontext
+from typing import Callable, Iterable
+
+import numpy as np
+import scipy.sparse as sp
+
+STATUS_OK = 0
+STATUS_NOT_CONVERGED = 1
+STATUS_BREAKDOWN = -4
+
+
+def csr(rowptr, colidx, vals, dtype=np.float64) -> sp.csr_matrix:
+    n = len(rowptr) - 1
+    return sp.csr_matrix((np.asarray(vals, dtype=dtype), np.asarray(colidx), np.asarray(rowptr)),
+                         shape=(n, n))
+
+
+def jacobi_diagonal(Q: sp.csr_matrix) -> np.ndarray:
+    """Diagonal J of eq. (J-diag), Section 3: J_kk = Q_kk + sum_{j != k} |Q_kj|.
+
+    Computed as the row absolute sums |Q| 1 (a row-by-row sum in stored
+    order, in Q's own precision), which is the same quantity for PSD Q.
+    A zero row gives J_kk = 0, replaced by 1.
+    """
+    absQ = abs(Q)
+    J = np.asarray(absQ @ np.ones(Q.shape[0], dtype=Q.dtype))
+    J = J.copy()
+    J[J == 0] = 1
+    return J
+
+
+def objective(Q: sp.csr_matrix, b: np.ndarray, x: np.ndarray) -> float:
+    """f(x) = 1/2 <x, Q x> - <b, x>, eq. (eq-qp)."""
+    return 0.5 * float(x @ (Q @ x)) - float(b @ x)
+
+
+def alpha_next(alpha: float) -> float:
+    """alpha_{t+1} = (1 + sqrt(1 + 4 alpha_t^2)) / 2 (Algorithm 1)."""
+    return (1.0 + math.sqrt(1.0 + 4.0 * alpha * alpha)) / 2.0
+
+
+@dataclass
+class OracleResult:
+    x: np.ndarray
+    iterations: int
+    status: int
+    hist: list = field(default_factory=list)          # ||Q y^t - b|| / ||b||, t = 1..T
+    restarts: list = field(default_factory=list)      # iterations t at which a restart fired
+    s_log: list = field(default_factory=list)         # <Q y^t - b, x^t - x^{t-1}>
+    sabs_log: list = field(default_factory=list)      # sum_i |g_i d_i| (scale of s_t, for near-tie checks)
+    confirms: list = field(default_factory=list)      # (t, ||b - Q x^t|| / ||b||)
+    relres: float = float("nan")                      # residual of the returned x (when computed)
+
+
+def accelerated_jacobi(rowptr, colidx, vals, b, x0=None, *, tol: float = 1e-8, max_iter: int = 5000,
+                       restart: bool = True, k0: int = 2, D: np.ndarray | None = None,
+                       confirm_gap: int = 8, forced_restarts: Iterable[int] | None = None,
+                       callback: Callable | None = None) -> OracleResult:
+    """Algorithm 3 (Section 3) with diagonal J, in float64.
+
+    ``restart`` is the IsRestart switch of Algorithm 3 (False gives Algorithm 1
+    with S = J - Q).  ``D`` replaces J when given (Remark 1 allows any
+    invertible J with J - Q PSD).  ``forced_restarts``, when given, replaces
+    the restart test by that exact set of iterations (used to replay a run
+    whose restart test was a numerical tie).  ``callback(t, info)`` sees every
+    iteration's vectors (used by invariant tests).
+    """
+    Q = csr(rowptr, colidx, vals)
+    n = Q.shape[0]
+    b = np.asarray(b, dtype=np.float64)
+    J = jacobi_diagonal(Q) if D is None else np.asarray(D, dtype=np.float64).copy()
+    dinv = 1.0 / J
+    x0 = np.zeros(n) if x0 is None else np.asarray(x0, dtype=np.float64).copy()
+    forced = None if forced_restarts is None else set(int(t) for t in forced_restarts)
+
+    res = OracleResult(x=x0.copy(), iterations=0, status=STATUS_OK)
+    nb = float(np.linalg.norm(b))
+    if nb == 0.0:
+        res.x = np.zeros(n)
+        res.relres = 0.0
+        return res
+
+    # Algorithm 3 input: x^0 = y^1, alpha_1 = 1, l = 0, K_0, K_re = 0
+    x_prev = x0.copy()
+    y = x0.copy()
+    alpha = 1.0
+    K_re, K, ell = 0, int(k0), 0
+    last_confirm = -(1 << 62)
+    for t in range(1, max_iter + 1):
+        # line 4: x^t = y^t + J^{-1}(b - Q y^t)
+        u = Q @ y
+        g = u - b
+        x = y - dinv * g
+        mon = float(np.linalg.norm(g)) / nb
+        res.hist.append(mon)
+        if not math.isfinite(mon):
+            res.x, res.iterations, res.status = x_prev, t, STATUS_BREAKDOWN
+            return res
+        if t == 1 and mon <= tol:
+            res.x, res.iterations, res.relres = x0, 0, mon
+            return res
+        if mon <= tol and t >= last_confirm + confirm_gap:
+            rho = float(np.linalg.norm(b - Q @ x)) / nb
+            last_confirm = t
+            res.confirms.append((t, rho))
+            if rho <= tol:
+                res.x, res.iterations, res.relres = x, t, rho
+                if callback is not None:
+                    callback(t, dict(x=x, y=y, x_prev=x_prev, alpha=alpha, restarted=False, final=True))
+                return res
+        # line 5: restart test <Q y^t - b, x^t - x^{t-1}> >= 0 past the prohibition period
+        d = x - x_prev
+        s = float(g @ d)
+        res.s_log.append(s)
+        res.sabs_log.append(float(np.abs(g * d).sum()))
+        if not math.isfinite(s):
+            res.x, res.iterations, res.status = x_prev, t, STATUS_BREAKDOWN
+            return res
+        if forced is not None:
+            do_restart = t in forced
+        else:
+            do_restart = restart and t > K_re + K and s >= 0.0
+        if callback is not None:
+            callback(t, dict(x=x, y=y, x_prev=x_prev, alpha=alpha, restarted=do_restart, final=False))
+        if do_restart:
+            # lines 6-10: K_re = t, K_{l+1} = 2 K_l, l += 1, alpha_{t+1} = 1, y^{t+1} = x^{t-1}, x^t = x^{t-1}
+            K_re = t
+            K = 2 * K
+            ell += 1
+            res.restarts.append(t)
+            a_next = 1.0
+            y = x_prev.copy()
+        else:
+            # lines 12-13: alpha_{t+1}, y^{t+1} = x^t + beta_t (x^t - x^{t-1})
+            a_next = alpha_next(alpha)
+            beta = (alpha - 1.0) / a_next
+            y = x + beta * d
+            x_prev = x
+        alpha = a_next
+    res.x, res.iterations, res.status = x_prev, max_iter, STATUS_NOT_CONVERGED
+    res.relres = float(np.linalg.norm(b - Q @ x_prev)) / nb
+    return res
+
+
+@dataclass
+class MixedResult:
+    x: np.ndarray
+    status: int
+    outer: int                                   # FP64 residual evaluations
+    inner_total: int                             # FP32 inner iterations summed over refinement steps
+    relres_hist: list = field(default_factory=list)   # ||b - Q x_k|| / ||b|| per refinement step
+    inner_iters: list = field(default_factory=list)
+    inner_restarts: list = field(default_factory=list)
+
+
+def inner_solve_fp32(Q32: sp.csr_matrix, dinv32: np.ndarray, r32: np.ndarray, *, inner_tol: float,
+                     max_iter: int, restart: bool, k0: int):
+    """Algorithm 3 on Q d = r in float32 from d^0 = 0 with float64 reductions.
+
+    The product, the Jacobi step and the momentum step are float32 operations
+    (float32 accumulation in the row sums).  The restart inner product and the
+    monitor norm are accumulated in float64.  The solve stops when
+    ||Q y^t - r|| / ||r|| <= inner_tol and returns x^t, or returns x^T after
+    ``max_iter`` iterations.  Returns (d, iterations, restarts).
+    """
+    n = Q32.shape[0]
+    f32 = np.float32
+    nr = math.sqrt(float(np.dot(r32.astype(np.float64), r32.astype(np.float64))))
+    if nr == 0.0:
+        return np.zeros(n, dtype=f32), 0, []
+    x_prev = np.zeros(n, dtype=f32)
+    y = np.zeros(n, dtype=f32)
+    alpha = 1.0
+    K_re, K = 0, int(k0)
+    restarts = []
+    for t in range(1, max_iter + 1):
+        u = Q32 @ y
+        g = (u - r32).astype(f32)
+        x = (y - dinv32 * g).astype(f32)
+        g64 = g.astype(np.float64)
+        mon = math.sqrt(float(g64 @ g64)) / nr
+        if not math.isfinite(mon):
+            return x, t, restarts
+        if mon <= inner_tol:
+            return x, t, restarts
+        d = (x - x_prev).astype(f32)
+        s = float(g64 @ d.astype(np.float64))
+        if restart and t > K_re + K and s >= 0.0:
+            K_re, K = t, 2 * K
+            restarts.append(t)
+            a_next = 1.0
+            y = x_prev.copy()
+        else:
+            a_next = alpha_next(alpha)
+            beta = f32((alpha - 1.0) / a_next)
+            y = (x + beta * d).astype(f32)
+            x_prev = x
+        alpha = a_next
+    return x_prev, max_iter, restarts
+
+
+def accelerated_jacobi_mixed(rowptr, colidx, vals, b, x0=None, *, tol: float = 1e-8, max_refine: int = 50,
+                             inner_tol: float = 1e-4, inner_max_iter: int = 5000, restart: bool = True,
+                             k0: int = 2) -> MixedResult:
+    """Float32 inner Algorithm 3 inside float64 iterative refinement.
+
+    Outer step k: r_k = b - Q x_k with float64 values and accumulation; stop
+    when ||r_k|| / ||b|| <= tol; otherwise round r_k to float32, solve
+    Q d = r_k approximately with ``inner_solve_fp32`` (float32 copy of Q, J
+    from the float32 row absolute sums), and set x_{k+1} = x_k + d in float64.
+    Not a method of the paper: the paper's algorithm is the inner solver.
+    """
+    Q = csr(rowptr, colidx, vals)
+    Q32 = csr(rowptr, colidx, np.asarray(vals, dtype=np.float32), dtype=np.float32)
+    n = Q.shape[0]
+    J32 = jacobi_diagonal(Q32)
+    dinv32 = (np.float32(1.0) / J32).astype(np.float32)
+    b = np.asarray(b, dtype=np.float64)
+    x = np.zeros(n) if x0 is None else np.asarray(x0, dtype=np.float64).copy()
+    nb = float(np.linalg.norm(b))
+    out = MixedResult(x=x, status=STATUS_OK, outer=0, inner_total=0)
+    if nb == 0.0:
+        out.x = np.zeros(n)
+        return out
+    for k in range(max_refine + 1):
+        r = b - Q @ x
+        rho = float(np.linalg.norm(r)) / nb
+        out.outer += 1
+        out.relres_hist.append(rho)
+        if not math.isfinite(rho):
+            out.status = STATUS_BREAKDOWN
+            break
+        if rho <= tol:
+            out.x = x
+            return out
+        if k == max_refine:
+            break
+        r32 = r.astype(np.float32)
+        d, it, rs = inner_solve_fp32(Q32, dinv32, r32, inner_tol=inner_tol, max_iter=inner_max_iter,
+                                     restart=restart, k0=k0)
+        out.inner_total += it
+        out.inner_iters.append(it)
+        out.inner_restarts.append(rs)
+        x = x + d.astype(np.float64)
+    out.x = x
+    if out.status == STATUS_OK:
+        out.status = STATUS_NOT_CONVERGED
+    return out
+
+
+# ----------------------------------------------------------------------------
+# Section 4.1 worked example, reduced to two scalars
+# ----------------------------------------------------------------------------
+
+def sdd_scalar_run(n: int, *, tol: float = 1e-8, max_iter: int = 5000, restart: bool = True, k0: int = 2,
+                   confirm_gap: int = 8, digits: int = 60):
+    """Algorithm 3 on the Section 4.1 system in high-precision scalar arithmetic.
+
+    Q = (n+1) I - 1 1^T, b = 1, x^0 = 0.  Q 1 = 1, so every iterate is a
+    multiple of the all-ones vector: y^t = eta_t 1, x^t = xi_t 1.  With
+    J = (2n - 1) I from eq. (J-diag):  Q y^t - b = (eta_t - 1) 1,
+    xi_t = eta_t - (eta_t - 1)/(2n - 1), the restart inner product is
+    n (eta_t - 1)(xi_t - xi_{t-1}), ||Q y^t - b||/||b|| = |eta_t - 1| and
+    ||b - Q x^t||/||b|| = |1 - xi_t|.  Same control flow and readings as
+    ``accelerated_jacobi``; arithmetic in ``digits``-digit decimals.
+    Returns dict(iterations, status, restarts, xi (list), hist (list)).
+    """
+    getcontext().prec = digits
+    one = Decimal(1)
+    J = Decimal(2 * n - 1)
+    tol_d = Decimal(repr(tol))
+    xi_prev = Decimal(0)
+    eta = Decimal(0)
+    alpha = one
+    K_re, K = 0, k0
+    last_confirm = -(1 << 62)
+    restarts, xis, hist = [], [], []
+    for t in range(1, max_iter + 1):
+        g = eta - one
+        xi = eta - g / J
+        mon = abs(g)
+        hist.append(mon)
+        if t == 1 and mon <= tol_d:
+            return dict(iterations=0, status=STATUS_OK, restarts=restarts, xi=[Decimal(0)], hist=hist)
+        if mon <= tol_d and t >= last_confirm + confirm_gap:
+            last_confirm = t
+            if abs(one - xi) <= tol_d:
+                xis.append(xi)
+                return dict(iterations=t, status=STATUS_OK, restarts=restarts, xi=xis, hist=hist)
+        d = xi - xi_prev
+        s = Decimal(n) * g * d
+        if restart and t > K_re + K and s >= 0:
+            K_re, K = t, 2 * K
+            restarts.append(t)
+            a_next = one
+            eta = xi_prev
+            xis.append(xi_prev)
+        else:
+            a_next = (one + (one + 4 * alpha * alpha).sqrt()) / 2
+            beta = (alpha - one) / a_next
+            eta = xi + beta * d
+            xi_prev = xi
+            xis.append(xi)
+        alpha = a_next
+    return dict(iterations=max_iter, status=STATUS_NOT_CONVERGED, restarts=restarts, xi=xis, hist=hist)
+
+
+# ----------------------------------------------------------------------------
+# plain definitions the limits are checked against
+# ----------------------------------------------------------------------------
+
+def dense_solution_spd(rowptr, colidx, vals, b) -> np.ndarray:
+    """x* = Q^{-1} b by dense Cholesky (small SPD systems only)."""
+    Q = csr(rowptr, colidx, vals).toarray()
+    L = np.linalg.cholesky(Q)
+    z = np.linalg.solve(L, b)
+    return np.linalg.solve(L.T, z)
+
+
+def dense_limit_spsd(rowptr, colidx, vals, b, x0, J=None) -> np.ndarray:
+    """The solution the method converges to on a consistent singular system (small systems only).
+
+    Each step is J-affine and N^T Q = 0, N^T b = 0 for a null-space basis N, so
+    N^T J x^t = N^T J x^0 for every t (follows from the update of Section 3).
+    The limit is therefore x_p - N (N^T J N)^{-1} N^T J (x_p - x^0), with
+    x_p = Q^+ b the minimum-norm solution.
+    """
+    Qs = csr(rowptr, colidx, vals)
+    Q = Qs.toarray()
+    if J is None:
+        J = jacobi_diagonal(Qs)
+    w, V = np.linalg.eigh(Q)
+    thr = 1e-9 * max(1.0, abs(w).max())
+    N = V[:, np.abs(w) <= thr]
+    xp = np.linalg.pinv(Q, rcond=1e-12, hermitian=True) @ b
+    if N.shape[1] == 0:
+        return xp
+    JN = J[:, None] * N
+    c = np.linalg.solve(N.T @ JN, JN.T @ (xp - x0))
+    return xp - N @ c
