@@ -1,0 +1,174 @@
+/*
+ * naj.h -- C ABI of the MI355X (gfx950) solver for consistent symmetric
+ * positive semidefinite systems Q x = b by the Nesterov-accelerated,
+ * adaptively restarted Jacobi-type method of Liang, Pang, Toh and Yang,
+ * "Nesterov's accelerated Jacobi-type methods for large-scale symmetric
+ * positive semidefinite linear systems" (arXiv 2407.03272).
+ *
+ * The method (Algorithm 3, Section 3): with a diagonal J such that J - Q is
+ * positive semidefinite (default: eq. (J-diag), J_kk = Q_kk + sum_{j!=k}|Q_kj|),
+ *     x^t     = y^t + J^{-1} (b - Q y^t)
+ *     restart when t > K_re + K_l and <Q y^t - b, x^t - x^{t-1}> >= 0:
+ *             K_re = t, K_{l+1} = 2 K_l, alpha_{t+1} = 1, y^{t+1} = x^{t-1}, x^t = x^{t-1}
+ *     else    alpha_{t+1} = (1 + sqrt(1 + 4 alpha_t^2)) / 2,
+ *             y^{t+1} = x^t + (alpha_t - 1)/alpha_{t+1} (x^t - x^{t-1})
+ * starting from x^0 = y^1, alpha_1 = 1, K_re = 0, K_0 >= 2 (Algorithms 1 and 2).
+ *
+ * Conventions for every entry point:
+ *  - Matrix and vector arguments are DEVICE pointers on the current HIP
+ *    device unless a comment says "host".  Matrices are CSR: int32 row
+ *    pointers [n+1] (rowptr[0] = 0, non-decreasing, rowptr[n] = nnz), int32
+ *    column indices [nnz] in [0, n), float64 values [nnz].  Symmetry and
+ *    positive semidefiniteness are the caller's contract (Section 1).
+ *  - Multi-RHS vectors are row-interleaved: element (i, j) of an n x k block
+ *    is at [i * k + j].
+ *  - `stream` is a hipStream_t passed as void* (NULL = default stream).  All
+ *    device work is ordered on it.
+ *  - Return values: NAJ_OK (0) or NAJ_NOT_CONVERGED (1) mean the outputs are
+ *    valid; negative values are errors, with a message in naj_last_error().
+ *    No C++ exception crosses this boundary.  Inputs found invalid before
+ *    any device work (NAJ_EINVAL) leave every output untouched.
+ *  - Objects are not thread-safe: calls on one system/batch/server must not
+ *    overlap.  Different objects may be used from different threads.
+ */
+#ifndef NAJ_H
+#define NAJ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum naj_status {
+    NAJ_OK = 0,
+    NAJ_NOT_CONVERGED = 1,   /* max_iter reached; x holds the last iterate x^t           */
+    NAJ_EINVAL = -1,         /* invalid argument (bad CSR, tol <= 0, k0 < 2, D <= 0, ...) */
+    NAJ_ENOMEM = -2,         /* device allocation failed                                  */
+    NAJ_EDEVICE = -3,        /* HIP runtime error or device-side timeout                  */
+    NAJ_EBREAKDOWN = -4,     /* a reduction became NaN/Inf (x holds the last finite x^{t-1}) */
+    NAJ_EBUSY = -6           /* server: no slot or memory for the request now             */
+} naj_status;
+
+enum { NAJ_FP64 = 0, NAJ_MIXED = 1 };
+
+/* Solver options.  Fill with naj_opts_default() and override fields. */
+typedef struct naj_opts {
+    double  tol;            /* stop when ||b - Q x^t||_2 / ||b||_2 <= tol (> 0); default 1e-8          */
+    int32_t max_iter;       /* iteration cap (per inner solve in mixed mode); default 20000            */
+    int32_t restart;        /* IsRestart of Algorithm 3 (0 = Algorithm 1 with S = J - Q); default 1    */
+    int32_t k0;             /* K_0 >= 2 of Algorithm 2; default 2                                      */
+    int32_t confirm_gap;    /* iterations between residual confirmations (>= 1); default 8             */
+    int32_t precision;      /* NAJ_FP64 or NAJ_MIXED; default NAJ_FP64                                 */
+    double  inner_tol;      /* mixed: inner stop ||Q y - r|| / ||r|| <= inner_tol; default 1e-4        */
+    int32_t max_refine;     /* mixed: maximum float64 refinement steps; default 50                     */
+    int32_t reserved;       /* must be 0                                                               */
+} naj_opts;
+
+/* Per-right-hand-side result of a solve (host struct). */
+typedef struct naj_result {
+    int32_t status;         /* naj_status of this right-hand side                                     */
+    int32_t iterations;     /* FP64: t at which x^t was accepted (0 = x^0 accepted); mixed: inner total */
+    int32_t restarts;       /* number of restarts (FP64) / inner restarts summed (mixed)               */
+    int32_t confirmations;  /* residual confirmations (FP64) / float64 residual passes (mixed)        */
+    double  relres;         /* ||b - Q x||_2 / ||b||_2 of the returned x as computed on the device     */
+    int32_t hist_len;       /* entries written to hist                                                 */
+    int32_t nrestart_log;   /* entries written to the restart log                                      */
+    double  kernel_ms;      /* device time of the solve kernel(s), from HIP events on `stream`         */
+    int32_t passes;         /* matrix passes of the solve kernel(s): iterations + confirmations (+ refinement residuals) */
+    int32_t grid;           /* workgroups of the persistent solve kernel                               */
+} naj_result;
+
+typedef struct naj_system naj_system;
+
+/* Fill `o` with the defaults listed in naj_opts. */
+void naj_opts_default(naj_opts *o);
+
+/* Thread-local message describing the last error of this thread ("" if none). */
+const char *naj_last_error(void);
+
+/* Library version string, e.g. "naj 0.1 gfx950". */
+const char *naj_version(void);
+
+/*
+ * Create a system from a device CSR matrix (Section 3 setup: the diagonal J
+ * and the row-parallel layout of Q; the paper's "J construction" phase).
+ *   n, nnz          : dimensions, 1 <= n < 2^31, 0 <= nnz < 2^31
+ *   rowptr, colidx,
+ *   vals            : device CSR as in the conventions above; copied, so the
+ *                     caller may free them once `stream` has passed this call
+ *   D               : optional device float64[n] diagonal used in place of J
+ *                     (Remark 1: any invertible diagonal with D - Q PSD);
+ *                     NULL = J of eq. (J-diag).  Entries must be > 0.
+ *   stream          : stream for the setup work; the call returns after it
+ *   out             : receives the new system; owned by the caller, release
+ *                     with naj_destroy_system
+ * Errors: NAJ_EINVAL (sizes, non-monotone rowptr, colidx out of range, D <= 0),
+ * NAJ_ENOMEM, NAJ_EDEVICE.
+ */
+naj_status naj_create_system(int64_t n, int64_t nnz, const int32_t *rowptr, const int32_t *colidx,
+                             const double *vals, const double *D, void *stream, naj_system **out);
+
+/* Release a system and all device memory it owns.  NULL is ignored. */
+void naj_destroy_system(naj_system *sys);
+
+/*
+ * Query a system (host outputs, any may be NULL):
+ *   n, nnz          : dimensions
+ *   device_bytes    : device memory the system owns (matrix layouts, J,
+ *                     workspace), for admission control
+ *   layout          : 0 = sliced rows of 64 (one row per lane), 1 = CSR row groups
+ *   stored_entries  : matrix entries stored in the layout, padding included
+ */
+naj_status naj_system_info(const naj_system *sys, int64_t *n, int64_t *nnz, int64_t *device_bytes,
+                           int32_t *layout, int64_t *stored_entries);
+
+/*
+ * Solve Q x = b for one right-hand side (Algorithm 3; with NAJ_MIXED the same
+ * algorithm runs in float32 inside float64 iterative refinement).
+ *   b               : device float64[n]
+ *   x0              : device float64[n] starting point x^0, or NULL for 0
+ *   opts            : host options, NULL = defaults
+ *   x               : device float64[n] output (may alias x0, not b)
+ *   res             : host result, required
+ *   hist            : host float64[hist_cap] or NULL.  FP64: hist[t-1] =
+ *                     ||Q y^t - b|| / ||b|| (the monitor at y^t) for each
+ *                     iteration t.  Mixed: the float64 relative residual of
+ *                     each refinement step.
+ *   restart_log     : host int32[log_cap] or NULL: the iterations t at which
+ *                     a restart fired (FP64 only), in order
+ *   trace           : host float64[2 * trace_cap] or NULL: for FP64, per
+ *                     iteration t the restart inner product
+ *                     s_t = <Q y^t - b, x^t - x^{t-1}> at [2(t-1)] and
+ *                     sum_i |(Q y^t - b)_i (x^t - x^{t-1})_i| at [2(t-1)+1]
+ *   stream          : the call returns after the stream has finished the solve
+ * Errors: NAJ_EINVAL (bad options), NAJ_ENOMEM, NAJ_EDEVICE, NAJ_EBREAKDOWN.
+ */
+naj_status naj_solve(naj_system *sys, const double *b, const double *x0, const naj_opts *opts, double *x,
+                     naj_result *res, double *hist, int32_t hist_cap, int32_t *restart_log, int32_t log_cap,
+                     double *trace, int32_t trace_cap, void *stream);
+
+/*
+ * Stand-alone kernels of the hot path, for measurement and tests.
+ *
+ * naj_step: one fused pass of Algorithm 3's row update (Section 3 display):
+ *   x = y - J^{-1} (Q y - b) with y = p + beta (p - r) (r unused when beta == 0),
+ *   and the reductions s = <Q y - b, x - p>, gg = ||Q y - b||^2,
+ *   sabs = sum |(Q y - b)_i (x - p)_i| written to host red[3].
+ *   p, r, b, x are device float64[n]; x must not alias p, r or b.
+ */
+naj_status naj_step(naj_system *sys, const double *p, const double *r, double beta, const double *b,
+                    double *x, double *red, void *stream);
+
+/* naj_residual: out = b - Q x (device float64[n], out may be NULL) and host *rr = ||b - Q x||^2. */
+naj_status naj_residual(naj_system *sys, const double *x, const double *b, double *out, double *rr,
+                        void *stream);
+
+/* naj_diagonal: the diagonal J in use (eq. (J-diag) or the caller's D), device float64[n] out. */
+naj_status naj_diagonal(naj_system *sys, double *out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NAJ_H */

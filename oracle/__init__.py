@@ -2,5 +2,5 @@
 from .naj_oracle import (  # noqa: F401
     STATUS_BREAKDOWN, STATUS_NOT_CONVERGED, STATUS_OK, MixedResult, OracleResult,
     accelerated_jacobi, accelerated_jacobi_mixed, alpha_next, csr, dense_limit_spsd,
-    dense_solution_spd, inner_solve_fp32, jacobi_diagonal, objective, sdd_scalar_run,
+    dense_solution_spd, fused_step, inner_solve_fp32, jacobi_diagonal, objective, sdd_scalar_run,
 )

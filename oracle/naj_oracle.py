@@ -89,6 +89,25 @@ def alpha_next(alpha: float) -> float:
     return (1.0 + math.sqrt(1.0 + 4.0 * alpha * alpha)) / 2.0
 
 
+def fused_step(rowptr, colidx, vals, p, r, beta, b, D=None):
+    """One pass of Algorithm 3's row update with the momentum point formed from two iterates.
+
+    y = p + beta (p - r) (y = p when beta == 0; Algorithm 1, momentum step),
+    x = y + J^{-1}(b - Q y) (Section 3 update), and the reductions the restart
+    test and the monitor use: s = <Q y - b, x - p>, gg = ||Q y - b||^2,
+    sabs = sum |(Q y - b)_i (x - p)_i|.  Returns (x, s, gg, sabs).
+    """
+    Q = csr(rowptr, colidx, vals)
+    J = jacobi_diagonal(Q) if D is None else np.asarray(D, dtype=np.float64)
+    dinv = 1.0 / J
+    p = np.asarray(p, dtype=np.float64)
+    y = p.copy() if beta == 0.0 else p + beta * (p - np.asarray(r, dtype=np.float64))
+    g = Q @ y - np.asarray(b, dtype=np.float64)
+    x = y - dinv * g
+    d = x - p
+    return x, float(g @ d), float(g @ g), float(np.abs(g * d).sum())
+
+
 @dataclass
 class OracleResult:
     x: np.ndarray
@@ -137,7 +156,7 @@ def accelerated_jacobi(rowptr, colidx, vals, b, x0=None, *, tol: float = 1e-8, m
     K_re, K, ell = 0, int(k0), 0
     last_confirm = -(1 << 62)
     for t in range(1, max_iter + 1):
-        # line 4: x^t = y^t + J^{-1}(b - Q y^t)
+        # Jacobi-type step of Section 3: x^t = y^t + J^{-1}(b - Q y^t)
         u = Q @ y
         g = u - b
         x = y - dinv * g
@@ -158,7 +177,7 @@ def accelerated_jacobi(rowptr, colidx, vals, b, x0=None, *, tol: float = 1e-8, m
                 if callback is not None:
                     callback(t, dict(x=x, y=y, x_prev=x_prev, alpha=alpha, restarted=False, final=True))
                 return res
-        # line 5: restart test <Q y^t - b, x^t - x^{t-1}> >= 0 past the prohibition period
+        # restart test of Algorithm 2/3: <Q y^t - b, x^t - x^{t-1}> >= 0 past the prohibition period
         d = x - x_prev
         s = float(g @ d)
         res.s_log.append(s)
@@ -173,7 +192,7 @@ def accelerated_jacobi(rowptr, colidx, vals, b, x0=None, *, tol: float = 1e-8, m
         if callback is not None:
             callback(t, dict(x=x, y=y, x_prev=x_prev, alpha=alpha, restarted=do_restart, final=False))
         if do_restart:
-            # lines 6-10: K_re = t, K_{l+1} = 2 K_l, l += 1, alpha_{t+1} = 1, y^{t+1} = x^{t-1}, x^t = x^{t-1}
+            # restart branch: K_re = t, K_{l+1} = 2 K_l, l += 1, alpha_{t+1} = 1, y^{t+1} = x^{t-1}, x^t = x^{t-1}
             K_re = t
             K = 2 * K
             ell += 1
@@ -181,7 +200,7 @@ def accelerated_jacobi(rowptr, colidx, vals, b, x0=None, *, tol: float = 1e-8, m
             a_next = 1.0
             y = x_prev.copy()
         else:
-            # lines 12-13: alpha_{t+1}, y^{t+1} = x^t + beta_t (x^t - x^{t-1})
+            # momentum branch: alpha_{t+1}, y^{t+1} = x^t + beta_t (x^t - x^{t-1})
             a_next = alpha_next(alpha)
             beta = (alpha - 1.0) / a_next
             y = x + beta * d

@@ -1,0 +1,617 @@
+// C ABI of the gfx950 accelerated-Jacobi solver (declared in include/naj.h).
+//
+// Host side: validates the CSR input on the device, builds the sliced-row
+// layout, owns all device memory of a system, and launches the persistent
+// solve kernel cooperatively (all workgroups resident, so the grid barrier
+// inside it is safe).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/naj.h"
+#include "naj_device.h"
+#include "naj_solve.h"
+
+using namespace naj;
+
+namespace {
+
+thread_local std::string g_err;
+
+naj_status fail(naj_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) {                                                                  \
+      return fail(e_ == hipErrorOutOfMemory ? NAJ_ENOMEM : NAJ_EDEVICE, "%s failed: %s (%s:%d)", #expr, \
+                  hipGetErrorString(e_), __FILE__, __LINE__);                                \
+    }                                                                                        \
+  } while (0)
+
+int env_int(const char* name, int dflt) {
+  const char* v = getenv(name);
+  if (!v || !*v) return dflt;
+  return atoi(v);
+}
+
+// ---------------------------------------------------------------------------- setup kernels
+
+__global__ void k_check_rowptr(const int32_t* rowptr, int64_t n, int64_t nnz, int* flag) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    if (rowptr[i] > rowptr[i + 1]) atomicOr(flag, 1);
+    if (i == 0 && rowptr[0] != 0) atomicOr(flag, 2);
+    if (i == n - 1 && (int64_t)rowptr[n] != nnz) atomicOr(flag, 4);
+  }
+}
+
+__global__ void k_check_cols(const int32_t* colidx, int64_t nnz, int64_t n, int* flag) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nnz; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t c = colidx[i];
+    if (c < 0 || (int64_t)c >= n) atomicOr(flag, 8);
+  }
+}
+
+__global__ void k_check_vals(const double* vals, int64_t nnz, int* flag) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nnz; i += (int64_t)gridDim.x * blockDim.x) {
+    if (!(fabs(vals[i]) < __builtin_inf())) atomicOr(flag, 32);
+  }
+}
+
+__global__ void k_check_D(const double* D, int64_t n, double* dinv, int* flag) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double d = D[i];
+    if (!(d > 0.0) || !(d < __builtin_inf())) atomicOr(flag, 16);
+    dinv[i] = 1.0 / d;
+  }
+}
+
+// Width of each 64-row slice = its longest row.
+__global__ void k_slice_width(const int32_t* rowptr, int64_t n, int64_t nslices, int32_t* width) {
+  const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t s = row / kWave;
+  int len = row < n ? rowptr[row + 1] - rowptr[row] : 0;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) len = max(len, __shfl_xor(len, off, 64));
+  if ((threadIdx.x % kWave) == 0 && s < nslices) width[s] = len;
+}
+
+__global__ void k_sell_fill(const int32_t* rowptr, const int32_t* colidx, const double* vals, int64_t n,
+                            int64_t nslices, const int64_t* slice_ptr, int32_t* col, double* val, float* val32) {
+  const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t s = row / kWave;
+  if (s >= nslices) return;
+  const int lane = (int)(row % kWave);
+  const int64_t base = slice_ptr[s];
+  const int width = (int)((slice_ptr[s + 1] - base) / kWave);
+  const int64_t r0 = row < n ? rowptr[row] : 0;
+  const int len = row < n ? rowptr[row + 1] - (int32_t)r0 : 0;
+  const int32_t self = row < n ? (int32_t)row : 0;
+  for (int k = 0; k < width; ++k) {
+    const int64_t dst = base + (int64_t)k * kWave + lane;
+    if (k < len) {
+      const double v = vals[r0 + k];
+      col[dst] = colidx[r0 + k];
+      val[dst] = v;
+      val32[dst] = (float)v;
+    } else {
+      col[dst] = self;
+      val[dst] = 0.0;
+      val32[dst] = 0.0f;
+    }
+  }
+}
+
+// J of eq. (J-diag) as the row absolute sum in row order (equal for PSD Q), zero rows -> 1.
+__global__ void k_row_abs_sum(Sell A, const double* dinv, double* out) {
+  const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t s = row / kWave;
+  if (s >= A.nslices || row >= A.n) return;
+  if (dinv) {
+    out[row] = 1.0 / dinv[row];
+    return;
+  }
+  const int lane = (int)(row % kWave);
+  const int64_t base = A.slice_ptr[s];
+  const int width = (int)((A.slice_ptr[s + 1] - base) / kWave);
+  double asum = 0.0;
+  for (int k = 0; k < width; ++k) asum = asum + fabs(A.val[base + (int64_t)k * kWave + lane]);
+  out[row] = asum == 0.0 ? 1.0 : asum;
+}
+
+// One fused pass (stand-alone form of the solve kernel's iteration pass).
+template <bool USER_D>
+__global__ void __launch_bounds__(kBlock) k_step64(SolveArgs a, const double* P, const double* R, double beta,
+                                                   int bz, double* W) {
+  __shared__ double sh[3][kWavesPerBlock];
+  const int lane = threadIdx.x % kWave;
+  const WaveRange wr = wave_range(a.A.nslices, a.nxcd);
+  double p0 = 0.0, p1 = 0.0, p2 = 0.0;
+  for (int64_t s = wr.first; s < wr.end; s += wr.step) iter_slice<USER_D>(a, s, lane, P, R, W, beta, bz != 0, p0, p1, p2);
+  block_sum3(p0, p1, p2, sh);
+  if (threadIdx.x == 0) {
+    a.part[0 * (size_t)gridDim.x + blockIdx.x] = p0;
+    a.part[1 * (size_t)gridDim.x + blockIdx.x] = p1;
+    a.part[2 * (size_t)gridDim.x + blockIdx.x] = p2;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_resid64(Sell A, int nxcd, const double* X, const double* b, double* out,
+                                                    double* part) {
+  __shared__ double sh[3][kWavesPerBlock];
+  const int lane = threadIdx.x % kWave;
+  const WaveRange wr = wave_range(A.nslices, nxcd);
+  double p0 = 0.0, p1 = 0.0, p2 = 0.0;
+  for (int64_t s = wr.first; s < wr.end; s += wr.step) resid_slice(A, s, lane, X, b, out, p0);
+  block_sum3(p0, p1, p2, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = p0;
+}
+
+// Fixed-order sums of `parts` rows of G partials into out[0..parts-1].
+__global__ void k_reduce_fixed(const double* part, int G, int parts, double* out) {
+  const int lane = threadIdx.x;
+  for (int k = 0; k < parts; ++k) {
+    double v = 0.0;
+    for (int i = lane; i < G; i += kWave) v = v + part[(size_t)k * G + i];
+    v = wave_sum(v);
+    if (lane == 0) out[k] = v;
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------- system object
+
+struct naj_system {
+  int device = 0;
+  int64_t n = 0, nnz = 0;
+  int64_t nslices = 0, stored = 0;
+  int64_t* slice_ptr = nullptr;
+  int32_t* col = nullptr;
+  double* val = nullptr;
+  float* val32 = nullptr;
+  double* dinv = nullptr;          // caller's D as 1/D, or null
+  double* vec[3] = {nullptr, nullptr, nullptr};
+  double* part = nullptr;          // 3 * max_grid
+  Ctrl* ctrl = nullptr;
+  Barrier* bar = nullptr;
+  double* hist = nullptr;
+  int hist_cap_dev = 0;
+  double* trace = nullptr;
+  int trace_cap_dev = 0;
+  double* scal = nullptr;          // small device scratch for reductions
+  int max_grid = 0;
+  int grid = 0;                    // grid of the persistent kernel
+  int nxcd = 1;
+  int cus = 0;
+  long long spin_ticks = 0;
+  int64_t bytes = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+namespace {
+
+template <typename T>
+naj_status dev_alloc(naj_system* s, T** p, size_t count) {
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return fail(e == hipErrorOutOfMemory ? NAJ_ENOMEM : NAJ_EDEVICE, "hipMalloc(%zu bytes): %s", count * sizeof(T),
+                hipGetErrorString(e));
+  }
+  s->bytes += (int64_t)(count * sizeof(T));
+  return NAJ_OK;
+}
+
+void free_system(naj_system* s) {
+  if (!s) return;
+  (void)hipFree(s->slice_ptr);
+  (void)hipFree(s->col);
+  (void)hipFree(s->val);
+  (void)hipFree(s->val32);
+  (void)hipFree(s->dinv);
+  for (auto& v : s->vec) (void)hipFree(v);
+  (void)hipFree(s->part);
+  (void)hipFree(s->ctrl);
+  (void)hipFree(s->bar);
+  (void)hipFree(s->hist);
+  (void)hipFree(s->trace);
+  (void)hipFree(s->scal);
+  if (s->ev0) (void)hipEventDestroy(s->ev0);
+  if (s->ev1) (void)hipEventDestroy(s->ev1);
+  delete s;
+}
+
+int blocks_for(int64_t work, int per_block) {
+  int64_t b = (work + per_block - 1) / per_block;
+  if (b < 1) b = 1;
+  if (b > 65535LL * 16) b = 65535LL * 16;
+  return (int)b;
+}
+
+naj_status choose_grid(naj_system* s) {
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, s->device));
+  s->cus = prop.multiProcessorCount;
+  int coop = 0;
+  HIP_TRY(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, s->device));
+  if (!coop) return fail(NAJ_EDEVICE, "device %d does not support cooperative launches", s->device);
+  int occ64 = 0, occ64d = 0;
+  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ64, (const void*)k_solve64<false>, kBlock, 0));
+  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ64d, (const void*)k_solve64<true>, kBlock, 0));
+  int occ = std::min(occ64, occ64d);
+  if (occ < 1) return fail(NAJ_EDEVICE, "solve kernel cannot be resident (occupancy 0)");
+  int per_cu = std::min(occ, std::max(1, env_int("NAJ_WG_PER_CU", 4)));
+  int nxcd = env_int("NAJ_NXCD", (s->cus % 8 == 0) ? 8 : 1);
+  if (nxcd < 1) nxcd = 1;
+  int gmax = per_cu * s->cus;
+  gmax -= gmax % nxcd;
+  if (gmax < nxcd) return fail(NAJ_EDEVICE, "grid too small for %d L2 domains", nxcd);
+  // no more workgroups than give each wave one slice
+  int64_t want = (s->nslices + kWavesPerBlock - 1) / kWavesPerBlock;
+  want = ((want + nxcd - 1) / nxcd) * nxcd;
+  s->nxcd = nxcd;
+  s->max_grid = gmax;
+  s->grid = (int)std::min<int64_t>(gmax, std::max<int64_t>(nxcd, want));
+  int khz = 0;
+  HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, s->device));
+  if (khz <= 0) khz = 100000;
+  s->spin_ticks = (long long)khz * 1000LL * (long long)std::max(1, env_int("NAJ_SPIN_SECONDS", 4));
+  // a tiny limit makes every barrier wait give up: lets a test force the timeout path from the host
+  if (getenv("NAJ_SPIN_TICKS")) s->spin_ticks = std::max(0, env_int("NAJ_SPIN_TICKS", 0));
+  return NAJ_OK;
+}
+
+naj_status ensure_hist(naj_system* s, int hist_cap, int trace_cap) {
+  if (hist_cap > s->hist_cap_dev) {
+    (void)hipFree(s->hist);
+    s->hist = nullptr;
+    s->hist_cap_dev = 0;
+    naj_status st = dev_alloc(s, &s->hist, (size_t)hist_cap);
+    if (st != NAJ_OK) return st;
+    s->hist_cap_dev = hist_cap;
+  }
+  if (trace_cap > s->trace_cap_dev) {
+    (void)hipFree(s->trace);
+    s->trace = nullptr;
+    s->trace_cap_dev = 0;
+    naj_status st = dev_alloc(s, &s->trace, (size_t)trace_cap * 2);
+    if (st != NAJ_OK) return st;
+    s->trace_cap_dev = trace_cap;
+  }
+  return NAJ_OK;
+}
+
+Sell sell_of(const naj_system* s) {
+  Sell A;
+  A.slice_ptr = s->slice_ptr;
+  A.col = s->col;
+  A.val = s->val;
+  A.val32 = s->val32;
+  A.n = s->n;
+  A.nslices = s->nslices;
+  return A;
+}
+
+naj_status check_opts(const naj_opts& o) {
+  if (!(o.tol > 0.0) || !std::isfinite(o.tol)) return fail(NAJ_EINVAL, "tol must be finite and > 0 (got %g)", o.tol);
+  if (o.max_iter < 1) return fail(NAJ_EINVAL, "max_iter must be >= 1 (got %d)", o.max_iter);
+  if (o.k0 < 2) return fail(NAJ_EINVAL, "k0 must be >= 2 (got %d)", o.k0);
+  if (o.confirm_gap < 1) return fail(NAJ_EINVAL, "confirm_gap must be >= 1 (got %d)", o.confirm_gap);
+  if (o.precision != NAJ_FP64 && o.precision != NAJ_MIXED) return fail(NAJ_EINVAL, "unknown precision %d", o.precision);
+  if (o.precision == NAJ_MIXED) {
+    if (!(o.inner_tol > 0.0 && o.inner_tol < 1.0)) return fail(NAJ_EINVAL, "inner_tol must be in (0,1)");
+    if (o.max_refine < 1) return fail(NAJ_EINVAL, "max_refine must be >= 1");
+  }
+  if (o.reserved != 0) return fail(NAJ_EINVAL, "reserved field must be 0");
+  return NAJ_OK;
+}
+
+SolveArgs make_args(naj_system* s, const double* b, const naj_opts& o) {
+  SolveArgs a;
+  a.A = sell_of(s);
+  a.dinv = s->dinv;
+  a.b = b;
+  a.buf0 = s->vec[0];
+  a.buf1 = s->vec[1];
+  a.buf2 = s->vec[2];
+  a.part = s->part;
+  a.ctrl = s->ctrl;
+  a.bar = s->bar;
+  a.hist = s->hist;
+  a.trace = s->trace;
+  a.hist_cap = s->hist_cap_dev;
+  a.trace_cap = s->trace_cap_dev;
+  a.tol = o.tol;
+  a.max_iter = o.max_iter;
+  a.restart = o.restart ? 1 : 0;
+  a.confirm_gap = o.confirm_gap;
+  a.nxcd = s->nxcd;
+  a.spin_ticks = s->spin_ticks;
+  return a;
+}
+
+naj_status residual_norm2(naj_system* s, const double* x, const double* b, double* out, double* rr,
+                          hipStream_t st) {
+  const int G = s->max_grid;
+  hipLaunchKernelGGL(k_resid64, dim3(G), dim3(kBlock), 0, st, sell_of(s), s->nxcd, x, b, out, s->part);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_reduce_fixed, dim3(1), dim3(kWave), 0, st, s->part, G, 1, s->scal);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(rr, s->scal, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return NAJ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void naj_opts_default(naj_opts* o) {
+  if (!o) return;
+  o->tol = 1e-8;
+  o->max_iter = 20000;
+  o->restart = 1;
+  o->k0 = 2;
+  o->confirm_gap = 8;
+  o->precision = NAJ_FP64;
+  o->inner_tol = 1e-4;
+  o->max_refine = 50;
+  o->reserved = 0;
+}
+
+const char* naj_last_error(void) { return g_err.c_str(); }
+
+const char* naj_version(void) { return "naj 0.1 gfx950"; }
+
+naj_status naj_create_system(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* colidx, const double* vals,
+                             const double* D, void* stream, naj_system** out) {
+  g_err.clear();
+  if (!out) return fail(NAJ_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n < 1 || n >= (1LL << 31) - 64) return fail(NAJ_EINVAL, "n must be in [1, 2^31-64) (got %lld)", (long long)n);
+  if (nnz < 0 || nnz >= (1LL << 31)) return fail(NAJ_EINVAL, "nnz must be in [0, 2^31) (got %lld)", (long long)nnz);
+  if (!rowptr || (nnz > 0 && (!colidx || !vals))) return fail(NAJ_EINVAL, "null CSR pointer");
+  hipStream_t st = (hipStream_t)stream;
+  naj_system* s = new naj_system();
+  naj_status rc = NAJ_OK;
+  int* flag = nullptr;
+  int32_t* width = nullptr;
+  int hflag = 0;
+  std::vector<int32_t> hw;
+  std::vector<int64_t> hp;
+#define STEP(x)              \
+  do {                       \
+    rc = (x);                \
+    if (rc != NAJ_OK) goto bad; \
+  } while (0)
+#define HSTEP(expr)                                                                                   \
+  do {                                                                                                \
+    hipError_t e_ = (expr);                                                                           \
+    if (e_ != hipSuccess) {                                                                           \
+      rc = fail(e_ == hipErrorOutOfMemory ? NAJ_ENOMEM : NAJ_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+      goto bad;                                                                                       \
+    }                                                                                                 \
+  } while (0)
+  HSTEP(hipGetDevice(&s->device));
+  s->n = n;
+  s->nnz = nnz;
+  s->nslices = (n + kWave - 1) / kWave;
+  HSTEP(hipMalloc((void**)&flag, sizeof(int)));
+  HSTEP(hipMemsetAsync(flag, 0, sizeof(int), st));
+  hipLaunchKernelGGL(k_check_rowptr, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, rowptr, n, nnz, flag);
+  HSTEP(hipGetLastError());
+  HSTEP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  HSTEP(hipStreamSynchronize(st));
+  if (hflag) {
+    rc = fail(NAJ_EINVAL, "invalid rowptr (flags 0x%x: 1 decreasing, 2 rowptr[0]!=0, 4 rowptr[n]!=nnz)", hflag);
+    goto bad;
+  }
+  if (nnz > 0) {
+    hipLaunchKernelGGL(k_check_cols, dim3(blocks_for(nnz, kBlock)), dim3(kBlock), 0, st, colidx, nnz, n, flag);
+    HSTEP(hipGetLastError());
+    hipLaunchKernelGGL(k_check_vals, dim3(blocks_for(nnz, kBlock)), dim3(kBlock), 0, st, vals, nnz, flag);
+    HSTEP(hipGetLastError());
+  }
+  if (D) {
+    STEP(dev_alloc(s, &s->dinv, (size_t)n));
+    hipLaunchKernelGGL(k_check_D, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, D, n, s->dinv, flag);
+    HSTEP(hipGetLastError());
+  }
+  HSTEP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  HSTEP(hipStreamSynchronize(st));
+  if (hflag) {
+    rc = fail(NAJ_EINVAL, "invalid input (flags 0x%x: 8 column index out of range, 16 D not finite and > 0, "
+              "32 value not finite)", hflag);
+    goto bad;
+  }
+  // sliced-row layout
+  HSTEP(hipMalloc((void**)&width, sizeof(int32_t) * s->nslices));
+  hipLaunchKernelGGL(k_slice_width, dim3(blocks_for(s->nslices * kWave, kBlock)), dim3(kBlock), 0, st, rowptr, n,
+                     s->nslices, width);
+  HSTEP(hipGetLastError());
+  hw.resize(s->nslices);
+  HSTEP(hipMemcpyAsync(hw.data(), width, sizeof(int32_t) * s->nslices, hipMemcpyDeviceToHost, st));
+  HSTEP(hipStreamSynchronize(st));
+  hp.resize(s->nslices + 1);
+  hp[0] = 0;
+  for (int64_t i = 0; i < s->nslices; ++i) hp[i + 1] = hp[i] + (int64_t)hw[i] * kWave;
+  s->stored = hp[s->nslices];
+  STEP(dev_alloc(s, &s->slice_ptr, (size_t)s->nslices + 1));
+  STEP(dev_alloc(s, &s->col, (size_t)s->stored));
+  STEP(dev_alloc(s, &s->val, (size_t)s->stored));
+  STEP(dev_alloc(s, &s->val32, (size_t)s->stored));
+  HSTEP(hipMemcpyAsync(s->slice_ptr, hp.data(), sizeof(int64_t) * (s->nslices + 1), hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_sell_fill, dim3(blocks_for(s->nslices * kWave, kBlock)), dim3(kBlock), 0, st, rowptr, colidx,
+                     vals, n, s->nslices, s->slice_ptr, s->col, s->val, s->val32);
+  HSTEP(hipGetLastError());
+  STEP(choose_grid(s));
+  for (auto& v : s->vec) STEP(dev_alloc(s, &v, (size_t)n));
+  STEP(dev_alloc(s, &s->part, (size_t)3 * s->max_grid));
+  STEP(dev_alloc(s, &s->ctrl, 1));
+  STEP(dev_alloc(s, &s->bar, 1));
+  STEP(dev_alloc(s, &s->scal, 8));
+  HSTEP(hipEventCreate(&s->ev0));
+  HSTEP(hipEventCreate(&s->ev1));
+  HSTEP(hipStreamSynchronize(st));
+  (void)hipFree(flag);
+  (void)hipFree(width);
+  *out = s;
+  return NAJ_OK;
+bad:
+  if (flag) (void)hipFree(flag);
+  if (width) (void)hipFree(width);
+  free_system(s);
+  return rc;
+#undef STEP
+#undef HSTEP
+}
+
+void naj_destroy_system(naj_system* s) {
+  if (!s) return;
+  (void)hipDeviceSynchronize();
+  free_system(s);
+}
+
+naj_status naj_system_info(const naj_system* s, int64_t* n, int64_t* nnz, int64_t* device_bytes, int32_t* layout,
+                           int64_t* stored_entries) {
+  if (!s) return fail(NAJ_EINVAL, "system is NULL");
+  if (n) *n = s->n;
+  if (nnz) *nnz = s->nnz;
+  if (device_bytes) *device_bytes = s->bytes;
+  if (layout) *layout = 0;
+  if (stored_entries) *stored_entries = s->stored;
+  return NAJ_OK;
+}
+
+naj_status naj_solve(naj_system* s, const double* b, const double* x0, const naj_opts* opts, double* x,
+                     naj_result* res, double* hist, int32_t hist_cap, int32_t* restart_log, int32_t log_cap,
+                     double* trace, int32_t trace_cap, void* stream) {
+  g_err.clear();
+  if (!s) return fail(NAJ_EINVAL, "system is NULL");
+  if (!b || !x || !res) return fail(NAJ_EINVAL, "b, x and res are required");
+  if (x == b) return fail(NAJ_EINVAL, "x must not alias b");
+  naj_opts o;
+  if (opts) o = *opts; else naj_opts_default(&o);
+  naj_status rc = check_opts(o);
+  if (rc != NAJ_OK) return rc;
+  if (o.precision != NAJ_FP64) return fail(NAJ_EINVAL, "mixed precision is not available in this build");
+  if ((hist && hist_cap < 0) || (trace && trace_cap < 0) || (restart_log && log_cap < 0))
+    return fail(NAJ_EINVAL, "negative capacity");
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(s->device));
+  rc = ensure_hist(s, hist ? hist_cap : 0, trace ? trace_cap : 0);
+  if (rc != NAJ_OK) return rc;
+  if (x0) HIP_TRY(hipMemcpyAsync(s->vec[0], x0, sizeof(double) * s->n, hipMemcpyDeviceToDevice, st));
+  else HIP_TRY(hipMemsetAsync(s->vec[0], 0, sizeof(double) * s->n, st));
+  hipLaunchKernelGGL(k_solve_init, dim3(1), dim3(64), 0, st, s->ctrl, s->bar, o.k0);
+  HIP_TRY(hipGetLastError());
+  SolveArgs a = make_args(s, b, o);
+  if (!hist) a.hist = nullptr, a.hist_cap = 0;
+  else a.hist_cap = std::min(hist_cap, s->hist_cap_dev);
+  if (!trace) a.trace = nullptr, a.trace_cap = 0;
+  else a.trace_cap = std::min(trace_cap, s->trace_cap_dev);
+  void* kargs[] = {&a};
+  const void* fn = s->dinv ? (const void*)k_solve64<true> : (const void*)k_solve64<false>;
+  HIP_TRY(hipEventRecord(s->ev0, st));
+  HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(s->grid), dim3(kBlock), kargs, 0, st));
+  HIP_TRY(hipEventRecord(s->ev1, st));
+  hipLaunchKernelGGL(k_copy_result, dim3(blocks_for(s->n, kBlock * 4)), dim3(kBlock), 0, st, s->ctrl, s->vec[0],
+                     s->vec[1], s->vec[2], x, s->n);
+  HIP_TRY(hipGetLastError());
+  Ctrl hc;
+  HIP_TRY(hipMemcpyAsync(&hc, s->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  const int hl = std::min(hc.hist_len, a.hist_cap);
+  if (hist && hl > 0) HIP_TRY(hipMemcpy(hist, s->hist, sizeof(double) * hl, hipMemcpyDeviceToHost));
+  const int tl = std::min(hc.hist_len, a.trace_cap);
+  if (trace && tl > 0) HIP_TRY(hipMemcpy(trace, s->trace, sizeof(double) * 2 * tl, hipMemcpyDeviceToHost));
+  int nlog = std::min(hc.restarts, (int)kRestartLogCap);
+  if (restart_log) {
+    nlog = std::min(nlog, (int)log_cap);
+    for (int i = 0; i < nlog; ++i) restart_log[i] = hc.restart_log[i];
+  }
+  res->status = hc.status;
+  res->iterations = hc.iterations;
+  res->restarts = hc.restarts;
+  res->confirmations = hc.confirms;
+  res->relres = hc.relres;
+  res->hist_len = hist ? hl : 0;
+  res->nrestart_log = restart_log ? nlog : 0;
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, s->ev0, s->ev1));
+  res->kernel_ms = ms;
+  res->passes = hc.hist_len + hc.confirms;
+  res->grid = s->grid;
+  if (hc.timeout) {
+    res->status = NAJ_EDEVICE;
+    return fail(NAJ_EDEVICE, "grid barrier wait timed out inside the solve kernel");
+  }
+  if (hc.status == ST_NOT_CONVERGED || hc.status == ST_BREAKDOWN) {
+    double rr = 0.0;
+    rc = residual_norm2(s, x, b, nullptr, &rr, st);
+    if (rc != NAJ_OK) return rc;
+    res->relres = std::sqrt(rr) / hc.nb;
+  }
+  if (hc.status == ST_BREAKDOWN) return fail(NAJ_EBREAKDOWN, "NaN/Inf in a reduction at iteration %d", hc.iterations);
+  return (naj_status)hc.status;
+}
+
+naj_status naj_step(naj_system* s, const double* p, const double* r, double beta, const double* b, double* x,
+                    double* red, void* stream) {
+  g_err.clear();
+  if (!s || !p || !b || !x || !red) return fail(NAJ_EINVAL, "null argument");
+  if (x == p || x == r || x == b) return fail(NAJ_EINVAL, "x must not alias p, r or b");
+  if (beta != 0.0 && !r) return fail(NAJ_EINVAL, "r is required when beta != 0");
+  hipStream_t st = (hipStream_t)stream;
+  naj_opts o;
+  naj_opts_default(&o);
+  SolveArgs a = make_args(s, b, o);
+  const int G = s->max_grid;
+  const int bz = beta == 0.0 ? 1 : 0;
+  if (s->dinv)
+    hipLaunchKernelGGL(k_step64<true>, dim3(G), dim3(kBlock), 0, st, a, p, bz ? p : r, beta, bz, x);
+  else
+    hipLaunchKernelGGL(k_step64<false>, dim3(G), dim3(kBlock), 0, st, a, p, bz ? p : r, beta, bz, x);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_reduce_fixed, dim3(1), dim3(kWave), 0, st, s->part, G, 3, s->scal);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(red, s->scal, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return NAJ_OK;
+}
+
+naj_status naj_residual(naj_system* s, const double* x, const double* b, double* out, double* rr, void* stream) {
+  g_err.clear();
+  if (!s || !x || !b || !rr) return fail(NAJ_EINVAL, "null argument");
+  return residual_norm2(s, x, b, out, rr, (hipStream_t)stream);
+}
+
+naj_status naj_diagonal(naj_system* s, double* out, void* stream) {
+  g_err.clear();
+  if (!s || !out) return fail(NAJ_EINVAL, "null argument");
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_row_abs_sum, dim3(blocks_for(s->nslices * kWave, kBlock)), dim3(kBlock), 0, st, sell_of(s),
+                     s->dinv, out);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(st));
+  return NAJ_OK;
+}
+
+}  // extern "C"

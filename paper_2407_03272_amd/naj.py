@@ -1,0 +1,254 @@
+"""Python binding of the C-ABI library libnaj.so (ctypes; argument marshalling only).
+
+Every step of the solver runs in the library's HIP kernels.  PyTorch provides
+device memory and streams: tensors are passed to the library as raw device
+pointers, the current torch stream as the hipStream_t.  Names follow
+include/naj.h.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libnaj.so")
+HEADER_PATH = os.path.join(os.path.dirname(_PKG), "include", "naj.h")
+
+NAJ_OK = 0
+NAJ_NOT_CONVERGED = 1
+NAJ_EINVAL = -1
+NAJ_ENOMEM = -2
+NAJ_EDEVICE = -3
+NAJ_EBREAKDOWN = -4
+NAJ_EBUSY = -6
+NAJ_FP64 = 0
+NAJ_MIXED = 1
+
+
+class NajError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"naj status {status}: {msg}")
+        self.status = status
+
+
+class NajOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("restart", ctypes.c_int32),
+                ("k0", ctypes.c_int32), ("confirm_gap", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class NajResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iterations", ctypes.c_int32), ("restarts", ctypes.c_int32),
+                ("confirmations", ctypes.c_int32), ("relres", ctypes.c_double), ("hist_len", ctypes.c_int32),
+                ("nrestart_log", ctypes.c_int32), ("kernel_ms", ctypes.c_double), ("passes", ctypes.c_int32),
+                ("grid", ctypes.c_int32)]
+
+
+_lib = None
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+_D = ctypes.c_double
+
+_SIGS = {
+    "naj_opts_default": (None, [ctypes.POINTER(NajOpts)]),
+    "naj_last_error": (ctypes.c_char_p, []),
+    "naj_version": (ctypes.c_char_p, []),
+    "naj_create_system": (ctypes.c_int, [_I64, _I64, _P, _P, _P, _P, _P, ctypes.POINTER(_P)]),
+    "naj_destroy_system": (None, [_P]),
+    "naj_system_info": (ctypes.c_int, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I64),
+                                       ctypes.POINTER(_I32), ctypes.POINTER(_I64)]),
+    "naj_solve": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(NajOpts), _P, ctypes.POINTER(NajResult), _P, _I32,
+                                 _P, _I32, _P, _I32, _P]),
+    "naj_step": (ctypes.c_int, [_P, _P, _P, _D, _P, _P, _P, _P]),
+    "naj_residual": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    "naj_diagonal": (ctypes.c_int, [_P, _P, _P]),
+}
+
+
+def header_functions(path: str = HEADER_PATH) -> list[str]:
+    """Names of the functions declared in include/naj.h."""
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(naj_[a-z0-9_]+)\s*\(", text)))
+
+
+def load(path: str = LIB_PATH):
+    """Load libnaj.so (fails loudly when it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build the HIP library first (python -m paper_2407_03272_amd.build "
+                           "or __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _check(st: int):
+    if st < 0:
+        raise NajError(st, load().naj_last_error().decode())
+    return st
+
+
+def default_opts(**kw) -> NajOpts:
+    o = NajOpts()
+    load().naj_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+@dataclass
+class SolveInfo:
+    status: int
+    iterations: int
+    restarts: int
+    confirmations: int
+    relres: float
+    hist: np.ndarray = field(default_factory=lambda: np.zeros(0))
+    restart_log: list = field(default_factory=list)
+    trace: np.ndarray = field(default_factory=lambda: np.zeros((0, 2)))
+    kernel_ms: float = 0.0
+    passes: int = 0
+    grid: int = 0
+
+
+class System:
+    """A system Q x = b resident on the GPU (naj_create_system).
+
+    rowptr, colidx: int32 CSR arrays; vals: float64; D: optional float64
+    diagonal replacing J.  Accepts numpy arrays or torch tensors; host arrays
+    are copied to ``device``.
+    """
+
+    def __init__(self, rowptr, colidx, vals, D=None, device="cuda:0", stream=None):
+        torch = _torch()
+        lib = load()
+        self.device = torch.device(device)
+        self._rowptr = self._dev(rowptr, torch.int32)
+        self._colidx = self._dev(colidx, torch.int32)
+        self._vals = self._dev(vals, torch.float64)
+        self._D = None if D is None else self._dev(D, torch.float64)
+        self.n = int(self._rowptr.numel() - 1)
+        self.nnz = int(self._colidx.numel())
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            st = lib.naj_create_system(self.n, self.nnz, _ptr(self._rowptr), _ptr(self._colidx), _ptr(self._vals),
+                                       _ptr(self._D), _stream_ptr(stream), ctypes.byref(h))
+        _check(st)
+        self._h = h
+        # inputs are copied by the library; drop our references
+        self._rowptr = self._colidx = self._vals = self._D = None
+
+    def _dev(self, a, dtype):
+        torch = _torch()
+        if isinstance(a, torch.Tensor):
+            return a.to(device=self.device, dtype=dtype).contiguous()
+        return torch.as_tensor(np.ascontiguousarray(a)).to(device=self.device, dtype=dtype).contiguous()
+
+    def vec(self, a):
+        return self._dev(a, _torch().float64)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().naj_destroy_system(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        n, nnz, by, st = _I64(), _I64(), _I64(), _I64()
+        lay = _I32()
+        _check(load().naj_system_info(self._h, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(by),
+                                      ctypes.byref(lay), ctypes.byref(st)))
+        return dict(n=n.value, nnz=nnz.value, device_bytes=by.value, layout=lay.value, stored_entries=st.value)
+
+    def solve(self, b, x0=None, *, out=None, hist_cap: int | None = None, trace: bool = False, stream=None,
+              **opts) -> tuple:
+        """naj_solve: returns (x, SolveInfo).  Options as in naj_opts (tol, max_iter, restart, k0, ...)."""
+        torch = _torch()
+        lib = load()
+        o = default_opts(**opts)
+        b = self.vec(b)
+        x0 = None if x0 is None else self.vec(x0)
+        x = out if out is not None else torch.empty(self.n, dtype=torch.float64, device=self.device)
+        cap = o.max_iter if hist_cap is None else hist_cap
+        hist = np.zeros(max(cap, 1), dtype=np.float64)
+        rlog = np.zeros(64, dtype=np.int32)
+        tr = np.zeros((max(cap, 1), 2), dtype=np.float64) if trace else None
+        res = NajResult()
+        with torch.cuda.device(self.device):
+            st = lib.naj_solve(self._h, _ptr(b), _ptr(x0), ctypes.byref(o), _ptr(x), ctypes.byref(res),
+                               hist.ctypes.data_as(_P) if cap > 0 else None, cap,
+                               rlog.ctypes.data_as(_P), 64,
+                               tr.ctypes.data_as(_P) if trace else None, cap if trace else 0,
+                               _stream_ptr(stream))
+        if st < 0 and st != NAJ_EBREAKDOWN:
+            _check(st)
+        info = SolveInfo(res.status, res.iterations, res.restarts, res.confirmations, res.relres,
+                         hist[:res.hist_len].copy(), rlog[:res.nrestart_log].tolist(),
+                         tr[:res.hist_len].copy() if trace else np.zeros((0, 2)),
+                         res.kernel_ms, res.passes, res.grid)
+        return x, info
+
+    def step(self, p, r, beta: float, b, stream=None):
+        """naj_step: one fused pass; returns (x, (s, gg, sabs))."""
+        torch = _torch()
+        p = self.vec(p)
+        r = None if r is None else self.vec(r)
+        b = self.vec(b)
+        x = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        red = np.zeros(3, dtype=np.float64)
+        with torch.cuda.device(self.device):
+            _check(load().naj_step(self._h, _ptr(p), _ptr(r), float(beta), _ptr(b), _ptr(x),
+                                   red.ctypes.data_as(_P), _stream_ptr(stream)))
+        return x, tuple(red)
+
+    def residual(self, x, b, want_vector: bool = False, stream=None):
+        """naj_residual: (b - Q x or None, ||b - Q x||^2)."""
+        torch = _torch()
+        x = self.vec(x)
+        b = self.vec(b)
+        out = torch.empty(self.n, dtype=torch.float64, device=self.device) if want_vector else None
+        rr = ctypes.c_double()
+        with torch.cuda.device(self.device):
+            _check(load().naj_residual(self._h, _ptr(x), _ptr(b), _ptr(out), ctypes.byref(rr), _stream_ptr(stream)))
+        return out, rr.value
+
+    def diagonal(self, stream=None):
+        torch = _torch()
+        out = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            _check(load().naj_diagonal(self._h, _ptr(out), _stream_ptr(stream)))
+        return out

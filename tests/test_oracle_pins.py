@@ -101,7 +101,7 @@ def test_spmv_exact_on_integer_matrix():
 @pytest.mark.parametrize("maker", [_tiny_spd, _tiny_laplacian])
 def test_step_solves_proximal_subproblem(maker):
     """Lemma 1's optimality condition with S = J - Q: Q x^t - b + S (x^t - y^t) = 0 at every iteration
-    (x^t is the argmin of line 3 of Algorithm 1/2; Section 3 turns it into the Jacobi-type step)."""
+    (x^t is the argmin of the proximal subproblem of Algorithms 1/2; Section 3 turns it into the Jacobi-type step)."""
     rowptr, colidx, vals = maker()
     Q = _dense(rowptr, colidx, vals)
     J = O.jacobi_diagonal(O.csr(rowptr, colidx, vals))
@@ -185,7 +185,7 @@ def test_restart_schedule_and_theorem2(k0):
       ||x - x*||_S^2 = 2 (f(x^0) - f*) lambda_max(Q^{-1/2} S Q^{-1/2});
     * restarts only past the prohibition period: gap since the last restart > K_0 2^l, and
       l <= log2(t + 2) - 1 (Theorem 2 proof);
-    * every restart saw <Q y^t - b, x^t - x^{t-1}> >= 0 and no eligible iteration skipped one (Algorithm 2 line 4)."""
+    * every restart saw <Q y^t - b, x^t - x^{t-1}> >= 0 and no eligible iteration skipped one (the restart test of Algorithm 2)."""
     rowptr, colidx, vals = _tiny_spd(120, 17)
     Q = _dense(rowptr, colidx, vals)
     rng = np.random.default_rng(3)
