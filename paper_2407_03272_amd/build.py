@@ -13,7 +13,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libnaj.so")
 SOURCES = ["naj_api.hip"]
-HEADERS = ["naj_device.h", "naj_solve.h"]
+HEADERS = ["naj_device.h", "naj_solve.h", "naj_partition.h"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
@@ -34,15 +34,17 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = True) -> str:
+def build(verbose: bool = True, out: str | None = None, defines: tuple = ()) -> str:
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-I", os.path.join(os.path.dirname(PKG), "include"), "-o", tmp, *srcs]
+    lib = out or LIB
+    tmp = lib + ".tmp"
+    cmd = [hipcc(), *HIPCC_FLAGS, *[f"-D{d}" for d in defines], "-I", os.path.join(os.path.dirname(PKG), "include"),
+           "-o", tmp, *srcs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True, cwd=CSRC)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

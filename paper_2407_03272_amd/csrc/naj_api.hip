@@ -134,42 +134,50 @@ __global__ void k_row_abs_sum(Sell A, const double* dinv, double* out) {
   out[row] = asum == 0.0 ? 1.0 : asum;
 }
 
+constexpr int kAux = 256;   // block size of the stand-alone one-pass kernels
+
 // One fused pass (stand-alone form of the solve kernel's iteration pass).
 template <bool USER_D>
-__global__ void __launch_bounds__(kBlock) k_step64(SolveArgs a, const double* P, const double* R, double beta,
-                                                   int bz, double* W) {
-  __shared__ double sh[3][kWavesPerBlock];
+__global__ void __launch_bounds__(kAux) k_step64(SolveArgs a, const double* P, const double* R, double beta,
+                                                 int bz, double* W) {
+  __shared__ double sh[3][kAux / kWave];
   const int lane = threadIdx.x % kWave;
-  const WaveRange wr = wave_range(a.A.nslices, a.nxcd);
+  const WaveRange wr = wave_range<kAux>(a.A.nslices, a.nxcd);
   double p0 = 0.0, p1 = 0.0, p2 = 0.0;
   for (int64_t s = wr.first; s < wr.end; s += wr.step) iter_slice<USER_D>(a, s, lane, P, R, W, beta, bz != 0, p0, p1, p2);
-  block_sum3(p0, p1, p2, sh);
+  block_sum3<kAux>(p0, p1, p2, sh);
   if (threadIdx.x == 0) {
-    a.part[0 * (size_t)gridDim.x + blockIdx.x] = p0;
-    a.part[1 * (size_t)gridDim.x + blockIdx.x] = p1;
-    a.part[2 * (size_t)gridDim.x + blockIdx.x] = p2;
+    double* slot = a.part + (size_t)blockIdx.x * kPartStride;
+    slot[0] = p0;
+    slot[1] = p1;
+    slot[2] = p2;
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_resid64(Sell A, int nxcd, const double* X, const double* b, double* out,
-                                                    double* part) {
-  __shared__ double sh[3][kWavesPerBlock];
+__global__ void __launch_bounds__(kAux) k_resid64(Sell A, int nxcd, const double* X, const double* b, double* out,
+                                                  double* part) {
+  __shared__ double sh[3][kAux / kWave];
   const int lane = threadIdx.x % kWave;
-  const WaveRange wr = wave_range(A.nslices, nxcd);
+  const WaveRange wr = wave_range<kAux>(A.nslices, nxcd);
   double p0 = 0.0, p1 = 0.0, p2 = 0.0;
   for (int64_t s = wr.first; s < wr.end; s += wr.step) resid_slice(A, s, lane, X, b, out, p0);
-  block_sum3(p0, p1, p2, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = p0;
+  block_sum3<kAux>(p0, p1, p2, sh);
+  if (threadIdx.x == 0) {
+    double* slot = part + (size_t)blockIdx.x * kPartStride;
+    slot[0] = p0;
+    slot[1] = 0.0;
+    slot[2] = 0.0;
+  }
 }
 
-// Fixed-order sums of `parts` rows of G partials into out[0..parts-1].
-__global__ void k_reduce_fixed(const double* part, int G, int parts, double* out) {
-  const int lane = threadIdx.x;
-  for (int k = 0; k < parts; ++k) {
-    double v = 0.0;
-    for (int i = lane; i < G; i += kWave) v = v + part[(size_t)k * G + i];
-    v = wave_sum(v);
-    if (lane == 0) out[k] = v;
+// Fixed-order sums of the G workgroups' three partials into out[0..2].
+__global__ void k_reduce_fixed(const double* part, int G, double* out) {
+  double r0, r1, r2;
+  grid_sum3(part, G, threadIdx.x, r0, r1, r2);
+  if (threadIdx.x == 0) {
+    out[0] = r0;
+    out[1] = r1;
+    out[2] = r2;
   }
 }
 
@@ -190,18 +198,24 @@ struct naj_system {
   double* part = nullptr;          // 3 * max_grid
   Ctrl* ctrl = nullptr;
   Barrier* bar = nullptr;
+  unsigned int* counters = nullptr;
   double* hist = nullptr;
   int hist_cap_dev = 0;
   double* trace = nullptr;
   int trace_cap_dev = 0;
   double* scal = nullptr;          // small device scratch for reductions
-  int max_grid = 0;
-  int grid = 0;                    // grid of the persistent kernel
+  int max_grid = 0;                // largest grid of any driver (sizes the partial-sum array)
+  int aux_grid = 0;                // grid of the stand-alone 256-thread one-pass kernels
+  int grid = 0;                    // grid of the solve driver in use
+  int mode = 0;                    // kModePass / kModeSmall / kModePersistent
+  int pass_bs = 256;               // block size of the per-pass kernel
   int nxcd = 1;
   int cus = 0;
   long long spin_ticks = 0;
   int64_t bytes = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t evc[2] = {nullptr, nullptr};
+  int* hflag = nullptr;            // pinned host slots for the phase word
 };
 
 namespace {
@@ -230,11 +244,15 @@ void free_system(naj_system* s) {
   (void)hipFree(s->part);
   (void)hipFree(s->ctrl);
   (void)hipFree(s->bar);
+  (void)hipFree(s->counters);
   (void)hipFree(s->hist);
   (void)hipFree(s->trace);
   (void)hipFree(s->scal);
   if (s->ev0) (void)hipEventDestroy(s->ev0);
   if (s->ev1) (void)hipEventDestroy(s->ev1);
+  for (auto& e : s->evc)
+    if (e) (void)hipEventDestroy(e);
+  if (s->hflag) (void)hipHostFree(s->hflag);
   delete s;
 }
 
@@ -245,30 +263,69 @@ int blocks_for(int64_t work, int per_block) {
   return (int)b;
 }
 
+constexpr int kModePass = 0, kModeSmall = 1, kModePersistent = 2;
+constexpr int kSmallBlock = 1024;
+
+const void* pass_kernel(bool user_d, int bs) {
+  if (bs == 1024) return user_d ? (const void*)k_pass64<true, 1024> : (const void*)k_pass64<false, 1024>;
+  if (bs == 512) return user_d ? (const void*)k_pass64<true, 512> : (const void*)k_pass64<false, 512>;
+  return user_d ? (const void*)k_pass64<true, 256> : (const void*)k_pass64<false, 256>;
+}
+
+const void* solve_kernel(bool user_d) {
+  return user_d ? (const void*)k_solve64<true, kSmallBlock> : (const void*)k_solve64<false, kSmallBlock>;
+}
+
 naj_status choose_grid(naj_system* s) {
   hipDeviceProp_t prop;
   HIP_TRY(hipGetDeviceProperties(&prop, s->device));
   s->cus = prop.multiProcessorCount;
-  int coop = 0;
-  HIP_TRY(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, s->device));
-  if (!coop) return fail(NAJ_EDEVICE, "device %d does not support cooperative launches", s->device);
-  int occ64 = 0, occ64d = 0;
-  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ64, (const void*)k_solve64<false>, kBlock, 0));
-  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ64d, (const void*)k_solve64<true>, kBlock, 0));
-  int occ = std::min(occ64, occ64d);
-  if (occ < 1) return fail(NAJ_EDEVICE, "solve kernel cannot be resident (occupancy 0)");
-  int per_cu = std::min(occ, std::max(1, env_int("NAJ_WG_PER_CU", 4)));
   int nxcd = env_int("NAJ_NXCD", (s->cus % 8 == 0) ? 8 : 1);
   if (nxcd < 1) nxcd = 1;
-  int gmax = per_cu * s->cus;
-  gmax -= gmax % nxcd;
-  if (gmax < nxcd) return fail(NAJ_EDEVICE, "grid too small for %d L2 domains", nxcd);
-  // no more workgroups than give each wave one slice
-  int64_t want = (s->nslices + kWavesPerBlock - 1) / kWavesPerBlock;
-  want = ((want + nxcd - 1) / nxcd) * nxcd;
+  if (nxcd > kMaxDomains) nxcd = kMaxDomains;
   s->nxcd = nxcd;
-  s->max_grid = gmax;
-  s->grid = (int)std::min<int64_t>(gmax, std::max<int64_t>(nxcd, want));
+  int bs = env_int("NAJ_BS", 256);   // 256 x 4 per CU measured best on 128^3 (with 512x2 and 1024x1)
+  if (bs != 256 && bs != 512 && bs != 1024) bs = 256;
+  s->pass_bs = bs;
+  const int per_cu = std::max(1, env_int("NAJ_WG_PER_CU", 4 * 256 / bs));
+  int g = per_cu * s->cus;
+  g -= g % nxcd;
+  if (g < nxcd) g = nxcd;
+  // no more workgroups than give each wave one slice
+  const int wpb = bs / kWave;
+  int64_t want = (s->nslices + wpb - 1) / wpb;
+  want = ((want + nxcd - 1) / nxcd) * nxcd;
+  s->max_grid = (int)std::max<int64_t>(nxcd, std::min<int64_t>(g, want));
+  const int small_slices = env_int("NAJ_SMALL_SLICES", 256);
+  const int force = env_int("NAJ_MODE", -1);
+  s->mode = s->nslices <= small_slices ? kModeSmall : kModePass;
+  if (force >= 0 && force <= 2) s->mode = force;
+  s->grid = s->max_grid;
+  if (s->mode == kModeSmall) s->grid = 1;
+  if (s->mode == kModePersistent) {
+    int coop = 0;
+    HIP_TRY(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, s->device));
+    if (!coop) return fail(NAJ_EDEVICE, "device %d does not support cooperative launches", s->device);
+    int occ1 = 0, occ2 = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ1, solve_kernel(false), kSmallBlock, 0));
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ2, solve_kernel(true), kSmallBlock, 0));
+    int resident = std::min(occ1, occ2) * s->cus;
+    resident -= resident % nxcd;
+    if (resident < nxcd) return fail(NAJ_EDEVICE, "persistent solve kernel cannot be resident");
+    const int wpb1 = kSmallBlock / kWave;
+    int64_t w1 = (s->nslices + wpb1 - 1) / wpb1;
+    w1 = ((w1 + nxcd - 1) / nxcd) * nxcd;
+    s->grid = (int)std::max<int64_t>(nxcd, std::min<int64_t>(resident, w1));
+    s->max_grid = std::max(s->max_grid, s->grid);
+  }
+  {
+    int ga = 8 * s->cus;
+    ga -= ga % nxcd;
+    int64_t wa = (s->nslices + kAux / kWave - 1) / (kAux / kWave);
+    wa = ((wa + nxcd - 1) / nxcd) * nxcd;
+    s->aux_grid = (int)std::max<int64_t>(nxcd, std::min<int64_t>(std::max(ga, nxcd), wa));
+    s->max_grid = std::max(s->max_grid, s->aux_grid);
+  }
   int khz = 0;
   HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, s->device));
   if (khz <= 0) khz = 100000;
@@ -334,6 +391,7 @@ SolveArgs make_args(naj_system* s, const double* b, const naj_opts& o) {
   a.part = s->part;
   a.ctrl = s->ctrl;
   a.bar = s->bar;
+  a.counters = s->counters;
   a.hist = s->hist;
   a.trace = s->trace;
   a.hist_cap = s->hist_cap_dev;
@@ -349,13 +407,62 @@ SolveArgs make_args(naj_system* s, const double* b, const naj_opts& o) {
 
 naj_status residual_norm2(naj_system* s, const double* x, const double* b, double* out, double* rr,
                           hipStream_t st) {
-  const int G = s->max_grid;
-  hipLaunchKernelGGL(k_resid64, dim3(G), dim3(kBlock), 0, st, sell_of(s), s->nxcd, x, b, out, s->part);
+  const int G = s->aux_grid;
+  hipLaunchKernelGGL(k_resid64, dim3(G), dim3(kAux), 0, st, sell_of(s), s->nxcd, x, b, out, s->part);
   HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(k_reduce_fixed, dim3(1), dim3(kWave), 0, st, s->part, G, 1, s->scal);
+  hipLaunchKernelGGL(k_reduce_fixed, dim3(1), dim3(kWave), 0, st, s->part, G, s->scal);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemcpyAsync(rr, s->scal, sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
+  return NAJ_OK;
+}
+
+
+// Runs the solve kernels on `st` for the prepared control block; ev0/ev1 bracket them.
+naj_status run_solve(naj_system* s, SolveArgs& a, const naj_opts& o, hipStream_t st) {
+  const bool ud = s->dinv != nullptr;
+  void* kargs[] = {&a};
+  if (s->mode == kModeSmall) {
+    HIP_TRY(hipEventRecord(s->ev0, st));
+    HIP_TRY(hipLaunchKernel(solve_kernel(ud), dim3(1), dim3(kSmallBlock), kargs, 0, st));
+    HIP_TRY(hipEventRecord(s->ev1, st));
+    return NAJ_OK;
+  }
+  if (s->mode == kModePersistent) {
+    HIP_TRY(hipEventRecord(s->ev0, st));
+    HIP_TRY(hipLaunchCooperativeKernel(solve_kernel(ud), dim3(s->grid), dim3(kSmallBlock), kargs, 0, st));
+    HIP_TRY(hipEventRecord(s->ev1, st));
+    return NAJ_OK;
+  }
+  // one launch per pass, enqueued in chunks; the host checks the phase word of
+  // the previous chunk while the current one runs, so the device never waits
+  const void* fn = pass_kernel(ud, s->pass_bs);
+  const dim3 grid(s->grid), block(s->pass_bs);
+  // passes: norm of b + iterations + confirmations (at most one per confirm_gap iterations, plus one)
+  const int64_t max_pass = 2 + (int64_t)o.max_iter + (int64_t)o.max_iter / std::max(1, o.confirm_gap) + 1;
+  int64_t launched = 0;
+  int chunk = 4, cur = 0, prev = -1;
+  HIP_TRY(hipEventRecord(s->ev0, st));
+  for (;;) {
+    const int64_t n_now = std::min<int64_t>(chunk, max_pass - launched);
+    for (int64_t i = 0; i < n_now; ++i) HIP_TRY(hipLaunchKernel(fn, grid, block, kargs, 0, st));
+    launched += n_now;
+    HIP_TRY(hipMemcpyAsync(&s->hflag[cur], &s->ctrl->phase, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipEventRecord(s->evc[cur], st));
+    if (prev >= 0) {
+      HIP_TRY(hipEventSynchronize(s->evc[prev]));
+      if (s->hflag[prev] == PH_DONE) break;
+    }
+    if (launched >= max_pass) {
+      HIP_TRY(hipEventSynchronize(s->evc[cur]));
+      if (s->hflag[cur] == PH_DONE) break;
+      return fail(NAJ_EDEVICE, "solve did not finish within %lld passes", (long long)launched);
+    }
+    prev = cur;
+    cur ^= 1;
+    chunk = std::min(chunk * 2, 16);
+  }
+  HIP_TRY(hipEventRecord(s->ev1, st));
   return NAJ_OK;
 }
 
@@ -415,7 +522,7 @@ naj_status naj_create_system(int64_t n, int64_t nnz, const int32_t* rowptr, cons
   s->nslices = (n + kWave - 1) / kWave;
   HSTEP(hipMalloc((void**)&flag, sizeof(int)));
   HSTEP(hipMemsetAsync(flag, 0, sizeof(int), st));
-  hipLaunchKernelGGL(k_check_rowptr, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, rowptr, n, nnz, flag);
+  hipLaunchKernelGGL(k_check_rowptr, dim3(blocks_for(n, kAux)), dim3(kAux), 0, st, rowptr, n, nnz, flag);
   HSTEP(hipGetLastError());
   HSTEP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
   HSTEP(hipStreamSynchronize(st));
@@ -424,14 +531,14 @@ naj_status naj_create_system(int64_t n, int64_t nnz, const int32_t* rowptr, cons
     goto bad;
   }
   if (nnz > 0) {
-    hipLaunchKernelGGL(k_check_cols, dim3(blocks_for(nnz, kBlock)), dim3(kBlock), 0, st, colidx, nnz, n, flag);
+    hipLaunchKernelGGL(k_check_cols, dim3(blocks_for(nnz, kAux)), dim3(kAux), 0, st, colidx, nnz, n, flag);
     HSTEP(hipGetLastError());
-    hipLaunchKernelGGL(k_check_vals, dim3(blocks_for(nnz, kBlock)), dim3(kBlock), 0, st, vals, nnz, flag);
+    hipLaunchKernelGGL(k_check_vals, dim3(blocks_for(nnz, kAux)), dim3(kAux), 0, st, vals, nnz, flag);
     HSTEP(hipGetLastError());
   }
   if (D) {
     STEP(dev_alloc(s, &s->dinv, (size_t)n));
-    hipLaunchKernelGGL(k_check_D, dim3(blocks_for(n, kBlock)), dim3(kBlock), 0, st, D, n, s->dinv, flag);
+    hipLaunchKernelGGL(k_check_D, dim3(blocks_for(n, kAux)), dim3(kAux), 0, st, D, n, s->dinv, flag);
     HSTEP(hipGetLastError());
   }
   HSTEP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -443,7 +550,7 @@ naj_status naj_create_system(int64_t n, int64_t nnz, const int32_t* rowptr, cons
   }
   // sliced-row layout
   HSTEP(hipMalloc((void**)&width, sizeof(int32_t) * s->nslices));
-  hipLaunchKernelGGL(k_slice_width, dim3(blocks_for(s->nslices * kWave, kBlock)), dim3(kBlock), 0, st, rowptr, n,
+  hipLaunchKernelGGL(k_slice_width, dim3(blocks_for(s->nslices * kWave, kAux)), dim3(kAux), 0, st, rowptr, n,
                      s->nslices, width);
   HSTEP(hipGetLastError());
   hw.resize(s->nslices);
@@ -458,17 +565,22 @@ naj_status naj_create_system(int64_t n, int64_t nnz, const int32_t* rowptr, cons
   STEP(dev_alloc(s, &s->val, (size_t)s->stored));
   STEP(dev_alloc(s, &s->val32, (size_t)s->stored));
   HSTEP(hipMemcpyAsync(s->slice_ptr, hp.data(), sizeof(int64_t) * (s->nslices + 1), hipMemcpyHostToDevice, st));
-  hipLaunchKernelGGL(k_sell_fill, dim3(blocks_for(s->nslices * kWave, kBlock)), dim3(kBlock), 0, st, rowptr, colidx,
+  hipLaunchKernelGGL(k_sell_fill, dim3(blocks_for(s->nslices * kWave, kAux)), dim3(kAux), 0, st, rowptr, colidx,
                      vals, n, s->nslices, s->slice_ptr, s->col, s->val, s->val32);
   HSTEP(hipGetLastError());
   STEP(choose_grid(s));
   for (auto& v : s->vec) STEP(dev_alloc(s, &v, (size_t)n));
-  STEP(dev_alloc(s, &s->part, (size_t)3 * s->max_grid));
+  STEP(dev_alloc(s, &s->part, (size_t)kPartStride * s->max_grid));
   STEP(dev_alloc(s, &s->ctrl, 1));
   STEP(dev_alloc(s, &s->bar, 1));
+  STEP(dev_alloc(s, &s->counters, (size_t)kCounterWords));
+  HSTEP(hipMemsetAsync(s->counters, 0, sizeof(unsigned int) * kCounterWords, st));
   STEP(dev_alloc(s, &s->scal, 8));
   HSTEP(hipEventCreate(&s->ev0));
   HSTEP(hipEventCreate(&s->ev1));
+  HSTEP(hipEventCreateWithFlags(&s->evc[0], hipEventDisableTiming));
+  HSTEP(hipEventCreateWithFlags(&s->evc[1], hipEventDisableTiming));
+  HSTEP(hipHostMalloc((void**)&s->hflag, 2 * sizeof(int), hipHostMallocDefault));
   HSTEP(hipStreamSynchronize(st));
   (void)hipFree(flag);
   (void)hipFree(width);
@@ -520,19 +632,16 @@ naj_status naj_solve(naj_system* s, const double* b, const double* x0, const naj
   if (rc != NAJ_OK) return rc;
   if (x0) HIP_TRY(hipMemcpyAsync(s->vec[0], x0, sizeof(double) * s->n, hipMemcpyDeviceToDevice, st));
   else HIP_TRY(hipMemsetAsync(s->vec[0], 0, sizeof(double) * s->n, st));
-  hipLaunchKernelGGL(k_solve_init, dim3(1), dim3(64), 0, st, s->ctrl, s->bar, o.k0);
+  hipLaunchKernelGGL(k_solve_init, dim3(1), dim3(64), 0, st, s->ctrl, s->bar, s->counters, o.k0);
   HIP_TRY(hipGetLastError());
   SolveArgs a = make_args(s, b, o);
   if (!hist) a.hist = nullptr, a.hist_cap = 0;
   else a.hist_cap = std::min(hist_cap, s->hist_cap_dev);
   if (!trace) a.trace = nullptr, a.trace_cap = 0;
   else a.trace_cap = std::min(trace_cap, s->trace_cap_dev);
-  void* kargs[] = {&a};
-  const void* fn = s->dinv ? (const void*)k_solve64<true> : (const void*)k_solve64<false>;
-  HIP_TRY(hipEventRecord(s->ev0, st));
-  HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(s->grid), dim3(kBlock), kargs, 0, st));
-  HIP_TRY(hipEventRecord(s->ev1, st));
-  hipLaunchKernelGGL(k_copy_result, dim3(blocks_for(s->n, kBlock * 4)), dim3(kBlock), 0, st, s->ctrl, s->vec[0],
+  rc = run_solve(s, a, o, st);
+  if (rc != NAJ_OK) return rc;
+  hipLaunchKernelGGL(k_copy_result, dim3(blocks_for(s->n, kAux * 4)), dim3(kAux), 0, st, s->ctrl, s->vec[0],
                      s->vec[1], s->vec[2], x, s->n);
   HIP_TRY(hipGetLastError());
   Ctrl hc;
@@ -583,14 +692,14 @@ naj_status naj_step(naj_system* s, const double* p, const double* r, double beta
   naj_opts o;
   naj_opts_default(&o);
   SolveArgs a = make_args(s, b, o);
-  const int G = s->max_grid;
+  const int G = s->aux_grid;
   const int bz = beta == 0.0 ? 1 : 0;
   if (s->dinv)
-    hipLaunchKernelGGL(k_step64<true>, dim3(G), dim3(kBlock), 0, st, a, p, bz ? p : r, beta, bz, x);
+    hipLaunchKernelGGL(k_step64<true>, dim3(G), dim3(kAux), 0, st, a, p, bz ? p : r, beta, bz, x);
   else
-    hipLaunchKernelGGL(k_step64<false>, dim3(G), dim3(kBlock), 0, st, a, p, bz ? p : r, beta, bz, x);
+    hipLaunchKernelGGL(k_step64<false>, dim3(G), dim3(kAux), 0, st, a, p, bz ? p : r, beta, bz, x);
   HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(k_reduce_fixed, dim3(1), dim3(kWave), 0, st, s->part, G, 3, s->scal);
+  hipLaunchKernelGGL(k_reduce_fixed, dim3(1), dim3(kWave), 0, st, s->part, G, s->scal);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemcpyAsync(red, s->scal, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
@@ -607,7 +716,7 @@ naj_status naj_diagonal(naj_system* s, double* out, void* stream) {
   g_err.clear();
   if (!s || !out) return fail(NAJ_EINVAL, "null argument");
   hipStream_t st = (hipStream_t)stream;
-  hipLaunchKernelGGL(k_row_abs_sum, dim3(blocks_for(s->nslices * kWave, kBlock)), dim3(kBlock), 0, st, sell_of(s),
+  hipLaunchKernelGGL(k_row_abs_sum, dim3(blocks_for(s->nslices * kWave, kAux)), dim3(kAux), 0, st, sell_of(s),
                      s->dinv, out);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(st));

@@ -16,11 +16,26 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "naj_partition.h"
+
 namespace naj {
 
 constexpr int kWave = 64;
-constexpr int kBlock = 256;
-constexpr int kWavesPerBlock = kBlock / kWave;
+#ifndef NAJ_UNROLL
+#define NAJ_UNROLL 8
+#endif
+constexpr int kUnroll = NAJ_UNROLL;   // column steps whose loads are issued together
+
+// Matrix entries are read once per pass: load them non-temporally so they do
+// not displace the vector data the gathers reuse.
+template <typename T>
+__device__ __forceinline__ T stream_load(const T* p) {
+#if defined(NAJ_PLAIN_LOADS)
+  return *p;
+#else
+  return __builtin_nontemporal_load(p);
+#endif
+}
 
 enum Phase : int { PH_NORMB = 0, PH_ITER = 1, PH_CONFIRM = 2, PH_DONE = 3 };
 
@@ -28,8 +43,9 @@ enum : int { ST_OK = 0, ST_NOT_CONVERGED = 1, ST_EDEVICE = -3, ST_BREAKDOWN = -4
 
 constexpr int kRestartLogCap = 64;
 
-// Control block of one solve: written only by the workgroup that arrives
-// last at a grid barrier, read by every workgroup after it.
+// Control block of one solve: written only by the workgroup that finishes a
+// pass last (or by the single workgroup of the small-system kernel), read by
+// every workgroup before the next pass.
 struct Ctrl {
   double alpha;          // alpha_t of the pass about to run
   double beta;           // y = P + beta (P - R) for the pass about to run
@@ -49,14 +65,21 @@ struct Ctrl {
   int pending_restart;   // restart decision held while a confirmation pass runs
   int hist_len;
   int timeout;           // set by a workgroup whose barrier wait timed out
+  int passes;            // matrix passes run so far (including the norm of b)
   int restart_log[kRestartLogCap];
 };
 
 struct Barrier {
-  unsigned long long count;   // arrivals, monotone over the solve
+  unsigned long long count;   // arrivals of the persistent kernel's grid barrier (monotone over a solve)
   unsigned int epoch_done;    // last released barrier epoch
   unsigned int pad;
 };
+
+// Arrival counters of the per-pass kernel: one per L2 domain plus one on top,
+// each on its own 4 KB page so the domains' atomics go to different channels.
+constexpr int kMaxDomains = 8;
+constexpr int kCounterStride = 1024;   // unsigned ints (4 KB)
+constexpr int kCounterWords = (kMaxDomains + 1) * kCounterStride;
 
 struct Sell {
   const int64_t* slice_ptr;   // [nslices+1]
@@ -77,6 +100,7 @@ struct SolveArgs {
   double* part;               // [3 * G]
   Ctrl* ctrl;
   Barrier* bar;
+  unsigned int* counters;     // [kCounterWords], zero between passes
   double* hist;
   double* trace;
   int hist_cap;
@@ -100,103 +124,71 @@ __device__ __forceinline__ double* pick(const SolveArgs& a, int i) {
   return i == 0 ? a.buf0 : (i == 1 ? a.buf1 : a.buf2);
 }
 
-// Slice range owned by one wave: the slices of an L2 domain are contiguous,
-// and the domain's waves sweep them together so neighbouring rows are read
-// close in time on the same L2.
-struct WaveRange {
-  int64_t first, end, step;
-};
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x / kWave); }
 
+using WaveRange = SliceRange;
+
+template <int BS>
 __device__ __forceinline__ WaveRange wave_range(int64_t nslices, int nxcd) {
-  const int G = gridDim.x;
-  const int w = blockIdx.x;
-  const int dom = w % nxcd;
-  const int j = w / nxcd;
-  const int per_dom = G / nxcd;
-  const int64_t lo = nslices * dom / nxcd;
-  const int64_t hi = nslices * (dom + 1) / nxcd;
-  const int wave = threadIdx.x / kWave;
-  WaveRange r;
-  r.first = lo + (int64_t)j * kWavesPerBlock + wave;
-  r.end = hi;
-  r.step = (int64_t)per_dom * kWavesPerBlock;
-  return r;
+  return slice_range(nslices, nxcd, (int)gridDim.x, (int)blockIdx.x, wave_id(), BS / kWave);
 }
 
-// One slice of the fused pass: u = Q y, g = u - b, x = y - J^{-1} g, d = x - P.
+// One slice of the fused pass: u = Q y, g = u - b, x = y - J^{-1} g, d = x - P,
+// with y = P + beta (P - R) formed at every gathered column (y = P when bz).
 template <bool USER_D>
 __device__ __forceinline__ void iter_slice(const SolveArgs& a, int64_t s, int lane, const double* __restrict__ P,
                                            const double* __restrict__ R, double* __restrict__ W, double beta,
                                            bool bz, double& ps, double& pgg, double& psabs) {
   const int64_t base = a.A.slice_ptr[s];
   const int width = (int)((a.A.slice_ptr[s + 1] - base) >> 6);
+  const int64_t row = s * kWave + lane;
+  const bool live = row < a.A.n;
+  const int64_t rr = live ? row : 0;
+  // own-row operands do not depend on the column loop: issue them first
+  const double Pi = P[rr];
+  const double Ri = bz ? 0.0 : R[rr];
+  const double bi = a.b[rr];
+  const double di = USER_D ? a.dinv[rr] : 0.0;
   const int32_t* __restrict__ cp = a.A.col + base + lane;
   const double* __restrict__ vp = a.A.val + base + lane;
   double acc = 0.0, asum = 0.0;
-  int k = 0;
-  if (bz) {
-    for (; k + 4 <= width; k += 4) {
-      const int c0 = __builtin_nontemporal_load(cp + (k + 0) * kWave);
-      const int c1 = __builtin_nontemporal_load(cp + (k + 1) * kWave);
-      const int c2 = __builtin_nontemporal_load(cp + (k + 2) * kWave);
-      const int c3 = __builtin_nontemporal_load(cp + (k + 3) * kWave);
-      const double v0 = __builtin_nontemporal_load(vp + (k + 0) * kWave);
-      const double v1 = __builtin_nontemporal_load(vp + (k + 1) * kWave);
-      const double v2 = __builtin_nontemporal_load(vp + (k + 2) * kWave);
-      const double v3 = __builtin_nontemporal_load(vp + (k + 3) * kWave);
-      const double y0 = P[c0], y1 = P[c1], y2 = P[c2], y3 = P[c3];
-      acc = acc + v0 * y0; asum = asum + fabs(v0);
-      acc = acc + v1 * y1; asum = asum + fabs(v1);
-      acc = acc + v2 * y2; asum = asum + fabs(v2);
-      acc = acc + v3 * y3; asum = asum + fabs(v3);
+  for (int k0 = 0; k0 < width; k0 += kUnroll) {
+    int c[kUnroll];
+    double v[kUnroll], y[kUnroll];
+#pragma unroll
+    for (int j = 0; j < kUnroll; ++j) {
+      if (k0 + j < width) {
+        c[j] = stream_load(cp + (k0 + j) * kWave);
+        v[j] = stream_load(vp + (k0 + j) * kWave);
+      }
     }
-    for (; k < width; ++k) {
-      const int c = __builtin_nontemporal_load(cp + k * kWave);
-      const double v = __builtin_nontemporal_load(vp + k * kWave);
-      acc = acc + v * P[c];
-      asum = asum + fabs(v);
-    }
-  } else {
-    for (; k + 4 <= width; k += 4) {
-      const int c0 = __builtin_nontemporal_load(cp + (k + 0) * kWave);
-      const int c1 = __builtin_nontemporal_load(cp + (k + 1) * kWave);
-      const int c2 = __builtin_nontemporal_load(cp + (k + 2) * kWave);
-      const int c3 = __builtin_nontemporal_load(cp + (k + 3) * kWave);
-      const double v0 = __builtin_nontemporal_load(vp + (k + 0) * kWave);
-      const double v1 = __builtin_nontemporal_load(vp + (k + 1) * kWave);
-      const double v2 = __builtin_nontemporal_load(vp + (k + 2) * kWave);
-      const double v3 = __builtin_nontemporal_load(vp + (k + 3) * kWave);
-      const double p0 = P[c0], p1 = P[c1], p2 = P[c2], p3 = P[c3];
-      const double r0 = R[c0], r1 = R[c1], r2 = R[c2], r3 = R[c3];
-      const double y0 = p0 + beta * (p0 - r0);
-      const double y1 = p1 + beta * (p1 - r1);
-      const double y2 = p2 + beta * (p2 - r2);
-      const double y3 = p3 + beta * (p3 - r3);
-      acc = acc + v0 * y0; asum = asum + fabs(v0);
-      acc = acc + v1 * y1; asum = asum + fabs(v1);
-      acc = acc + v2 * y2; asum = asum + fabs(v2);
-      acc = acc + v3 * y3; asum = asum + fabs(v3);
-    }
-    for (; k < width; ++k) {
-      const int c = __builtin_nontemporal_load(cp + k * kWave);
-      const double v = __builtin_nontemporal_load(vp + k * kWave);
-      const double p = P[c];
-      const double y = p + beta * (p - R[c]);
-      acc = acc + v * y;
-      asum = asum + fabs(v);
-    }
-  }
-  const int64_t row = s * kWave + lane;
-  if (row < a.A.n) {
-    const double Pi = P[row];
-    const double yi = bz ? Pi : Pi + beta * (Pi - R[row]);
-    const double g = acc - a.b[row];
-    double dv;
-    if (USER_D) {
-      dv = a.dinv[row];
+    if (bz) {
+#pragma unroll
+      for (int j = 0; j < kUnroll; ++j)
+        if (k0 + j < width) y[j] = P[c[j]];
     } else {
-      dv = 1.0 / (asum == 0.0 ? 1.0 : asum);
+      double pj[kUnroll], rj[kUnroll];
+#pragma unroll
+      for (int j = 0; j < kUnroll; ++j)
+        if (k0 + j < width) {
+          pj[j] = P[c[j]];
+          rj[j] = R[c[j]];
+        }
+#pragma unroll
+      for (int j = 0; j < kUnroll; ++j)
+        if (k0 + j < width) y[j] = pj[j] + beta * (pj[j] - rj[j]);
     }
+#pragma unroll
+    for (int j = 0; j < kUnroll; ++j)
+      if (k0 + j < width) {
+        acc = acc + v[j] * y[j];
+        asum = asum + fabs(v[j]);
+      }
+  }
+  if (live) {
+    const double yi = bz ? Pi : Pi + beta * (Pi - Ri);
+    const double g = acc - bi;
+    const double dv = USER_D ? di : 1.0 / (asum == 0.0 ? 1.0 : asum);
     const double xi = yi - dv * g;
     W[row] = xi;
     const double d = xi - Pi;
@@ -212,30 +204,39 @@ __device__ __forceinline__ void resid_slice(const Sell& A, int64_t s, int lane, 
                                             const double* __restrict__ b, double* __restrict__ out, double& prr) {
   const int64_t base = A.slice_ptr[s];
   const int width = (int)((A.slice_ptr[s + 1] - base) >> 6);
+  const int64_t row = s * kWave + lane;
+  const bool live = row < A.n;
+  const double bi = b[live ? row : 0];
   const int32_t* __restrict__ cp = A.col + base + lane;
   const double* __restrict__ vp = A.val + base + lane;
   double acc = 0.0;
-  int k = 0;
-  for (; k + 4 <= width; k += 4) {
-    const int c0 = cp[(k + 0) * kWave], c1 = cp[(k + 1) * kWave], c2 = cp[(k + 2) * kWave], c3 = cp[(k + 3) * kWave];
-    const double v0 = vp[(k + 0) * kWave], v1 = vp[(k + 1) * kWave], v2 = vp[(k + 2) * kWave], v3 = vp[(k + 3) * kWave];
-    const double x0 = X[c0], x1 = X[c1], x2 = X[c2], x3 = X[c3];
-    acc = acc + v0 * x0;
-    acc = acc + v1 * x1;
-    acc = acc + v2 * x2;
-    acc = acc + v3 * x3;
+  for (int k0 = 0; k0 < width; k0 += kUnroll) {
+    int c[kUnroll];
+    double v[kUnroll], xj[kUnroll];
+#pragma unroll
+    for (int j = 0; j < kUnroll; ++j)
+      if (k0 + j < width) {
+        c[j] = stream_load(cp + (k0 + j) * kWave);
+        v[j] = stream_load(vp + (k0 + j) * kWave);
+      }
+#pragma unroll
+    for (int j = 0; j < kUnroll; ++j)
+      if (k0 + j < width) xj[j] = X[c[j]];
+#pragma unroll
+    for (int j = 0; j < kUnroll; ++j)
+      if (k0 + j < width) acc = acc + v[j] * xj[j];
   }
-  for (; k < width; ++k) acc = acc + vp[k * kWave] * X[cp[k * kWave]];
-  const int64_t row = s * kWave + lane;
-  if (row < A.n) {
-    const double r = b[row] - acc;
+  if (live) {
+    const double r = bi - acc;
     if (out) out[row] = r;
     prr = prr + r * r;
   }
 }
 
 // Sum three per-thread values over the workgroup in a fixed order; result valid in thread 0.
-__device__ __forceinline__ void block_sum3(double& a, double& b, double& c, double (*sh)[kWavesPerBlock]) {
+template <int BS>
+__device__ __forceinline__ void block_sum3(double& a, double& b, double& c, double (*sh)[BS / kWave]) {
+  constexpr int WPB = BS / kWave;
   a = wave_sum(a);
   b = wave_sum(b);
   c = wave_sum(c);
@@ -250,7 +251,7 @@ __device__ __forceinline__ void block_sum3(double& a, double& b, double& c, doub
     a = sh[0][0];
     b = sh[1][0];
     c = sh[2][0];
-    for (int i = 1; i < kWavesPerBlock; ++i) {
+    for (int i = 1; i < WPB; ++i) {
       a = a + sh[0][i];
       b = b + sh[1][i];
       c = c + sh[2][i];
@@ -258,12 +259,43 @@ __device__ __forceinline__ void block_sum3(double& a, double& b, double& c, doub
   }
 }
 
-// Sum part[k*G + 0 .. k*G + G-1] in a fixed order with one wavefront.
-__device__ __forceinline__ double grid_sum_fixed(const double* part, int k, int G, int lane) {
-  double v = 0.0;
-  for (int i = lane; i < G; i += kWave) v = v + __hip_atomic_load(part + (size_t)k * G + i, __ATOMIC_RELAXED,
-                                                                     __HIP_MEMORY_SCOPE_AGENT);
-  return wave_sum(v);
+// s_waitcnt vmcnt(0): every vector memory operation this wave issued, stores
+// included, has completed (gfx9-family encoding: expcnt and lgkmcnt left at max).
+__device__ __forceinline__ void wait_stores_complete() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// Per-workgroup partial sums live at part[4*w + k], k = 0, 1, 2 (32 B per workgroup).
+constexpr int kPartStride = 4;
+
+// Sums of the G workgroups' partials in a fixed order (lane l adds slots l, l+64, ...
+// in turn, then the lanes are combined by the xor butterfly); every lane gets
+// the result.  Loads are issued four slots at a time before any is used.
+__device__ __forceinline__ void grid_sum3(const double* __restrict__ part, int G, int lane, double& r0, double& r1,
+                                          double& r2) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  int i = lane;
+  for (; i + 3 * kWave < G; i += 4 * kWave) {
+    double v[4][3];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) v[q][k] = part[(size_t)(i + q * kWave) * kPartStride + k];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      s0 = s0 + v[q][0];
+      s1 = s1 + v[q][1];
+      s2 = s2 + v[q][2];
+    }
+  }
+  for (; i < G; i += kWave) {
+    const double* p = part + (size_t)i * kPartStride;
+    const double a0 = p[0], a1 = p[1], a2 = p[2];
+    s0 = s0 + a0;
+    s1 = s1 + a1;
+    s2 = s2 + a2;
+  }
+  r0 = wave_sum(s0);
+  r1 = wave_sum(s1);
+  r2 = wave_sum(s2);
 }
 
 }  // namespace naj

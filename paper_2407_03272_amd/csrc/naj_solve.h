@@ -1,25 +1,28 @@
-// Persistent single-system solve kernel: every iteration of Algorithm 3 is
-// one fused pass over the matrix followed by one grid barrier.  The
-// workgroup that arrives last at the barrier reduces the per-workgroup
-// partial sums in a fixed order and takes the scalar decisions of
-// Algorithm 2 (restart test, alpha/beta, prohibition period, stopping), then
-// releases the others.  Restarts never move data: they only change which of
-// the three vector buffers plays x^{t-1}, x^{t-2} and x^t in the next pass.
+// Solve kernels.  Every iteration of Algorithm 3 is one fused pass over the
+// matrix (product, Jacobi-type step and the partial sums of the restart
+// inner product and the residual monitor) followed by one scalar decision:
+// the restart test and the restart/momentum branches of Algorithm 2, or the
+// stopping test.  The decision is taken by the workgroup that finishes the
+// pass last, from the per-workgroup partial sums added in a fixed order, so
+// every run of the same system takes the same decisions.  Restarts never
+// move data: they only change which of three vector buffers plays x^{t-1},
+// x^{t-2} and x^t in the next pass.
+//
+// Two drivers share the pass:
+//  * k_pass64: one launch per pass.  Kernel boundaries order the passes
+//    (the next launch sees the previous one's vector writes and control
+//    block); large systems use it.
+//  * k_solve64: one persistent launch per solve.  With a single workgroup
+//    the passes are separated by workgroup barriers only (small systems);
+//    with several co-resident workgroups by a counting grid barrier.
 #pragma once
 
 #include "naj_device.h"
 
 namespace naj {
 
-__device__ __forceinline__ int ld_i(const int* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ double ld_d(const double* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Scalar control after an iteration pass that did not stop: the restart test and the
-// restart/momentum branches of Algorithm 2.
+// Scalar control after an iteration pass that did not stop: the restart and
+// momentum branches of Algorithm 2, then the iteration cap.
 __device__ inline void apply_step(const SolveArgs& a, Ctrl* c, bool restart) {
   const int t = c->t;
   if (restart) {
@@ -56,9 +59,10 @@ __device__ inline void apply_step(const SolveArgs& a, Ctrl* c, bool restart) {
   }
 }
 
-// Runs on one thread of the last-arriving workgroup.
+// The decision after a pass, from its three reduced sums.  One thread runs it.
 __device__ inline void control_update(const SolveArgs& a, Ctrl* c, double r0, double r1, double r2) {
   const int phase = c->phase;
+  c->passes += 1;
   if (phase == PH_NORMB) {
     const double nb = sqrt(r0);
     c->nb = nb;
@@ -128,70 +132,153 @@ __device__ inline void control_update(const SolveArgs& a, Ctrl* c, double r0, do
   }
 }
 
-template <bool USER_D>
-__global__ void __launch_bounds__(kBlock) k_solve64(SolveArgs a) {
-  __shared__ double sh[3][kWavesPerBlock];
-  __shared__ int s_phase, s_iP, s_iR, s_iW, s_bz, s_last, s_stop;
-  __shared__ double s_beta;
-  const int G = gridDim.x;
-  const int lane = threadIdx.x % kWave;
-  const WaveRange wr = wave_range(a.A.nslices, a.nxcd);
-  unsigned int epoch = 0;
+// Control fields a pass needs, staged in LDS by thread 0.
+struct PassView {
+  int phase, iP, iR, iW, bz;
+  double beta;
+};
 
-  for (;;) {
-    if (threadIdx.x == 0) {
-      s_phase = ld_i(&a.ctrl->phase);
-      s_iP = ld_i(&a.ctrl->iP);
-      s_iR = ld_i(&a.ctrl->iR);
-      s_iW = ld_i(&a.ctrl->iW);
-      s_bz = ld_i(&a.ctrl->beta_zero);
-      s_beta = ld_d(&a.ctrl->beta);
-    }
-    __syncthreads();
-    const int phase = s_phase;
-    if (phase == PH_DONE) break;
-    double p0 = 0.0, p1 = 0.0, p2 = 0.0;
-    if (phase == PH_ITER) {
-      const double* P = pick(a, s_iP);
-      const double* R = pick(a, s_iR);
-      double* W = pick(a, s_iW);
-      const double beta = s_beta;
-      const bool bz = s_bz != 0;
-      for (int64_t s = wr.first; s < wr.end; s += wr.step) iter_slice<USER_D>(a, s, lane, P, R, W, beta, bz, p0, p1, p2);
-    } else if (phase == PH_CONFIRM) {
-      const double* X = pick(a, s_iW);
-      for (int64_t s = wr.first; s < wr.end; s += wr.step) resid_slice(a.A, s, lane, X, a.b, nullptr, p0);
-    } else {  // PH_NORMB
-      for (int64_t s = wr.first; s < wr.end; s += wr.step) {
-        const int64_t row = s * kWave + lane;
-        if (row < a.A.n) {
-          const double v = a.b[row];
-          p0 = p0 + v * v;
-        }
+__device__ __forceinline__ void load_view(const Ctrl* c, PassView* v) {
+  v->phase = c->phase;
+  v->iP = c->iP;
+  v->iR = c->iR;
+  v->iW = c->iW;
+  v->bz = c->beta_zero;
+  v->beta = c->beta;
+}
+
+// The workgroup's share of one pass; partial sums in p0..p2 (per thread).
+template <bool USER_D, int BS>
+__device__ __forceinline__ void run_pass(const SolveArgs& a, const PassView& v, double& p0, double& p1,
+                                         double& p2) {
+  const int lane = threadIdx.x % kWave;
+  const WaveRange wr = wave_range<BS>(a.A.nslices, a.nxcd);
+  if (v.phase == PH_ITER) {
+    const double* P = pick(a, v.iP);
+    const double* R = pick(a, v.iR);
+    double* W = pick(a, v.iW);
+    const bool bz = v.bz != 0;
+    for (int64_t s = wr.first; s < wr.end; s += wr.step) iter_slice<USER_D>(a, s, lane, P, R, W, v.beta, bz, p0, p1, p2);
+  } else if (v.phase == PH_CONFIRM) {
+    const double* X = pick(a, v.iW);
+    for (int64_t s = wr.first; s < wr.end; s += wr.step) resid_slice(a.A, s, lane, X, a.b, nullptr, p0);
+  } else {  // PH_NORMB
+    for (int64_t s = wr.first; s < wr.end; s += wr.step) {
+      const int64_t row = s * kWave + lane;
+      if (row < a.A.n) {
+        const double x = a.b[row];
+        p0 = p0 + x * x;
       }
     }
-    block_sum3(p0, p1, p2, sh);
+  }
+}
+
+// One pass per launch.  The last workgroup to finish reduces the partials and
+// updates the control block for the next launch; launches after the solve has
+// finished return at once.
+template <bool USER_D, int BS>
+__global__ void __launch_bounds__(BS) k_pass64(SolveArgs a) {
+  __shared__ double sh[3][BS / kWave];
+  __shared__ PassView v;
+  __shared__ int s_last;
+  if (threadIdx.x == 0) load_view(a.ctrl, &v);
+  __syncthreads();
+  if (v.phase == PH_DONE) return;
+  double p0 = 0.0, p1 = 0.0, p2 = 0.0;
+  run_pass<USER_D, BS>(a, v, p0, p1, p2);
+  block_sum3<BS>(p0, p1, p2, sh);
+  const int G = gridDim.x;
+  if (threadIdx.x == 0) {
+    // Partials are written through to the agent coherence point (agent-scope
+    // atomic stores) and must have completed before the arrival is counted;
+    // the last arriver reads them back with agent-scope atomic loads.  No L2
+    // writeback/invalidate is needed for them; the vector writes reach the
+    // next pass through the kernel boundary.
+    double* slot = a.part + (size_t)blockIdx.x * kPartStride;
+    __hip_atomic_store(slot + 0, p0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(slot + 1, p1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(slot + 2, p2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    wait_stores_complete();
+    // two-level arrival count: workgroups of one L2 domain count on their own
+    // counter; the domain's last arriver counts on the top counter
+    const int nd = effective_domains(G, a.nxcd);
+    const int dom = blockIdx.x % nd;
+    unsigned int* dc = a.counters + (size_t)dom * kCounterStride;
+    unsigned int* tc = a.counters + (size_t)kMaxDomains * kCounterStride;
+    int last = 0;
+    const unsigned int o1 = __hip_atomic_fetch_add(dc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (o1 == (unsigned int)(G / nd - 1)) {
+      __hip_atomic_store(dc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned int o2 = __hip_atomic_fetch_add(tc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (o2 == (unsigned int)(nd - 1)) {
+        __hip_atomic_store(tc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        last = 1;
+      }
+    }
+    s_last = last;
+  }
+  __syncthreads();
+  if (s_last && threadIdx.x < kWave) {
+    const int lane = threadIdx.x;
+    // drop stale L2 copies of the partials (written through by other domains), then read them in bulk
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    double r0, r1, r2;
+    grid_sum3(a.part, G, lane, r0, r1, r2);
+    if (lane == 0) control_update(a, a.ctrl, r0, r1, r2);
+  }
+}
+
+// One persistent launch per solve (see the file comment).
+template <bool USER_D, int BS>
+__global__ void __launch_bounds__(BS) k_solve64(SolveArgs a) {
+  __shared__ double sh[3][BS / kWave];
+  __shared__ PassView v;
+  __shared__ int s_last, s_stop;
+  const int G = gridDim.x;
+  const int lane = threadIdx.x % kWave;
+  unsigned int epoch = 0;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      if (G == 1) {
+        load_view(a.ctrl, &v);
+      } else {
+        v.phase = __hip_atomic_load(&a.ctrl->phase, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        v.iP = __hip_atomic_load(&a.ctrl->iP, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        v.iR = __hip_atomic_load(&a.ctrl->iR, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        v.iW = __hip_atomic_load(&a.ctrl->iW, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        v.bz = __hip_atomic_load(&a.ctrl->beta_zero, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        v.beta = __hip_atomic_load(&a.ctrl->beta, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    __syncthreads();
+    if (v.phase == PH_DONE) break;
+    double p0 = 0.0, p1 = 0.0, p2 = 0.0;
+    run_pass<USER_D, BS>(a, v, p0, p1, p2);
+    block_sum3<BS>(p0, p1, p2, sh);
+    if (G == 1) {
+      // single workgroup: every wave runs on this CU, a workgroup barrier orders the passes
+      if (threadIdx.x == 0) control_update(a, a.ctrl, p0, p1, p2);
+      __syncthreads();
+      continue;
+    }
     ++epoch;
     if (threadIdx.x == 0) {
-      a.part[0 * (size_t)G + blockIdx.x] = p0;
-      a.part[1 * (size_t)G + blockIdx.x] = p1;
-      a.part[2 * (size_t)G + blockIdx.x] = p2;
-      __threadfence();
-      const unsigned long long old = __hip_atomic_fetch_add(&a.bar->count, 1ULL, __ATOMIC_ACQ_REL,
-                                                            __HIP_MEMORY_SCOPE_AGENT);
+      double* slot = a.part + (size_t)blockIdx.x * kPartStride;
+      slot[0] = p0;
+      slot[1] = p1;
+      slot[2] = p2;
+      const unsigned long long old =
+          __hip_atomic_fetch_add(&a.bar->count, 1ULL, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
       s_last = (old == (unsigned long long)epoch * (unsigned long long)G - 1ULL) ? 1 : 0;
       s_stop = 0;
     }
     __syncthreads();
     if (s_last) {
       if (threadIdx.x < kWave) {
-        __threadfence();
-        const double r0 = grid_sum_fixed(a.part, 0, G, lane);
-        const double r1 = grid_sum_fixed(a.part, 1, G, lane);
-        const double r2 = grid_sum_fixed(a.part, 2, G, lane);
+        double r0, r1, r2;
+        grid_sum3(a.part, G, lane, r0, r1, r2);
         if (lane == 0) {
           control_update(a, a.ctrl, r0, r1, r2);
-          __threadfence();
           __hip_atomic_store(&a.bar->epoch_done, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
       }
@@ -200,23 +287,25 @@ __global__ void __launch_bounds__(kBlock) k_solve64(SolveArgs a) {
       unsigned int spins = 0;
       while (__hip_atomic_load(&a.bar->epoch_done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
         __builtin_amdgcn_s_sleep(1);
-        if ((++spins & 255u) == 0u) {
-          if (ld_i(&a.ctrl->timeout) != 0 || wall_clock64() - t0 > a.spin_ticks) {
+        if (a.spin_ticks == 0 || (++spins & 255u) == 0u) {
+          if (a.spin_ticks == 0 ||
+              __hip_atomic_load(&a.ctrl->timeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+              wall_clock64() - t0 > a.spin_ticks) {
             __hip_atomic_store(&a.ctrl->timeout, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             s_stop = 1;
             break;
           }
         }
       }
-      __threadfence();
     }
     __syncthreads();
     if (s_stop) break;
   }
 }
 
-// Clears the control block and the barrier before a solve.
-__global__ void k_solve_init(Ctrl* c, Barrier* bar, int k0) {
+// Clears the control block, the barrier and the arrival counters before a solve.
+__global__ void k_solve_init(Ctrl* c, Barrier* bar, unsigned int* counters, int k0) {
+  for (int i = threadIdx.x; i <= kMaxDomains; i += blockDim.x) counters[(size_t)i * kCounterStride] = 0u;
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     c->alpha = 1.0;
     c->beta = 0.0;
@@ -240,6 +329,7 @@ __global__ void k_solve_init(Ctrl* c, Barrier* bar, int k0) {
     c->pending_restart = 0;
     c->hist_len = 0;
     c->timeout = 0;
+    c->passes = 0;
     for (int i = 0; i < kRestartLogCap; ++i) c->restart_log[i] = 0;
     bar->count = 0ULL;
     bar->epoch_done = 0u;
@@ -254,6 +344,11 @@ __global__ void k_copy_result(const Ctrl* c, const double* b0, const double* b1,
   const double* src = r == 0 ? b0 : (r == 1 ? b1 : b2);
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     x[i] = r < 0 ? 0.0 : src[i];
+}
+
+// Copies the phase word (for the host's stop check) into a small host-visible slot.
+__global__ void k_peek_phase(const Ctrl* c, int* dst) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = c->phase;
 }
 
 }  // namespace naj

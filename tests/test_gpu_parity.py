@@ -126,6 +126,22 @@ def test_solve_poisson2d_matches_oracle_bitwise(naj):
     assert info.relres <= 1e-8
 
 
+@pytest.mark.parametrize("mode", ["0", "1", "2"])
+def test_every_driver_matches_oracle(naj, mode, monkeypatch):
+    """The three solve drivers (one launch per pass / one workgroup / cooperative persistent grid) share the
+    pass and must all reproduce the oracle's run, on a regular and on a ragged matrix."""
+    _say("driver", mode)
+    monkeypatch.setenv("NAJ_MODE", mode)
+    s = W.poisson2d_64()
+    sysm = naj.System(s.rowptr, s.colidx, s.vals)
+    rowptr, colidx, vals = W.random_spd(1000, 0.02, 5)
+    sysr = naj.System(rowptr, colidx, vals)
+    monkeypatch.delenv("NAJ_MODE")
+    _compare_solve(naj, sysm, s.rowptr, s.colidx, s.vals, s.b, tol=1e-8, max_iter=20000, bitwise=True)
+    b = np.random.default_rng(3).standard_normal(1000)
+    _compare_solve(naj, sysr, rowptr, colidx, vals, b, tol=1e-9, max_iter=20000)
+
+
 def test_solve_without_restart_is_algorithm1(naj):
     _say("solve no restart, capped")
     s = W.poisson2d_64()
@@ -219,8 +235,10 @@ def test_barrier_timeout_path_exits_cleanly(naj, monkeypatch):
     _say("forced barrier timeout")
     s = W.poisson2d_64()
     monkeypatch.setenv("NAJ_SPIN_TICKS", "0")
+    monkeypatch.setenv("NAJ_MODE", "2")          # the cooperative persistent driver has the grid barrier
     sysm = naj.System(s.rowptr, s.colidx, s.vals)
     monkeypatch.delenv("NAJ_SPIN_TICKS")
+    monkeypatch.delenv("NAJ_MODE")
     with pytest.raises(naj.NajError, match="timed out"):
         sysm.solve(s.b)
     sysm.close()
