@@ -4,11 +4,13 @@ Default workload: the 3D 7-point Dirichlet Laplacian on a 128^3 grid
 (n = 2,097,152, nnz = 14,581,760), float64, b = Q x* with x* ~ N(0,1)
 (seed 1002), x^0 = 0, restart on, K_0 = 2, solved to a confirmed relative
 residual <= 1e-8.  One step = one complete solve (all iterations of the
-persistent kernel), inputs resident in HBM, system set up beforehand.
+fused-pass launches), inputs resident in HBM, system set up beforehand.
 
 Prints one JSON line with the solve throughput, p50/p99 latency, the
-roofline figures of the persistent solve kernel (algorithmic bytes per
-launch / its HIP-event duration) and the CPU oracle baseline.
+roofline figures of the fused iteration kernel k_pass64 (algorithmic bytes
+per launch / its mean launch duration from HIP events on the solve's stream),
+the HBM traffic per launch from the committed counter runs (null when the
+kernel sources changed since), and the CPU oracle baseline.
 
     python bench.py [--steps K] [--warmup W] [--workload laplace3d_128|poisson2d_64|laplace3d_160]
 """
@@ -26,6 +28,30 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
+CSRC = os.path.join(ROOT, "paper_2407_03272_amd", "csrc")
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def kernel_source_hash() -> str:
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(CSRC, "*.h")) + glob.glob(os.path.join(CSRC, "*.hip"))):
+        h.update(os.path.basename(p).encode())
+        h.update(open(p, "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per pass from the committed rocprofv3 counter runs, or None when none exist for this
+    workload or the kernel sources changed since they were taken."""
+    path = os.path.join(PROFILES, f"k_pass64_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    return rec["traffic_bytes_per_pass"]
 
 
 def bytes_per_iteration(n: int, nnz: int, s_v: int = 8, s_x: int = 8, k: int = 1) -> int:
@@ -76,6 +102,8 @@ def main():
     ap.add_argument("--workload", default="laplace3d_128")
     ap.add_argument("--cpu-sample-iters", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--pmc-sample", action="store_true",
+                    help="run only a 1 GiB torch copy (counter calibration) and a 50-iteration solve, for rocprofv3 --pmc")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
@@ -88,6 +116,17 @@ def main():
     sysobj = make_workload(args.workload)
     n, nnz = sysobj.n, sysobj.nnz
     dev = torch.device("cuda:0")
+    if args.pmc_sample:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)     # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        sysm = naj.System(sysobj.rowptr, sysobj.colidx, sysobj.vals, device="cuda:0")
+        b = torch.as_tensor(sysobj.b).to(dev)
+        _, info = sysm.solve(b, hist_cap=0, tol=1e-30, max_iter=50)
+        print(json.dumps({"pmc_sample": True, "copy_bytes_each_way": src.numel() * 8, "passes": info.passes}))
+        return
     sysm = naj.System(sysobj.rowptr, sysobj.colidx, sysobj.vals, device="cuda:0")
     b = torch.as_tensor(sysobj.b).to(dev)
     x = torch.empty(n, dtype=torch.float64, device=dev)
@@ -112,8 +151,9 @@ def main():
     total = time.perf_counter() - t_start
 
     it = iters[-1]
-    conf = passes[-1] - it
-    # every pass of the kernel: norm of b (8n bytes), iterations, residual confirmations
+    conf = passes[-1] - it - 1
+    # every pass of a solve: norm of b (8n bytes), the iterations, the residual confirmations.  The
+    # HIP events bracket all launches of a solve (the trailing launches that return at once included).
     alg_bytes = 8 * n + it * bytes_per_iteration(n, nnz) + conf * bytes_per_residual(n, nnz)
     kernel_s = float(np.mean(kms)) / 1e3
     achieved = alg_bytes / kernel_s / 1e9
@@ -139,10 +179,11 @@ def main():
         "p99_ms": float(np.percentile(lat, 99) * 1e3),
         "kernel_ms": float(np.mean(kms)),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_solve64 (persistent, one launch per solve)",
-                     "algorithmic_bytes_per_launch": alg_bytes,
-                     "bytes_per_iteration": bytes_per_iteration(n, nnz)},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload),
+                     "kernel": "k_pass64 (fused iteration pass, one launch per pass)",
+                     "launches_per_solve": passes[-1],
+                     "algorithmic_bytes_per_launch": bytes_per_iteration(n, nnz),
+                     "mean_launch_us": kernel_s / passes[-1] * 1e6},
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(sysobj, it, args.cpu_sample_iters)

@@ -284,10 +284,10 @@ naj_status choose_grid(naj_system* s) {
   if (nxcd < 1) nxcd = 1;
   if (nxcd > kMaxDomains) nxcd = kMaxDomains;
   s->nxcd = nxcd;
-  int bs = env_int("NAJ_BS", 256);   // 256 x 4 per CU measured best on 128^3 (with 512x2 and 1024x1)
+  int bs = env_int("NAJ_BS", 256);   // 256 threads x 3 per CU measured best on the 128^3 Laplacian
   if (bs != 256 && bs != 512 && bs != 1024) bs = 256;
   s->pass_bs = bs;
-  const int per_cu = std::max(1, env_int("NAJ_WG_PER_CU", 4 * 256 / bs));
+  const int per_cu = std::max(1, env_int("NAJ_WG_PER_CU", bs == 256 ? 3 : 2 * 256 / bs));
   int g = per_cu * s->cus;
   g -= g % nxcd;
   if (g < nxcd) g = nxcd;

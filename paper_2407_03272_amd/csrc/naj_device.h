@@ -22,18 +22,20 @@ namespace naj {
 
 constexpr int kWave = 64;
 #ifndef NAJ_UNROLL
-#define NAJ_UNROLL 8
+#define NAJ_UNROLL 4
 #endif
-constexpr int kUnroll = NAJ_UNROLL;   // column steps whose loads are issued together
+// Column steps whose loads are issued together.  4 measured best on the 128^3
+// Laplacian (fewer registers, more resident waves than 8 or 16).
+constexpr int kUnroll = NAJ_UNROLL;
 
-// Matrix entries are read once per pass: load them non-temporally so they do
-// not displace the vector data the gathers reuse.
+// Loads of matrix entries.  Ordinary cached loads measured faster than
+// non-temporal ones (which are kept as a build option).
 template <typename T>
 __device__ __forceinline__ T stream_load(const T* p) {
-#if defined(NAJ_PLAIN_LOADS)
-  return *p;
-#else
+#if defined(NAJ_NT_LOADS)
   return __builtin_nontemporal_load(p);
+#else
+  return *p;
 #endif
 }
 
