@@ -226,17 +226,18 @@ def inner_solve_fp32(Q32: sp.csr_matrix, dinv32: np.ndarray, r32: np.ndarray, *,
                      max_iter: int, restart: bool, k0: int):
     """Algorithm 3 on Q d = r in float32 from d^0 = 0 with float64 reductions.
 
-    The product, the Jacobi step and the momentum step are float32 operations
-    (float32 accumulation in the row sums).  The restart inner product and the
-    monitor norm are accumulated in float64.  The solve stops when
-    ||Q y^t - r|| / ||r|| <= inner_tol and returns x^t, or returns x^T after
-    ``max_iter`` iterations.  Returns (d, iterations, restarts).
+    The product, the Jacobi-type step and the momentum step are float32
+    operations (float32 accumulation in the row sums; the momentum coefficient
+    rounded to float32).  The restart inner product and the monitor norm are
+    accumulated in float64 from the exactly converted float32 operands.  The
+    solve stops when ||Q y^t - r|| / ||r|| <= inner_tol and returns x^t, or
+    returns the last iterate after ``max_iter`` iterations.
+    Returns (d, iterations, restarts, finite).
     """
     n = Q32.shape[0]
     f32 = np.float32
-    nr = math.sqrt(float(np.dot(r32.astype(np.float64), r32.astype(np.float64))))
-    if nr == 0.0:
-        return np.zeros(n, dtype=f32), 0, []
+    r64 = r32.astype(np.float64)
+    nr = math.sqrt(float(r64 @ r64))
     x_prev = np.zeros(n, dtype=f32)
     y = np.zeros(n, dtype=f32)
     alpha = 1.0
@@ -248,12 +249,12 @@ def inner_solve_fp32(Q32: sp.csr_matrix, dinv32: np.ndarray, r32: np.ndarray, *,
         x = (y - dinv32 * g).astype(f32)
         g64 = g.astype(np.float64)
         mon = math.sqrt(float(g64 @ g64)) / nr
-        if not math.isfinite(mon):
-            return x, t, restarts
-        if mon <= inner_tol:
-            return x, t, restarts
         d = (x - x_prev).astype(f32)
         s = float(g64 @ d.astype(np.float64))
+        if not (math.isfinite(mon) and math.isfinite(s)):
+            return x_prev, t, restarts, False
+        if mon <= inner_tol:
+            return x, t, restarts, True
         if restart and t > K_re + K and s >= 0.0:
             K_re, K = t, 2 * K
             restarts.append(t)
@@ -265,25 +266,31 @@ def inner_solve_fp32(Q32: sp.csr_matrix, dinv32: np.ndarray, r32: np.ndarray, *,
             y = (x + beta * d).astype(f32)
             x_prev = x
         alpha = a_next
-    return x_prev, max_iter, restarts
+    return x_prev, max_iter, restarts, True
 
 
 def accelerated_jacobi_mixed(rowptr, colidx, vals, b, x0=None, *, tol: float = 1e-8, max_refine: int = 50,
-                             inner_tol: float = 1e-4, inner_max_iter: int = 5000, restart: bool = True,
-                             k0: int = 2) -> MixedResult:
+                             inner_tol: float = 1e-4, inner_max_iter: int = 20000, restart: bool = True,
+                             k0: int = 2, D: np.ndarray | None = None) -> MixedResult:
     """Float32 inner Algorithm 3 inside float64 iterative refinement.
 
-    Outer step k: r_k = b - Q x_k with float64 values and accumulation; stop
-    when ||r_k|| / ||b|| <= tol; otherwise round r_k to float32, solve
-    Q d = r_k approximately with ``inner_solve_fp32`` (float32 copy of Q, J
-    from the float32 row absolute sums), and set x_{k+1} = x_k + d in float64.
-    Not a method of the paper: the paper's algorithm is the inner solver.
+    Outer step k = 0, 1, ...: r_k = b - Q x_k with float64 values and
+    accumulation; stop when ||r_k|| / ||b|| <= tol, or (NOT_CONVERGED) when k
+    reaches ``max_refine`` or fl32(r_k) is zero; otherwise solve Q d = fl32(r_k)
+    approximately with ``inner_solve_fp32`` (float32 copy of Q, J from the
+    float32 row absolute sums, or fl32(1/D) for a caller diagonal) and set
+    x_{k+1} = x_k + d in float64.  A non-finite inner reduction ends the solve
+    with BREAKDOWN and x_k.  The refinement loop is not part of the paper; the
+    paper's algorithm is the inner solver.
     """
     Q = csr(rowptr, colidx, vals)
     Q32 = csr(rowptr, colidx, np.asarray(vals, dtype=np.float32), dtype=np.float32)
     n = Q.shape[0]
-    J32 = jacobi_diagonal(Q32)
-    dinv32 = (np.float32(1.0) / J32).astype(np.float32)
+    if D is None:
+        J32 = jacobi_diagonal(Q32)
+        dinv32 = (np.float32(1.0) / J32).astype(np.float32)
+    else:
+        dinv32 = (1.0 / np.asarray(D, dtype=np.float64)).astype(np.float32)
     b = np.asarray(b, dtype=np.float64)
     x = np.zeros(n) if x0 is None else np.asarray(x0, dtype=np.float64).copy()
     nb = float(np.linalg.norm(b))
@@ -296,24 +303,25 @@ def accelerated_jacobi_mixed(rowptr, colidx, vals, b, x0=None, *, tol: float = 1
         rho = float(np.linalg.norm(r)) / nb
         out.outer += 1
         out.relres_hist.append(rho)
+        out.x = x
         if not math.isfinite(rho):
             out.status = STATUS_BREAKDOWN
-            break
-        if rho <= tol:
-            out.x = x
             return out
-        if k == max_refine:
-            break
+        if rho <= tol:
+            return out
         r32 = r.astype(np.float32)
-        d, it, rs = inner_solve_fp32(Q32, dinv32, r32, inner_tol=inner_tol, max_iter=inner_max_iter,
-                                     restart=restart, k0=k0)
+        if k == max_refine or not np.any(r32):
+            break
+        d, it, rs, finite = inner_solve_fp32(Q32, dinv32, r32, inner_tol=inner_tol, max_iter=inner_max_iter,
+                                             restart=restart, k0=k0)
         out.inner_total += it
         out.inner_iters.append(it)
         out.inner_restarts.append(rs)
+        if not finite:
+            out.status = STATUS_BREAKDOWN
+            return out
         x = x + d.astype(np.float64)
-    out.x = x
-    if out.status == STATUS_OK:
-        out.status = STATUS_NOT_CONVERGED
+    out.status = STATUS_NOT_CONVERGED
     return out
 
 

@@ -195,6 +195,7 @@ struct naj_system {
   float* val32 = nullptr;
   double* dinv = nullptr;          // caller's D as 1/D, or null
   double* vec[3] = {nullptr, nullptr, nullptr};
+  float* fvec[4] = {nullptr, nullptr, nullptr, nullptr};   // mixed precision: 3 inner iterates + r32 (lazy)
   double* part = nullptr;          // 3 * max_grid
   Ctrl* ctrl = nullptr;
   Barrier* bar = nullptr;
@@ -241,6 +242,7 @@ void free_system(naj_system* s) {
   (void)hipFree(s->val32);
   (void)hipFree(s->dinv);
   for (auto& v : s->vec) (void)hipFree(v);
+  for (auto& v : s->fvec) (void)hipFree(v);
   (void)hipFree(s->part);
   (void)hipFree(s->ctrl);
   (void)hipFree(s->bar);
@@ -400,6 +402,14 @@ SolveArgs make_args(naj_system* s, const double* b, const naj_opts& o) {
   a.max_iter = o.max_iter;
   a.restart = o.restart ? 1 : 0;
   a.confirm_gap = o.confirm_gap;
+  a.k0 = o.k0;
+  a.precision = o.precision == NAJ_MIXED ? 1 : 0;
+  a.max_refine = o.max_refine;
+  a.inner_tol = o.inner_tol;
+  a.f0 = s->fvec[0];
+  a.f1 = s->fvec[1];
+  a.f2 = s->fvec[2];
+  a.r32 = s->fvec[3];
   a.nxcd = s->nxcd;
   a.spin_ticks = s->spin_ticks;
   return a;
@@ -439,7 +449,9 @@ naj_status run_solve(naj_system* s, SolveArgs& a, const naj_opts& o, hipStream_t
   const void* fn = pass_kernel(ud, s->pass_bs);
   const dim3 grid(s->grid), block(s->pass_bs);
   // passes: norm of b + iterations + confirmations (at most one per confirm_gap iterations, plus one)
-  const int64_t max_pass = 2 + (int64_t)o.max_iter + (int64_t)o.max_iter / std::max(1, o.confirm_gap) + 1;
+  const int64_t max_pass = o.precision == NAJ_MIXED
+                               ? 2 + (int64_t)(o.max_refine + 1) * (1 + (int64_t)o.max_iter)
+                               : 2 + (int64_t)o.max_iter + (int64_t)o.max_iter / std::max(1, o.confirm_gap) + 1;
   int64_t launched = 0;
   int chunk = 4, cur = 0, prev = -1;
   HIP_TRY(hipEventRecord(s->ev0, st));
@@ -623,13 +635,18 @@ naj_status naj_solve(naj_system* s, const double* b, const double* x0, const naj
   if (opts) o = *opts; else naj_opts_default(&o);
   naj_status rc = check_opts(o);
   if (rc != NAJ_OK) return rc;
-  if (o.precision != NAJ_FP64) return fail(NAJ_EINVAL, "mixed precision is not available in this build");
   if ((hist && hist_cap < 0) || (trace && trace_cap < 0) || (restart_log && log_cap < 0))
     return fail(NAJ_EINVAL, "negative capacity");
   hipStream_t st = (hipStream_t)stream;
   HIP_TRY(hipSetDevice(s->device));
   rc = ensure_hist(s, hist ? hist_cap : 0, trace ? trace_cap : 0);
   if (rc != NAJ_OK) return rc;
+  if (o.precision == NAJ_MIXED && !s->fvec[0]) {
+    for (auto& v : s->fvec) {
+      rc = dev_alloc(s, &v, (size_t)s->n);
+      if (rc != NAJ_OK) return rc;
+    }
+  }
   if (x0) HIP_TRY(hipMemcpyAsync(s->vec[0], x0, sizeof(double) * s->n, hipMemcpyDeviceToDevice, st));
   else HIP_TRY(hipMemsetAsync(s->vec[0], 0, sizeof(double) * s->n, st));
   hipLaunchKernelGGL(k_solve_init, dim3(1), dim3(64), 0, st, s->ctrl, s->bar, s->counters, o.k0);
@@ -649,7 +666,7 @@ naj_status naj_solve(naj_system* s, const double* b, const double* x0, const naj
   HIP_TRY(hipStreamSynchronize(st));
   const int hl = std::min(hc.hist_len, a.hist_cap);
   if (hist && hl > 0) HIP_TRY(hipMemcpy(hist, s->hist, sizeof(double) * hl, hipMemcpyDeviceToHost));
-  const int tl = std::min(hc.hist_len, a.trace_cap);
+  const int tl = std::min(o.precision == NAJ_MIXED ? hc.outer : hc.hist_len, a.trace_cap);
   if (trace && tl > 0) HIP_TRY(hipMemcpy(trace, s->trace, sizeof(double) * 2 * tl, hipMemcpyDeviceToHost));
   int nlog = std::min(hc.restarts, (int)kRestartLogCap);
   if (restart_log) {
@@ -661,12 +678,17 @@ naj_status naj_solve(naj_system* s, const double* b, const double* x0, const naj
   res->restarts = hc.restarts;
   res->confirmations = hc.confirms;
   res->relres = hc.relres;
+  if (o.precision == NAJ_MIXED) {
+    res->iterations = hc.inner_total;
+    res->restarts = hc.inner_restarts;
+    res->confirmations = hc.outer;
+  }
   res->hist_len = hist ? hl : 0;
   res->nrestart_log = restart_log ? nlog : 0;
   float ms = 0.f;
   HIP_TRY(hipEventElapsedTime(&ms, s->ev0, s->ev1));
   res->kernel_ms = ms;
-  res->passes = hc.hist_len + hc.confirms;
+  res->passes = hc.passes;
   res->grid = s->grid;
   if (hc.timeout) {
     res->status = NAJ_EDEVICE;

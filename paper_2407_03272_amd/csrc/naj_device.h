@@ -39,7 +39,8 @@ __device__ __forceinline__ T stream_load(const T* p) {
 #endif
 }
 
-enum Phase : int { PH_NORMB = 0, PH_ITER = 1, PH_CONFIRM = 2, PH_DONE = 3 };
+// PH_RESID64 and PH_INNER32 belong to the mixed-precision refinement loop.
+enum Phase : int { PH_NORMB = 0, PH_ITER = 1, PH_CONFIRM = 2, PH_DONE = 3, PH_RESID64 = 4, PH_INNER32 = 5 };
 
 enum : int { ST_OK = 0, ST_NOT_CONVERGED = 1, ST_EDEVICE = -3, ST_BREAKDOWN = -4 };
 
@@ -68,6 +69,16 @@ struct Ctrl {
   int hist_len;
   int timeout;           // set by a workgroup whose barrier wait timed out
   int passes;            // matrix passes run so far (including the norm of b)
+  // mixed precision: the inner float32 solve reuses t, alpha, beta, K_re, K, ell,
+  // iP/iR/iW (float32 buffers) and beta_zero above
+  int zp;                // inner pass t = 1: the previous inner iterate is the zero vector
+  int iX, iXn;           // float64 buffers: current x, next x (written by an updating residual pass)
+  int iD;                // float32 buffer holding the inner result d of the pending update
+  int update;            // the next residual pass applies x + d
+  int outer;             // float64 residual passes done
+  int inner_total;       // inner iterations summed over refinement steps
+  int inner_restarts;    // inner restarts summed
+  double nr;             // ||fl32(r)||_2 of the current inner right-hand side
   int restart_log[kRestartLogCap];
 };
 
@@ -111,8 +122,17 @@ struct SolveArgs {
   int max_iter;
   int restart;
   int confirm_gap;
+  int k0;
   int nxcd;                   // workgroups are spread round-robin over this many L2 domains
   long long spin_ticks;       // barrier wait limit in wall-clock ticks
+  // mixed precision
+  int precision;              // 0 float64, 1 float32 inner solve + float64 refinement
+  int max_refine;
+  double inner_tol;
+  float* f0;                  // three float32 inner iterates
+  float* f1;
+  float* f2;
+  float* r32;                 // float32 right-hand side of the inner solve
 };
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -124,6 +144,10 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 __device__ __forceinline__ double* pick(const SolveArgs& a, int i) {
   return i == 0 ? a.buf0 : (i == 1 ? a.buf1 : a.buf2);
+}
+
+__device__ __forceinline__ float* pickf(const SolveArgs& a, int i) {
+  return i == 0 ? a.f0 : (i == 1 ? a.f1 : a.f2);
 }
 
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x / kWave); }
@@ -232,6 +256,134 @@ __device__ __forceinline__ void resid_slice(const Sell& A, int64_t s, int lane, 
     const double r = bi - acc;
     if (out) out[row] = r;
     prr = prr + r * r;
+  }
+}
+
+// One slice of the float32 inner pass (mixed precision): the same step as
+// iter_slice on Q d = r32 with float32 values, vectors and row sums; the
+// restart inner product and the monitor are accumulated in float64 from
+// exactly converted float32 operands.  zp: the previous iterate is zero.
+template <bool USER_D>
+__device__ __forceinline__ void inner_slice(const SolveArgs& a, int64_t s, int lane, const float* __restrict__ P,
+                                            const float* __restrict__ R, float* __restrict__ W, float beta, bool bz,
+                                            bool zp, double& ps, double& pgg, double& psabs) {
+  const int64_t base = a.A.slice_ptr[s];
+  const int width = (int)((a.A.slice_ptr[s + 1] - base) >> 6);
+  const int64_t row = s * kWave + lane;
+  const bool live = row < a.A.n;
+  const int64_t rr = live ? row : 0;
+  const float Pi = zp ? 0.0f : P[rr];
+  const float Ri = (zp || bz) ? 0.0f : R[rr];
+  const float bi = a.r32[rr];
+  const double di = USER_D ? a.dinv[rr] : 0.0;
+  const int32_t* __restrict__ cp = a.A.col + base + lane;
+  const float* __restrict__ vp = a.A.val32 + base + lane;
+  float acc = 0.0f, asum = 0.0f;
+  for (int k0 = 0; k0 < width; k0 += kUnroll) {
+    int c[kUnroll];
+    float v[kUnroll], y[kUnroll];
+#pragma unroll
+    for (int j = 0; j < kUnroll; ++j)
+      if (k0 + j < width) {
+        c[j] = stream_load(cp + (k0 + j) * kWave);
+        v[j] = stream_load(vp + (k0 + j) * kWave);
+      }
+    if (zp) {
+#pragma unroll
+      for (int j = 0; j < kUnroll; ++j) y[j] = 0.0f;
+    } else if (bz) {
+#pragma unroll
+      for (int j = 0; j < kUnroll; ++j)
+        if (k0 + j < width) y[j] = P[c[j]];
+    } else {
+      float pj[kUnroll], rj[kUnroll];
+#pragma unroll
+      for (int j = 0; j < kUnroll; ++j)
+        if (k0 + j < width) {
+          pj[j] = P[c[j]];
+          rj[j] = R[c[j]];
+        }
+#pragma unroll
+      for (int j = 0; j < kUnroll; ++j)
+        if (k0 + j < width) y[j] = pj[j] + beta * (pj[j] - rj[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < kUnroll; ++j)
+      if (k0 + j < width) {
+        acc = acc + v[j] * y[j];
+        asum = asum + fabsf(v[j]);
+      }
+  }
+  if (live) {
+    const float yi = (zp || bz) ? Pi : Pi + beta * (Pi - Ri);
+    const float g = acc - bi;
+    const float dv = USER_D ? (float)di : 1.0f / (asum == 0.0f ? 1.0f : asum);
+    const float xi = yi - dv * g;
+    W[row] = xi;
+    const float d = xi - Pi;
+    const double g64 = (double)g, d64 = (double)d;
+    const double gd = g64 * d64;
+    ps = ps + gd;
+    pgg = pgg + g64 * g64;
+    psabs = psabs + fabs(gd);
+  }
+}
+
+// One slice of the float64 residual pass of the refinement loop: with D != null
+// the iterate is first updated, x_new = X + (double)D (formed at every gathered
+// column, stored for the own rows in Xn); then r = b - Q x_new in float64,
+// r32 = fl32(r), and ||r||^2, ||r32||^2 are accumulated.
+__device__ __forceinline__ void resid_mixed_slice(const SolveArgs& a, int64_t s, int lane, const double* __restrict__ X,
+                                                  const float* __restrict__ D, double* __restrict__ Xn, double& prr,
+                                                  double& pr32) {
+  const int64_t base = a.A.slice_ptr[s];
+  const int width = (int)((a.A.slice_ptr[s + 1] - base) >> 6);
+  const int64_t row = s * kWave + lane;
+  const bool live = row < a.A.n;
+  const int64_t rr = live ? row : 0;
+  const double bi = a.b[rr];
+  const double xi0 = X[rr];
+  const float di0 = D ? D[rr] : 0.0f;
+  const int32_t* __restrict__ cp = a.A.col + base + lane;
+  const double* __restrict__ vp = a.A.val + base + lane;
+  double acc = 0.0;
+  for (int k0 = 0; k0 < width; k0 += kUnroll) {
+    int c[kUnroll];
+    double v[kUnroll], xj[kUnroll];
+#pragma unroll
+    for (int j = 0; j < kUnroll; ++j)
+      if (k0 + j < width) {
+        c[j] = stream_load(cp + (k0 + j) * kWave);
+        v[j] = stream_load(vp + (k0 + j) * kWave);
+      }
+    if (D) {
+      float dj[kUnroll];
+#pragma unroll
+      for (int j = 0; j < kUnroll; ++j)
+        if (k0 + j < width) {
+          xj[j] = X[c[j]];
+          dj[j] = D[c[j]];
+        }
+#pragma unroll
+      for (int j = 0; j < kUnroll; ++j)
+        if (k0 + j < width) xj[j] = xj[j] + (double)dj[j];
+    } else {
+#pragma unroll
+      for (int j = 0; j < kUnroll; ++j)
+        if (k0 + j < width) xj[j] = X[c[j]];
+    }
+#pragma unroll
+    for (int j = 0; j < kUnroll; ++j)
+      if (k0 + j < width) acc = acc + v[j] * xj[j];
+  }
+  if (live) {
+    if (D) Xn[row] = xi0 + (double)di0;
+    const double r = bi - acc;
+    const float r32 = (float)r;
+    a.r32[row] = r32;
+    prr = prr + r * r;
+    const double r64 = (double)r32;
+    pr32 = pr32 + r64 * r64;
   }
 }
 

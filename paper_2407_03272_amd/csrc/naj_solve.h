@@ -59,6 +59,109 @@ __device__ inline void apply_step(const SolveArgs& a, Ctrl* c, bool restart) {
   }
 }
 
+// Mixed precision, after a float64 residual pass (refinement step k = c->outer):
+// accept x, give up, or start a float32 inner solve of Q d = fl32(r) from d = 0.
+__device__ inline void mixed_after_residual(const SolveArgs& a, Ctrl* c, double rr, double r32sq) {
+  if (c->update) {               // the pass wrote x + d into iXn: it is the current iterate now
+    const int t = c->iX;
+    c->iX = c->iXn;
+    c->iXn = t;
+    c->update = 0;
+  }
+  const int k = c->outer;
+  const double rho = sqrt(rr) / c->nb;
+  c->outer = k + 1;
+  if (a.hist && k < a.hist_cap) a.hist[k] = rho;
+  c->hist_len = k + 1;
+  c->relres = rho;
+  c->result = c->iX;
+  if (!(rho < __builtin_inf())) {
+    c->status = ST_BREAKDOWN;
+    c->phase = PH_DONE;
+    return;
+  }
+  if (rho <= a.tol) {
+    c->status = ST_OK;
+    c->phase = PH_DONE;
+    return;
+  }
+  c->nr = sqrt(r32sq);
+  if (k >= a.max_refine || c->nr == 0.0) {   // refinement budget spent, or nothing left to correct in float32
+    c->status = ST_NOT_CONVERGED;
+    c->phase = PH_DONE;
+    return;
+  }
+  c->t = 1;
+  c->alpha = 1.0;
+  c->beta = 0.0;
+  c->beta_zero = 1;
+  c->zp = 1;
+  c->K_re = 0;
+  c->K = a.k0;
+  c->ell = 0;
+  c->iP = 0;
+  c->iR = 1;
+  c->iW = 2;
+  c->phase = PH_INNER32;
+}
+
+__device__ inline void mixed_finish_inner(const SolveArgs& a, Ctrl* c, int d_buf, int its) {
+  const int k = c->outer - 1;
+  if (a.trace && k < a.trace_cap) {
+    a.trace[2 * k] = (double)its;
+    a.trace[2 * k + 1] = (double)c->ell;
+  }
+  c->inner_total += its;
+  c->inner_restarts += c->ell;
+  c->iD = d_buf;
+  c->update = 1;
+  c->phase = PH_RESID64;
+}
+
+// Mixed precision, after a float32 inner pass: the inner solve's stop test, then
+// the restart test and the restart/momentum branches of Algorithm 2.
+__device__ inline void mixed_after_inner(const SolveArgs& a, Ctrl* c, double s, double gg, double sabs) {
+  (void)sabs;
+  const int t = c->t;
+  const double mon = sqrt(gg) / c->nr;
+  if (!(mon < __builtin_inf()) || !(fabs(s) < __builtin_inf())) {
+    c->status = ST_BREAKDOWN;
+    c->result = c->iX;
+    c->phase = PH_DONE;
+    return;
+  }
+  if (mon <= a.inner_tol) {
+    mixed_finish_inner(a, c, c->iW, t);     // d = x^t
+    return;
+  }
+  const bool restart = a.restart && (t > c->K_re + c->K) && (s >= 0.0);
+  if (restart) {
+    c->K_re = t;
+    c->K = c->K < (1 << 29) ? 2 * c->K : c->K;
+    c->ell += 1;
+    c->alpha = 1.0;
+    c->beta = 0.0;
+    c->beta_zero = 1;
+  } else {
+    const double alpha = c->alpha;
+    const double an = (1.0 + sqrt(1.0 + 4.0 * alpha * alpha)) / 2.0;
+    const double beta = (alpha - 1.0) / an;
+    c->alpha = an;
+    c->beta = beta;
+    c->beta_zero = beta == 0.0 ? 1 : 0;
+    const int p = c->iP, r = c->iR, w = c->iW;
+    c->iP = w;
+    c->iR = p;
+    c->iW = r;
+    c->zp = 0;
+  }
+  if (t >= a.max_iter) {
+    mixed_finish_inner(a, c, c->iP, a.max_iter);   // d = the last iterate
+    return;
+  }
+  c->t = t + 1;
+}
+
 // The decision after a pass, from its three reduced sums.  One thread runs it.
 __device__ inline void control_update(const SolveArgs& a, Ctrl* c, double r0, double r1, double r2) {
   const int phase = c->phase;
@@ -78,8 +181,16 @@ __device__ inline void control_update(const SolveArgs& a, Ctrl* c, double r0, do
       c->relres = 0.0;
       c->phase = PH_DONE;
     } else {
-      c->phase = PH_ITER;
+      c->phase = a.precision ? PH_RESID64 : PH_ITER;
     }
+    return;
+  }
+  if (phase == PH_RESID64) {
+    mixed_after_residual(a, c, r0, r1);
+    return;
+  }
+  if (phase == PH_INNER32) {
+    mixed_after_inner(a, c, r0, r1, r2);
     return;
   }
   if (phase == PH_ITER) {
@@ -134,7 +245,7 @@ __device__ inline void control_update(const SolveArgs& a, Ctrl* c, double r0, do
 
 // Control fields a pass needs, staged in LDS by thread 0.
 struct PassView {
-  int phase, iP, iR, iW, bz;
+  int phase, iP, iR, iW, bz, zp, iX, iXn, iD, update;
   double beta;
 };
 
@@ -145,6 +256,11 @@ __device__ __forceinline__ void load_view(const Ctrl* c, PassView* v) {
   v->iW = c->iW;
   v->bz = c->beta_zero;
   v->beta = c->beta;
+  v->zp = c->zp;
+  v->iX = c->iX;
+  v->iXn = c->iXn;
+  v->iD = c->iD;
+  v->update = c->update;
 }
 
 // The workgroup's share of one pass; partial sums in p0..p2 (per thread).
@@ -162,6 +278,19 @@ __device__ __forceinline__ void run_pass(const SolveArgs& a, const PassView& v, 
   } else if (v.phase == PH_CONFIRM) {
     const double* X = pick(a, v.iW);
     for (int64_t s = wr.first; s < wr.end; s += wr.step) resid_slice(a.A, s, lane, X, a.b, nullptr, p0);
+  } else if (v.phase == PH_INNER32) {
+    const float* P = pickf(a, v.iP);
+    const float* R = pickf(a, v.iR);
+    float* W = pickf(a, v.iW);
+    const float beta = (float)v.beta;
+    const bool bz = v.bz != 0, zp = v.zp != 0;
+    for (int64_t s = wr.first; s < wr.end; s += wr.step)
+      inner_slice<USER_D>(a, s, lane, P, R, W, beta, bz, zp, p0, p1, p2);
+  } else if (v.phase == PH_RESID64) {
+    const double* X = pick(a, v.iX);
+    const float* D = v.update ? pickf(a, v.iD) : nullptr;
+    double* Xn = v.update ? pick(a, v.iXn) : nullptr;
+    for (int64_t s = wr.first; s < wr.end; s += wr.step) resid_mixed_slice(a, s, lane, X, D, Xn, p0, p1);
   } else {  // PH_NORMB
     for (int64_t s = wr.first; s < wr.end; s += wr.step) {
       const int64_t row = s * kWave + lane;
@@ -248,6 +377,11 @@ __global__ void __launch_bounds__(BS) k_solve64(SolveArgs a) {
         v.iW = __hip_atomic_load(&a.ctrl->iW, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         v.bz = __hip_atomic_load(&a.ctrl->beta_zero, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         v.beta = __hip_atomic_load(&a.ctrl->beta, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        v.zp = __hip_atomic_load(&a.ctrl->zp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        v.iX = __hip_atomic_load(&a.ctrl->iX, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        v.iXn = __hip_atomic_load(&a.ctrl->iXn, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        v.iD = __hip_atomic_load(&a.ctrl->iD, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        v.update = __hip_atomic_load(&a.ctrl->update, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
     }
     __syncthreads();
@@ -330,6 +464,15 @@ __global__ void k_solve_init(Ctrl* c, Barrier* bar, unsigned int* counters, int 
     c->hist_len = 0;
     c->timeout = 0;
     c->passes = 0;
+    c->zp = 0;
+    c->iX = 0;
+    c->iXn = 1;
+    c->iD = 0;
+    c->update = 0;
+    c->outer = 0;
+    c->inner_total = 0;
+    c->inner_restarts = 0;
+    c->nr = 0.0;
     for (int i = 0; i < kRestartLogCap; ++i) c->restart_log[i] = 0;
     bar->count = 0ULL;
     bar->epoch_done = 0u;
