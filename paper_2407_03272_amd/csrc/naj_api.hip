@@ -81,26 +81,28 @@ __global__ void k_check_D(const double* D, int64_t n, double* dinv, int* flag) {
   }
 }
 
-// Width of each 64-row slice = its longest row.
-__global__ void k_slice_width(const int32_t* rowptr, int64_t n, int64_t nslices, int32_t* width) {
-  const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int64_t s = row / kWave;
+// Width of each 64-row slice (rows row0 + 64 s + lane) = its longest row.
+__global__ void k_slice_width(const int32_t* rowptr, int64_t row0, int64_t n, int64_t nslices, int32_t* width) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t s = t / kWave;
+  const int64_t row = row0 + t;
   int len = row < n ? rowptr[row + 1] - rowptr[row] : 0;
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) len = max(len, __shfl_xor(len, off, 64));
   if ((threadIdx.x % kWave) == 0 && s < nslices) width[s] = len;
 }
 
-__global__ void k_sell_fill(const int32_t* rowptr, const int32_t* colidx, const double* vals, int64_t n,
+__global__ void k_sell_fill(const int32_t* rowptr, const int32_t* colidx, const double* vals, int64_t row0, int64_t n,
                             int64_t nslices, const int64_t* slice_ptr, int32_t* col, double* val, float* val32) {
-  const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int64_t s = row / kWave;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t s = t / kWave;
   if (s >= nslices) return;
-  const int lane = (int)(row % kWave);
+  const int lane = (int)(t % kWave);
+  const int64_t row = row0 + t;
   const int64_t base = slice_ptr[s];
   const int width = (int)((slice_ptr[s + 1] - base) / kWave);
   const int64_t r0 = row < n ? rowptr[row] : 0;
-  const int len = row < n ? rowptr[row + 1] - (int32_t)r0 : 0;
+  const int len = row < n ? (int)(rowptr[row + 1] - r0) : 0;
   const int32_t self = row < n ? (int32_t)row : 0;
   for (int k = 0; k < width; ++k) {
     const int64_t dst = base + (int64_t)k * kWave + lane;
@@ -117,16 +119,65 @@ __global__ void k_sell_fill(const int32_t* rowptr, const int32_t* colidx, const 
   }
 }
 
+// Symmetric renumbering: new row i is old row perm[i]; its entries keep their
+// stored order, with columns renamed through iperm.  One wavefront per row.
+__global__ void k_permute_rows(const int32_t* rowptr, const int32_t* colidx, const double* vals, int64_t n,
+                               const int32_t* perm, const int32_t* iperm, const int64_t* new_rowptr, int32_t* new_col,
+                               double* new_val) {
+  const int lane = threadIdx.x % kWave;
+  const int64_t w0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
+  const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
+  for (int64_t i = w0; i < n; i += nw) {
+    const int32_t o = perm[i];
+    const int64_t s = rowptr[o], e = rowptr[o + 1], d = new_rowptr[i];
+    for (int64_t k = s + lane; k < e; k += kWave) {
+      new_col[d + (k - s)] = iperm[colidx[k]];
+      new_val[d + (k - s)] = vals[k];
+    }
+  }
+}
+
+__global__ void k_to_float(const double* in, float* out, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = (float)in[i];
+}
+
+// out[i] = in[perm[i]] (into the solver's row order)
+__global__ void k_gather(const double* in, const int32_t* perm, double* out, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = in[perm[i]];
+}
+
+// out[perm[i]] = in[i] (back to the caller's row order)
+__global__ void k_scatter(const double* in, const int32_t* perm, double* out, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[perm[i]] = in[i];
+}
+
+// J of the long rows, summed in the order the solve kernels use.
+__global__ void k_long_abs_sum(Sell A, double* out) {
+  const int lane = threadIdx.x % kWave;
+  const int64_t w0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
+  const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
+  for (int64_t r = w0; r < A.n_long; r += nw) {
+    double acc, asum;
+    long_row_sums<double>(A.lcol, A.lval, A.lrowptr[r], A.lrowptr[r + 1], lane, [](int) { return 0.0; }, acc, asum);
+    asum = wave_sum(asum);
+    if (lane == 0) out[r] = asum == 0.0 ? 1.0 : asum;
+  }
+}
+
 // J of eq. (J-diag) as the row absolute sum in row order (equal for PSD Q), zero rows -> 1.
 __global__ void k_row_abs_sum(Sell A, const double* dinv, double* out) {
-  const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int64_t s = row / kWave;
-  if (s >= A.nslices || row >= A.n) return;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (dinv) {
-    out[row] = 1.0 / dinv[row];
+    if (t < A.n) out[t] = 1.0 / dinv[t];
     return;
   }
-  const int lane = (int)(row % kWave);
+  const int64_t s = t / kWave;
+  const int64_t row = A.row0 + t;
+  if (s >= A.nslices || row >= A.n) return;
+  const int lane = (int)(t % kWave);
   const int64_t base = A.slice_ptr[s];
   const int width = (int)((A.slice_ptr[s + 1] - base) / kWave);
   double asum = 0.0;
@@ -141,10 +192,8 @@ template <bool USER_D>
 __global__ void __launch_bounds__(kAux) k_step64(SolveArgs a, const double* P, const double* R, double beta,
                                                  int bz, double* W) {
   __shared__ double sh[3][kAux / kWave];
-  const int lane = threadIdx.x % kWave;
-  const WaveRange wr = wave_range<kAux>(a.A.nslices, a.nxcd);
   double p0 = 0.0, p1 = 0.0, p2 = 0.0;
-  for (int64_t s = wr.first; s < wr.end; s += wr.step) iter_slice<USER_D>(a, s, lane, P, R, W, beta, bz != 0, p0, p1, p2);
+  pass_iter64<USER_D, kAux>(a, P, R, W, beta, bz != 0, p0, p1, p2);
   block_sum3<kAux>(p0, p1, p2, sh);
   if (threadIdx.x == 0) {
     double* slot = a.part + (size_t)blockIdx.x * kPartStride;
@@ -157,10 +206,8 @@ __global__ void __launch_bounds__(kAux) k_step64(SolveArgs a, const double* P, c
 __global__ void __launch_bounds__(kAux) k_resid64(Sell A, int nxcd, const double* X, const double* b, double* out,
                                                   double* part) {
   __shared__ double sh[3][kAux / kWave];
-  const int lane = threadIdx.x % kWave;
-  const WaveRange wr = wave_range<kAux>(A.nslices, nxcd);
   double p0 = 0.0, p1 = 0.0, p2 = 0.0;
-  for (int64_t s = wr.first; s < wr.end; s += wr.step) resid_slice(A, s, lane, X, b, out, p0);
+  pass_resid64<kAux>(A, nxcd, X, b, out, p0);
   block_sum3<kAux>(p0, p1, p2, sh);
   if (threadIdx.x == 0) {
     double* slot = part + (size_t)blockIdx.x * kPartStride;
@@ -193,7 +240,16 @@ struct naj_system {
   int32_t* col = nullptr;
   double* val = nullptr;
   float* val32 = nullptr;
-  double* dinv = nullptr;          // caller's D as 1/D, or null
+  double* dinv = nullptr;          // caller's D as 1/D (solver row order), or null
+  // row order: with the irregular layout rows are renumbered by decreasing length
+  int32_t* perm = nullptr;         // solver row i is caller row perm[i]; null = identity
+  double* bperm = nullptr;         // b in solver row order (irregular layout only)
+  int64_t n_long = 0;              // rows handled one wavefront per row
+  int64_t* lrowptr = nullptr;
+  int32_t* lcol = nullptr;
+  double* lval = nullptr;
+  float* lval32 = nullptr;
+  int layout = 0;                  // 0 = slices in caller order; 1 = sorted slices + long rows
   double* vec[3] = {nullptr, nullptr, nullptr};
   float* fvec[4] = {nullptr, nullptr, nullptr, nullptr};   // mixed precision: 3 inner iterates + r32 (lazy)
   double* part = nullptr;          // 3 * max_grid
@@ -241,6 +297,12 @@ void free_system(naj_system* s) {
   (void)hipFree(s->val);
   (void)hipFree(s->val32);
   (void)hipFree(s->dinv);
+  (void)hipFree(s->perm);
+  (void)hipFree(s->bperm);
+  (void)hipFree(s->lrowptr);
+  (void)hipFree(s->lcol);
+  (void)hipFree(s->lval);
+  (void)hipFree(s->lval32);
   for (auto& v : s->vec) (void)hipFree(v);
   for (auto& v : s->fvec) (void)hipFree(v);
   (void)hipFree(s->part);
@@ -300,7 +362,7 @@ naj_status choose_grid(naj_system* s) {
   s->max_grid = (int)std::max<int64_t>(nxcd, std::min<int64_t>(g, want));
   const int small_slices = env_int("NAJ_SMALL_SLICES", 256);
   const int force = env_int("NAJ_MODE", -1);
-  s->mode = s->nslices <= small_slices ? kModeSmall : kModePass;
+  s->mode = s->nslices + s->n_long / 4 <= small_slices ? kModeSmall : kModePass;
   if (force >= 0 && force <= 2) s->mode = force;
   s->grid = s->max_grid;
   if (s->mode == kModeSmall) s->grid = 1;
@@ -365,6 +427,12 @@ Sell sell_of(const naj_system* s) {
   A.val32 = s->val32;
   A.n = s->n;
   A.nslices = s->nslices;
+  A.row0 = s->n_long;
+  A.n_long = s->n_long;
+  A.lrowptr = s->lrowptr;
+  A.lcol = s->lcol;
+  A.lval = s->lval;
+  A.lval32 = s->lval32;
   return A;
 }
 
@@ -427,6 +495,148 @@ naj_status residual_norm2(naj_system* s, const double* x, const double* b, doubl
   return NAJ_OK;
 }
 
+
+
+// Rows longer than this go to the one-wavefront-per-row part of the irregular layout.
+constexpr int kLongRow = 128;
+
+// Builds the matrix layout from the caller's (validated) device CSR.  Regular
+// matrices keep the caller's row order in 64-row slices.  When that would pad
+// the slices heavily (rows of very different lengths, e.g. power-law graphs),
+// rows are renumbered by decreasing length (a symmetric permutation; each
+// row keeps its stored entry order), rows longer than kLongRow are kept as
+// CSR for one-wavefront-per-row processing, and the rest go to slices.
+naj_status build_layout(naj_system* s, const int32_t* rowptr, const int32_t* colidx, const double* vals,
+                        hipStream_t st) {
+  const int64_t n = s->n;
+  std::vector<int32_t> hrp(n + 1);
+  HIP_TRY(hipMemcpyAsync(hrp.data(), rowptr, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  int64_t plain_stored = 0;
+  int maxlen = 0;
+  for (int64_t sl = 0; sl * kWave < n; ++sl) {
+    int w = 0;
+    for (int64_t r = sl * kWave; r < std::min<int64_t>(n, (sl + 1) * kWave); ++r) w = std::max(w, hrp[r + 1] - hrp[r]);
+    plain_stored += (int64_t)w * kWave;
+    maxlen = std::max(maxlen, w);
+  }
+  int layout = plain_stored > (int64_t)(1.3 * (double)std::max<int64_t>(s->nnz, n)) ? 1 : 0;
+  const int forced = env_int("NAJ_LAYOUT", -1);
+  if (forced == 0 || forced == 1) layout = forced;
+  s->layout = layout;
+
+  const int32_t* src_rp = rowptr;
+  const int32_t* src_col = colidx;
+  const double* src_val = vals;
+  int64_t* new_rp_d = nullptr;
+  int32_t* tmp_col = nullptr;
+  double* tmp_val = nullptr;
+  int32_t* tmp_rp32 = nullptr;
+  std::vector<int32_t> hrp2;
+  naj_status rc = NAJ_OK;
+  if (layout == 1) {
+    // counting sort by decreasing length (stable)
+    std::vector<int64_t> cnt((size_t)maxlen + 2, 0);
+    for (int64_t r = 0; r < n; ++r) cnt[(size_t)(maxlen - (hrp[r + 1] - hrp[r]))] += 1;
+    int64_t acc = 0;
+    for (auto& c : cnt) {
+      const int64_t t = c;
+      c = acc;
+      acc += t;
+    }
+    std::vector<int32_t> perm(n), iperm(n);
+    for (int64_t r = 0; r < n; ++r) {
+      const int64_t pos = cnt[(size_t)(maxlen - (hrp[r + 1] - hrp[r]))]++;
+      perm[pos] = (int32_t)r;
+      iperm[r] = (int32_t)pos;
+    }
+    std::vector<int64_t> nrp(n + 1);
+    nrp[0] = 0;
+    int64_t nlong = 0;
+    for (int64_t i = 0; i < n; ++i) {
+      const int len = hrp[perm[i] + 1] - hrp[perm[i]];
+      nrp[i + 1] = nrp[i] + len;
+      if (len > kLongRow) nlong = i + 1;
+    }
+    s->n_long = nlong;
+    hrp2.resize(n + 1);
+    for (int64_t i = 0; i <= n; ++i) hrp2[i] = (int32_t)nrp[i];
+    int32_t* iperm_d = nullptr;
+    rc = dev_alloc(s, &s->perm, (size_t)n);
+    if (rc != NAJ_OK) return rc;
+    HIP_TRY(hipMalloc((void**)&iperm_d, sizeof(int32_t) * n));
+    HIP_TRY(hipMalloc((void**)&new_rp_d, sizeof(int64_t) * (n + 1)));
+    HIP_TRY(hipMalloc((void**)&tmp_rp32, sizeof(int32_t) * (n + 1)));
+    HIP_TRY(hipMalloc((void**)&tmp_col, sizeof(int32_t) * std::max<int64_t>(1, s->nnz)));
+    HIP_TRY(hipMalloc((void**)&tmp_val, sizeof(double) * std::max<int64_t>(1, s->nnz)));
+    HIP_TRY(hipMemcpyAsync(s->perm, perm.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(iperm_d, iperm.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(new_rp_d, nrp.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(tmp_rp32, hrp2.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_permute_rows, dim3(blocks_for(n * kWave, kAux)), dim3(kAux), 0, st, rowptr, colidx, vals, n,
+                       s->perm, iperm_d, new_rp_d, tmp_col, tmp_val);
+    HIP_TRY(hipGetLastError());
+    if (s->dinv) {   // caller's diagonal into solver order
+      double* t = nullptr;
+      HIP_TRY(hipMalloc((void**)&t, sizeof(double) * n));
+      hipLaunchKernelGGL(k_gather, dim3(blocks_for(n, kAux)), dim3(kAux), 0, st, s->dinv, s->perm, t, n);
+      HIP_TRY(hipGetLastError());
+      HIP_TRY(hipMemcpyAsync(s->dinv, t, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      (void)hipFree(t);
+    }
+    // long rows: the prefix of the renumbered CSR
+    const int64_t lnnz = nrp[nlong];
+    rc = dev_alloc(s, &s->lrowptr, (size_t)nlong + 1);
+    if (rc == NAJ_OK) rc = dev_alloc(s, &s->lcol, (size_t)lnnz);
+    if (rc == NAJ_OK) rc = dev_alloc(s, &s->lval, (size_t)lnnz);
+    if (rc == NAJ_OK) rc = dev_alloc(s, &s->lval32, (size_t)lnnz);
+    if (rc == NAJ_OK) rc = dev_alloc(s, &s->bperm, (size_t)n);
+    if (rc != NAJ_OK) return rc;
+    HIP_TRY(hipMemcpyAsync(s->lrowptr, nrp.data(), sizeof(int64_t) * (nlong + 1), hipMemcpyHostToDevice, st));
+    if (lnnz > 0) {
+      HIP_TRY(hipMemcpyAsync(s->lcol, tmp_col, sizeof(int32_t) * lnnz, hipMemcpyDeviceToDevice, st));
+      HIP_TRY(hipMemcpyAsync(s->lval, tmp_val, sizeof(double) * lnnz, hipMemcpyDeviceToDevice, st));
+      hipLaunchKernelGGL(k_to_float, dim3(blocks_for(lnnz, kAux)), dim3(kAux), 0, st, s->lval, s->lval32, lnnz);
+      HIP_TRY(hipGetLastError());
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    (void)hipFree(iperm_d);
+    src_rp = tmp_rp32;
+    src_col = tmp_col;
+    src_val = tmp_val;
+  }
+  // slices over rows [n_long, n)
+  const int64_t row0 = s->n_long;
+  s->nslices = (n - row0 + kWave - 1) / kWave;
+  const std::vector<int32_t>& rp = layout == 1 ? hrp2 : hrp;
+  std::vector<int64_t> hp(s->nslices + 1);
+  hp[0] = 0;
+  for (int64_t sl = 0; sl < s->nslices; ++sl) {
+    int w = 0;
+    for (int64_t r = row0 + sl * kWave; r < std::min<int64_t>(n, row0 + (sl + 1) * kWave); ++r)
+      w = std::max(w, rp[r + 1] - rp[r]);
+    hp[sl + 1] = hp[sl] + (int64_t)w * kWave;
+  }
+  s->stored = hp[s->nslices] + (layout == 1 ? (int64_t)rp[row0] : 0);
+  rc = dev_alloc(s, &s->slice_ptr, (size_t)s->nslices + 1);
+  if (rc == NAJ_OK) rc = dev_alloc(s, &s->col, (size_t)hp[s->nslices]);
+  if (rc == NAJ_OK) rc = dev_alloc(s, &s->val, (size_t)hp[s->nslices]);
+  if (rc == NAJ_OK) rc = dev_alloc(s, &s->val32, (size_t)hp[s->nslices]);
+  if (rc != NAJ_OK) return rc;
+  HIP_TRY(hipMemcpyAsync(s->slice_ptr, hp.data(), sizeof(int64_t) * (s->nslices + 1), hipMemcpyHostToDevice, st));
+  if (s->nslices > 0) {
+    hipLaunchKernelGGL(k_sell_fill, dim3(blocks_for(s->nslices * kWave, kAux)), dim3(kAux), 0, st, src_rp, src_col,
+                       src_val, row0, n, s->nslices, s->slice_ptr, s->col, s->val, s->val32);
+    HIP_TRY(hipGetLastError());
+  }
+  HIP_TRY(hipStreamSynchronize(st));
+  if (new_rp_d) (void)hipFree(new_rp_d);
+  if (tmp_rp32) (void)hipFree(tmp_rp32);
+  if (tmp_col) (void)hipFree(tmp_col);
+  if (tmp_val) (void)hipFree(tmp_val);
+  return NAJ_OK;
+}
 
 // Runs the solve kernels on `st` for the prepared control block; ev0/ev1 bracket them.
 naj_status run_solve(naj_system* s, SolveArgs& a, const naj_opts& o, hipStream_t st) {
@@ -511,10 +721,7 @@ naj_status naj_create_system(int64_t n, int64_t nnz, const int32_t* rowptr, cons
   naj_system* s = new naj_system();
   naj_status rc = NAJ_OK;
   int* flag = nullptr;
-  int32_t* width = nullptr;
   int hflag = 0;
-  std::vector<int32_t> hw;
-  std::vector<int64_t> hp;
 #define STEP(x)              \
   do {                       \
     rc = (x);                \
@@ -531,7 +738,6 @@ naj_status naj_create_system(int64_t n, int64_t nnz, const int32_t* rowptr, cons
   HSTEP(hipGetDevice(&s->device));
   s->n = n;
   s->nnz = nnz;
-  s->nslices = (n + kWave - 1) / kWave;
   HSTEP(hipMalloc((void**)&flag, sizeof(int)));
   HSTEP(hipMemsetAsync(flag, 0, sizeof(int), st));
   hipLaunchKernelGGL(k_check_rowptr, dim3(blocks_for(n, kAux)), dim3(kAux), 0, st, rowptr, n, nnz, flag);
@@ -560,26 +766,7 @@ naj_status naj_create_system(int64_t n, int64_t nnz, const int32_t* rowptr, cons
               "32 value not finite)", hflag);
     goto bad;
   }
-  // sliced-row layout
-  HSTEP(hipMalloc((void**)&width, sizeof(int32_t) * s->nslices));
-  hipLaunchKernelGGL(k_slice_width, dim3(blocks_for(s->nslices * kWave, kAux)), dim3(kAux), 0, st, rowptr, n,
-                     s->nslices, width);
-  HSTEP(hipGetLastError());
-  hw.resize(s->nslices);
-  HSTEP(hipMemcpyAsync(hw.data(), width, sizeof(int32_t) * s->nslices, hipMemcpyDeviceToHost, st));
-  HSTEP(hipStreamSynchronize(st));
-  hp.resize(s->nslices + 1);
-  hp[0] = 0;
-  for (int64_t i = 0; i < s->nslices; ++i) hp[i + 1] = hp[i] + (int64_t)hw[i] * kWave;
-  s->stored = hp[s->nslices];
-  STEP(dev_alloc(s, &s->slice_ptr, (size_t)s->nslices + 1));
-  STEP(dev_alloc(s, &s->col, (size_t)s->stored));
-  STEP(dev_alloc(s, &s->val, (size_t)s->stored));
-  STEP(dev_alloc(s, &s->val32, (size_t)s->stored));
-  HSTEP(hipMemcpyAsync(s->slice_ptr, hp.data(), sizeof(int64_t) * (s->nslices + 1), hipMemcpyHostToDevice, st));
-  hipLaunchKernelGGL(k_sell_fill, dim3(blocks_for(s->nslices * kWave, kAux)), dim3(kAux), 0, st, rowptr, colidx,
-                     vals, n, s->nslices, s->slice_ptr, s->col, s->val, s->val32);
-  HSTEP(hipGetLastError());
+  STEP(build_layout(s, rowptr, colidx, vals, st));
   STEP(choose_grid(s));
   for (auto& v : s->vec) STEP(dev_alloc(s, &v, (size_t)n));
   STEP(dev_alloc(s, &s->part, (size_t)kPartStride * s->max_grid));
@@ -595,12 +782,10 @@ naj_status naj_create_system(int64_t n, int64_t nnz, const int32_t* rowptr, cons
   HSTEP(hipHostMalloc((void**)&s->hflag, 2 * sizeof(int), hipHostMallocDefault));
   HSTEP(hipStreamSynchronize(st));
   (void)hipFree(flag);
-  (void)hipFree(width);
   *out = s;
   return NAJ_OK;
 bad:
   if (flag) (void)hipFree(flag);
-  if (width) (void)hipFree(width);
   free_system(s);
   return rc;
 #undef STEP
@@ -619,7 +804,7 @@ naj_status naj_system_info(const naj_system* s, int64_t* n, int64_t* nnz, int64_
   if (n) *n = s->n;
   if (nnz) *nnz = s->nnz;
   if (device_bytes) *device_bytes = s->bytes;
-  if (layout) *layout = 0;
+  if (layout) *layout = s->layout;
   if (stored_entries) *stored_entries = s->stored;
   return NAJ_OK;
 }
@@ -647,11 +832,22 @@ naj_status naj_solve(naj_system* s, const double* b, const double* x0, const naj
       if (rc != NAJ_OK) return rc;
     }
   }
-  if (x0) HIP_TRY(hipMemcpyAsync(s->vec[0], x0, sizeof(double) * s->n, hipMemcpyDeviceToDevice, st));
-  else HIP_TRY(hipMemsetAsync(s->vec[0], 0, sizeof(double) * s->n, st));
+  const double* b_in = b;
+  if (s->perm) {   // into the solver's row order
+    hipLaunchKernelGGL(k_gather, dim3(blocks_for(s->n, kAux * 4)), dim3(kAux), 0, st, b, s->perm, s->bperm, s->n);
+    HIP_TRY(hipGetLastError());
+    b_in = s->bperm;
+    if (x0) {
+      hipLaunchKernelGGL(k_gather, dim3(blocks_for(s->n, kAux * 4)), dim3(kAux), 0, st, x0, s->perm, s->vec[0], s->n);
+      HIP_TRY(hipGetLastError());
+    }
+  } else if (x0) {
+    HIP_TRY(hipMemcpyAsync(s->vec[0], x0, sizeof(double) * s->n, hipMemcpyDeviceToDevice, st));
+  }
+  if (!x0) HIP_TRY(hipMemsetAsync(s->vec[0], 0, sizeof(double) * s->n, st));
   hipLaunchKernelGGL(k_solve_init, dim3(1), dim3(64), 0, st, s->ctrl, s->bar, s->counters, o.k0);
   HIP_TRY(hipGetLastError());
-  SolveArgs a = make_args(s, b, o);
+  SolveArgs a = make_args(s, b_in, o);
   if (!hist) a.hist = nullptr, a.hist_cap = 0;
   else a.hist_cap = std::min(hist_cap, s->hist_cap_dev);
   if (!trace) a.trace = nullptr, a.trace_cap = 0;
@@ -659,7 +855,7 @@ naj_status naj_solve(naj_system* s, const double* b, const double* x0, const naj
   rc = run_solve(s, a, o, st);
   if (rc != NAJ_OK) return rc;
   hipLaunchKernelGGL(k_copy_result, dim3(blocks_for(s->n, kAux * 4)), dim3(kAux), 0, st, s->ctrl, s->vec[0],
-                     s->vec[1], s->vec[2], x, s->n);
+                     s->vec[1], s->vec[2], x, s->perm, s->n);
   HIP_TRY(hipGetLastError());
   Ctrl hc;
   HIP_TRY(hipMemcpyAsync(&hc, s->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
@@ -694,9 +890,9 @@ naj_status naj_solve(naj_system* s, const double* b, const double* x0, const naj
     res->status = NAJ_EDEVICE;
     return fail(NAJ_EDEVICE, "grid barrier wait timed out inside the solve kernel");
   }
-  if (hc.status == ST_NOT_CONVERGED || hc.status == ST_BREAKDOWN) {
-    double rr = 0.0;
-    rc = residual_norm2(s, x, b, nullptr, &rr, st);
+  if ((hc.status == ST_NOT_CONVERGED || hc.status == ST_BREAKDOWN) && hc.result >= 0 && hc.nb > 0.0) {
+    double rr = 0.0;   // residual of the returned iterate, in the solver's row order
+    rc = residual_norm2(s, s->vec[hc.result], b_in, nullptr, &rr, st);
     if (rc != NAJ_OK) return rc;
     res->relres = std::sqrt(rr) / hc.nb;
   }
@@ -716,11 +912,29 @@ naj_status naj_step(naj_system* s, const double* p, const double* r, double beta
   SolveArgs a = make_args(s, b, o);
   const int G = s->aux_grid;
   const int bz = beta == 0.0 ? 1 : 0;
+  const double* P = p;
+  const double* R = bz ? p : r;
+  double* W = x;
+  if (s->perm) {   // run in the solver's row order
+    const dim3 g1(blocks_for(s->n, kAux * 4)), b1(kAux);
+    hipLaunchKernelGGL(k_gather, g1, b1, 0, st, p, s->perm, s->vec[0], s->n);
+    if (!bz) hipLaunchKernelGGL(k_gather, g1, b1, 0, st, r, s->perm, s->vec[1], s->n);
+    hipLaunchKernelGGL(k_gather, g1, b1, 0, st, b, s->perm, s->bperm, s->n);
+    HIP_TRY(hipGetLastError());
+    P = s->vec[0];
+    R = bz ? s->vec[0] : s->vec[1];
+    W = s->vec[2];
+    a.b = s->bperm;
+  }
   if (s->dinv)
-    hipLaunchKernelGGL(k_step64<true>, dim3(G), dim3(kAux), 0, st, a, p, bz ? p : r, beta, bz, x);
+    hipLaunchKernelGGL(k_step64<true>, dim3(G), dim3(kAux), 0, st, a, P, R, beta, bz, W);
   else
-    hipLaunchKernelGGL(k_step64<false>, dim3(G), dim3(kAux), 0, st, a, p, bz ? p : r, beta, bz, x);
+    hipLaunchKernelGGL(k_step64<false>, dim3(G), dim3(kAux), 0, st, a, P, R, beta, bz, W);
   HIP_TRY(hipGetLastError());
+  if (s->perm) {
+    hipLaunchKernelGGL(k_scatter, dim3(blocks_for(s->n, kAux * 4)), dim3(kAux), 0, st, W, s->perm, x, s->n);
+    HIP_TRY(hipGetLastError());
+  }
   hipLaunchKernelGGL(k_reduce_fixed, dim3(1), dim3(kWave), 0, st, s->part, G, s->scal);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemcpyAsync(red, s->scal, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -731,16 +945,38 @@ naj_status naj_step(naj_system* s, const double* p, const double* r, double beta
 naj_status naj_residual(naj_system* s, const double* x, const double* b, double* out, double* rr, void* stream) {
   g_err.clear();
   if (!s || !x || !b || !rr) return fail(NAJ_EINVAL, "null argument");
-  return residual_norm2(s, x, b, out, rr, (hipStream_t)stream);
+  hipStream_t st = (hipStream_t)stream;
+  if (!s->perm) return residual_norm2(s, x, b, out, rr, st);
+  const dim3 g1(blocks_for(s->n, kAux * 4)), b1(kAux);
+  hipLaunchKernelGGL(k_gather, g1, b1, 0, st, x, s->perm, s->vec[0], s->n);
+  hipLaunchKernelGGL(k_gather, g1, b1, 0, st, b, s->perm, s->bperm, s->n);
+  HIP_TRY(hipGetLastError());
+  naj_status rc = residual_norm2(s, s->vec[0], s->bperm, out ? s->vec[1] : nullptr, rr, st);
+  if (rc != NAJ_OK) return rc;
+  if (out) {
+    hipLaunchKernelGGL(k_scatter, g1, b1, 0, st, s->vec[1], s->perm, out, s->n);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(st));
+  }
+  return NAJ_OK;
 }
 
 naj_status naj_diagonal(naj_system* s, double* out, void* stream) {
   g_err.clear();
   if (!s || !out) return fail(NAJ_EINVAL, "null argument");
   hipStream_t st = (hipStream_t)stream;
-  hipLaunchKernelGGL(k_row_abs_sum, dim3(blocks_for(s->nslices * kWave, kAux)), dim3(kAux), 0, st, sell_of(s),
-                     s->dinv, out);
+  double* dst = s->perm ? s->vec[0] : out;
+  hipLaunchKernelGGL(k_row_abs_sum, dim3(blocks_for(std::max<int64_t>(s->n, s->nslices * kWave), kAux)), dim3(kAux), 0,
+                     st, sell_of(s), s->dinv, dst);
   HIP_TRY(hipGetLastError());
+  if (!s->dinv && s->n_long > 0) {
+    hipLaunchKernelGGL(k_long_abs_sum, dim3(blocks_for(s->n_long * kWave, kAux)), dim3(kAux), 0, st, sell_of(s), dst);
+    HIP_TRY(hipGetLastError());
+  }
+  if (s->perm) {
+    hipLaunchKernelGGL(k_scatter, dim3(blocks_for(s->n, kAux * 4)), dim3(kAux), 0, st, dst, s->perm, out, s->n);
+    HIP_TRY(hipGetLastError());
+  }
   HIP_TRY(hipStreamSynchronize(st));
   return NAJ_OK;
 }

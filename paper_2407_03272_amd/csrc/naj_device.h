@@ -94,6 +94,9 @@ constexpr int kMaxDomains = 8;
 constexpr int kCounterStride = 1024;   // unsigned ints (4 KB)
 constexpr int kCounterWords = (kMaxDomains + 1) * kCounterStride;
 
+// Matrix in the solver's row order.  Rows [0, n_long) are long rows stored as
+// CSR (lrowptr/lcol/lval), one wavefront per row; rows [row0, n) with
+// row0 = n_long are stored in 64-row slices, one lane per row.
 struct Sell {
   const int64_t* slice_ptr;   // [nslices+1]
   const int32_t* col;
@@ -101,6 +104,12 @@ struct Sell {
   const float* val32;
   int64_t n;
   int64_t nslices;
+  int64_t row0;               // first row held by the slices (= n_long)
+  int64_t n_long;
+  const int64_t* lrowptr;     // [n_long+1]
+  const int32_t* lcol;
+  const double* lval;
+  const float* lval32;
 };
 
 struct SolveArgs {
@@ -167,7 +176,7 @@ __device__ __forceinline__ void iter_slice(const SolveArgs& a, int64_t s, int la
                                            bool bz, double& ps, double& pgg, double& psabs) {
   const int64_t base = a.A.slice_ptr[s];
   const int width = (int)((a.A.slice_ptr[s + 1] - base) >> 6);
-  const int64_t row = s * kWave + lane;
+  const int64_t row = a.A.row0 + s * kWave + lane;
   const bool live = row < a.A.n;
   const int64_t rr = live ? row : 0;
   // own-row operands do not depend on the column loop: issue them first
@@ -230,7 +239,7 @@ __device__ __forceinline__ void resid_slice(const Sell& A, int64_t s, int lane, 
                                             const double* __restrict__ b, double* __restrict__ out, double& prr) {
   const int64_t base = A.slice_ptr[s];
   const int width = (int)((A.slice_ptr[s + 1] - base) >> 6);
-  const int64_t row = s * kWave + lane;
+  const int64_t row = A.row0 + s * kWave + lane;
   const bool live = row < A.n;
   const double bi = b[live ? row : 0];
   const int32_t* __restrict__ cp = A.col + base + lane;
@@ -269,7 +278,7 @@ __device__ __forceinline__ void inner_slice(const SolveArgs& a, int64_t s, int l
                                             bool zp, double& ps, double& pgg, double& psabs) {
   const int64_t base = a.A.slice_ptr[s];
   const int width = (int)((a.A.slice_ptr[s + 1] - base) >> 6);
-  const int64_t row = s * kWave + lane;
+  const int64_t row = a.A.row0 + s * kWave + lane;
   const bool live = row < a.A.n;
   const int64_t rr = live ? row : 0;
   const float Pi = zp ? 0.0f : P[rr];
@@ -338,7 +347,7 @@ __device__ __forceinline__ void resid_mixed_slice(const SolveArgs& a, int64_t s,
                                                   double& pr32) {
   const int64_t base = a.A.slice_ptr[s];
   const int width = (int)((a.A.slice_ptr[s + 1] - base) >> 6);
-  const int64_t row = s * kWave + lane;
+  const int64_t row = a.A.row0 + s * kWave + lane;
   const bool live = row < a.A.n;
   const int64_t rr = live ? row : 0;
   const double bi = a.b[rr];
@@ -386,6 +395,147 @@ __device__ __forceinline__ void resid_mixed_slice(const SolveArgs& a, int64_t s,
     pr32 = pr32 + r64 * r64;
   }
 }
+
+// ---------------------------------------------------------------------------
+// Long rows: one wavefront per row.  Lane l adds the row's entries l, l+64,
+// l+128, ... in turn, then the lanes are combined by the xor butterfly: a fixed
+// order (repeatable), though not the row's stored order.
+constexpr int kLongUnroll = 4;
+
+__device__ __forceinline__ float wave_sum_f(float v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// sum_k v_k * y(c_k) and sum_k |v_k| over [s, e); Y maps a column to its (already formed) y value.
+template <typename T, typename VT, typename YF>
+__device__ __forceinline__ void long_row_sums(const int32_t* __restrict__ col, const VT* __restrict__ val, int64_t s,
+                                              int64_t e, int lane, YF yof, T& acc, T& asum) {
+  acc = (T)0;
+  asum = (T)0;
+  for (int64_t k = s + lane; k < e; k += (int64_t)kWave * kLongUnroll) {
+    int c[kLongUnroll];
+    T v[kLongUnroll], y[kLongUnroll];
+#pragma unroll
+    for (int q = 0; q < kLongUnroll; ++q)
+      if (k + q * kWave < e) {
+        c[q] = col[k + q * kWave];
+        v[q] = (T)val[k + q * kWave];
+      }
+#pragma unroll
+    for (int q = 0; q < kLongUnroll; ++q)
+      if (k + q * kWave < e) y[q] = yof(c[q]);
+#pragma unroll
+    for (int q = 0; q < kLongUnroll; ++q)
+      if (k + q * kWave < e) {
+        acc = acc + v[q] * y[q];
+        asum = asum + (v[q] < (T)0 ? -v[q] : v[q]);
+      }
+  }
+}
+
+template <bool USER_D>
+__device__ __forceinline__ void iter_long(const SolveArgs& a, int64_t r, int lane, const double* __restrict__ P,
+                                          const double* __restrict__ R, double* __restrict__ W, double beta, bool bz,
+                                          double& ps, double& pgg, double& psabs) {
+  double acc, asum;
+  const int64_t s = a.A.lrowptr[r], e = a.A.lrowptr[r + 1];
+  if (bz)
+    long_row_sums<double>(a.A.lcol, a.A.lval, s, e, lane, [&](int c) { return P[c]; }, acc, asum);
+  else
+    long_row_sums<double>(a.A.lcol, a.A.lval, s, e, lane,
+                          [&](int c) { const double p = P[c]; return p + beta * (p - R[c]); }, acc, asum);
+  acc = wave_sum(acc);
+  asum = wave_sum(asum);
+  if (lane == 0) {
+    const double Pi = P[r];
+    const double yi = bz ? Pi : Pi + beta * (Pi - R[r]);
+    const double g = acc - a.b[r];
+    const double dv = USER_D ? a.dinv[r] : 1.0 / (asum == 0.0 ? 1.0 : asum);
+    const double xi = yi - dv * g;
+    W[r] = xi;
+    const double dd = xi - Pi;
+    const double gd = g * dd;
+    ps = ps + gd;
+    pgg = pgg + g * g;
+    psabs = psabs + fabs(gd);
+  }
+}
+
+__device__ __forceinline__ void resid_long(const Sell& A, int64_t r, int lane, const double* __restrict__ X,
+                                           const double* __restrict__ b, double* __restrict__ out, double& prr) {
+  double acc, asum;
+  long_row_sums<double>(A.lcol, A.lval, A.lrowptr[r], A.lrowptr[r + 1], lane, [&](int c) { return X[c]; }, acc, asum);
+  acc = wave_sum(acc);
+  if (lane == 0) {
+    const double res = b[r] - acc;
+    if (out) out[r] = res;
+    prr = prr + res * res;
+  }
+}
+
+template <bool USER_D>
+__device__ __forceinline__ void inner_long(const SolveArgs& a, int64_t r, int lane, const float* __restrict__ P,
+                                           const float* __restrict__ R, float* __restrict__ W, float beta, bool bz,
+                                           bool zp, double& ps, double& pgg, double& psabs) {
+  float acc, asum;
+  const int64_t s = a.A.lrowptr[r], e = a.A.lrowptr[r + 1];
+  if (zp)
+    long_row_sums<float>(a.A.lcol, a.A.lval32, s, e, lane, [&](int c) { (void)c; return 0.0f; }, acc, asum);
+  else if (bz)
+    long_row_sums<float>(a.A.lcol, a.A.lval32, s, e, lane, [&](int c) { return P[c]; }, acc, asum);
+  else
+    long_row_sums<float>(a.A.lcol, a.A.lval32, s, e, lane,
+                         [&](int c) { const float p = P[c]; return p + beta * (p - R[c]); }, acc, asum);
+  acc = wave_sum_f(acc);
+  asum = wave_sum_f(asum);
+  if (lane == 0) {
+    const float Pi = zp ? 0.0f : P[r];
+    const float yi = (zp || bz) ? Pi : Pi + beta * (Pi - R[r]);
+    const float g = acc - a.r32[r];
+    const float dv = USER_D ? (float)a.dinv[r] : 1.0f / (asum == 0.0f ? 1.0f : asum);
+    const float xi = yi - dv * g;
+    W[r] = xi;
+    const float dd = xi - Pi;
+    const double g64 = (double)g, d64 = (double)dd;
+    const double gd = g64 * d64;
+    ps = ps + gd;
+    pgg = pgg + g64 * g64;
+    psabs = psabs + fabs(gd);
+  }
+}
+
+__device__ __forceinline__ void resid_mixed_long(const SolveArgs& a, int64_t r, int lane, const double* __restrict__ X,
+                                                 const float* __restrict__ D, double* __restrict__ Xn, double& prr,
+                                                 double& pr32) {
+  double acc, asum;
+  const int64_t s = a.A.lrowptr[r], e = a.A.lrowptr[r + 1];
+  if (D)
+    long_row_sums<double>(a.A.lcol, a.A.lval, s, e, lane, [&](int c) { return X[c] + (double)D[c]; }, acc, asum);
+  else
+    long_row_sums<double>(a.A.lcol, a.A.lval, s, e, lane, [&](int c) { return X[c]; }, acc, asum);
+  acc = wave_sum(acc);
+  if (lane == 0) {
+    if (D) Xn[r] = X[r] + (double)D[r];
+    const double res = a.b[r] - acc;
+    const float r32 = (float)res;
+    a.r32[r] = r32;
+    prr = prr + res * res;
+    const double r64 = (double)r32;
+    pr32 = pr32 + r64 * r64;
+  }
+}
+
+// Long rows handed out round-robin over every wave of the grid (heaviest first).
+template <int BS>
+struct LongRange {
+  int64_t first, step;
+  __device__ __forceinline__ LongRange() {
+    first = (int64_t)blockIdx.x * (BS / kWave) + wave_id();
+    step = (int64_t)gridDim.x * (BS / kWave);
+  }
+};
 
 // Sum three per-thread values over the workgroup in a fixed order; result valid in thread 0.
 template <int BS>

@@ -263,41 +263,61 @@ __device__ __forceinline__ void load_view(const Ctrl* c, PassView* v) {
   v->update = c->update;
 }
 
+// The workgroup's share of one float64 iteration pass (long rows, then slices).
+template <bool USER_D, int BS>
+__device__ __forceinline__ void pass_iter64(const SolveArgs& a, const double* P, const double* R, double* W,
+                                            double beta, bool bz, double& p0, double& p1, double& p2) {
+  const int lane = threadIdx.x % kWave;
+  const LongRange<BS> lr;
+  for (int64_t r = lr.first; r < a.A.n_long; r += lr.step) iter_long<USER_D>(a, r, lane, P, R, W, beta, bz, p0, p1, p2);
+  const WaveRange wr = wave_range<BS>(a.A.nslices, a.nxcd);
+  for (int64_t s = wr.first; s < wr.end; s += wr.step) iter_slice<USER_D>(a, s, lane, P, R, W, beta, bz, p0, p1, p2);
+}
+
+// The workgroup's share of r = b - Q X (float64); ||r||^2 in p0.
+template <int BS>
+__device__ __forceinline__ void pass_resid64(const Sell& A, int nxcd, const double* X, const double* b, double* out,
+                                             double& p0) {
+  const int lane = threadIdx.x % kWave;
+  const LongRange<BS> lr;
+  for (int64_t r = lr.first; r < A.n_long; r += lr.step) resid_long(A, r, lane, X, b, out, p0);
+  const WaveRange wr = wave_range<BS>(A.nslices, nxcd);
+  for (int64_t s = wr.first; s < wr.end; s += wr.step) resid_slice(A, s, lane, X, b, out, p0);
+}
+
 // The workgroup's share of one pass; partial sums in p0..p2 (per thread).
 template <bool USER_D, int BS>
 __device__ __forceinline__ void run_pass(const SolveArgs& a, const PassView& v, double& p0, double& p1,
                                          double& p2) {
   const int lane = threadIdx.x % kWave;
-  const WaveRange wr = wave_range<BS>(a.A.nslices, a.nxcd);
   if (v.phase == PH_ITER) {
-    const double* P = pick(a, v.iP);
-    const double* R = pick(a, v.iR);
-    double* W = pick(a, v.iW);
-    const bool bz = v.bz != 0;
-    for (int64_t s = wr.first; s < wr.end; s += wr.step) iter_slice<USER_D>(a, s, lane, P, R, W, v.beta, bz, p0, p1, p2);
+    pass_iter64<USER_D, BS>(a, pick(a, v.iP), pick(a, v.iR), pick(a, v.iW), v.beta, v.bz != 0, p0, p1, p2);
   } else if (v.phase == PH_CONFIRM) {
-    const double* X = pick(a, v.iW);
-    for (int64_t s = wr.first; s < wr.end; s += wr.step) resid_slice(a.A, s, lane, X, a.b, nullptr, p0);
+    pass_resid64<BS>(a.A, a.nxcd, pick(a, v.iW), a.b, nullptr, p0);
   } else if (v.phase == PH_INNER32) {
     const float* P = pickf(a, v.iP);
     const float* R = pickf(a, v.iR);
     float* W = pickf(a, v.iW);
     const float beta = (float)v.beta;
     const bool bz = v.bz != 0, zp = v.zp != 0;
+    const LongRange<BS> lr;
+    for (int64_t r = lr.first; r < a.A.n_long; r += lr.step)
+      inner_long<USER_D>(a, r, lane, P, R, W, beta, bz, zp, p0, p1, p2);
+    const WaveRange wr = wave_range<BS>(a.A.nslices, a.nxcd);
     for (int64_t s = wr.first; s < wr.end; s += wr.step)
       inner_slice<USER_D>(a, s, lane, P, R, W, beta, bz, zp, p0, p1, p2);
   } else if (v.phase == PH_RESID64) {
     const double* X = pick(a, v.iX);
     const float* D = v.update ? pickf(a, v.iD) : nullptr;
     double* Xn = v.update ? pick(a, v.iXn) : nullptr;
+    const LongRange<BS> lr;
+    for (int64_t r = lr.first; r < a.A.n_long; r += lr.step) resid_mixed_long(a, r, lane, X, D, Xn, p0, p1);
+    const WaveRange wr = wave_range<BS>(a.A.nslices, a.nxcd);
     for (int64_t s = wr.first; s < wr.end; s += wr.step) resid_mixed_slice(a, s, lane, X, D, Xn, p0, p1);
-  } else {  // PH_NORMB
-    for (int64_t s = wr.first; s < wr.end; s += wr.step) {
-      const int64_t row = s * kWave + lane;
-      if (row < a.A.n) {
-        const double x = a.b[row];
-        p0 = p0 + x * x;
-      }
+  } else {  // PH_NORMB: every row, flat
+    for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < a.A.n; i += (int64_t)gridDim.x * BS) {
+      const double x = a.b[i];
+      p0 = p0 + x * x;
     }
   }
 }
@@ -481,12 +501,13 @@ __global__ void k_solve_init(Ctrl* c, Barrier* bar, unsigned int* counters, int 
 }
 
 // Copies the buffer the control block names as the answer into x (zeros for -1).
+// With perm (irregular layout) the solver's row i is the caller's row perm[i].
 __global__ void k_copy_result(const Ctrl* c, const double* b0, const double* b1, const double* b2, double* x,
-                              int64_t n) {
+                              const int32_t* perm, int64_t n) {
   const int r = c->result;
   const double* src = r == 0 ? b0 : (r == 1 ? b1 : b2);
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    x[i] = r < 0 ? 0.0 : src[i];
+    x[perm ? perm[i] : i] = r < 0 ? 0.0 : src[i];
 }
 
 // Copies the phase word (for the host's stop check) into a small host-visible slot.

@@ -294,3 +294,72 @@ def test_full_size_solve_matches_stored_oracle_run(naj, c2):
     Q = O.csr(c2.rowptr, c2.colidx, c2.vals)
     rel = np.linalg.norm(c2.b - Q @ xg) / np.linalg.norm(c2.b)
     assert rel <= 1e-8 and rel == pytest.approx(info.relres, rel=1e-6)
+
+
+# --------------------------------------------------------------------------- irregular rows (sorted layout)
+
+def test_irregular_layout_chung_lu(naj):
+    """Power-law Chung-Lu Laplacian (n = 2^15, mean degree 16, max degree ~700): rows renumbered by decreasing
+    length, rows longer than 128 processed one wavefront per row.  Iterates within 1e-10 of the oracle (long
+    rows sum in a different order, so not bit-identical); the step, residual and diagonal kernels too."""
+    _say("irregular chung-lu 2^15")
+    s = W.chung_lu_laplacian(1 << 15, 16, 2.5, seed=81, b_seed=82)
+    sysm = naj.System(s.rowptr, s.colidx, s.vals)
+    info = sysm.info()
+    assert info["layout"] == 1
+    assert info["stored_entries"] <= 1.05 * s.nnz
+    _compare_solve(naj, sysm, s.rowptr, s.colidx, s.vals, s.b, tol=1e-8, max_iter=20000)
+    rng = np.random.default_rng(5)
+    p, r = rng.standard_normal(s.n), rng.standard_normal(s.n)
+    x, (s_, gg, sabs) = sysm.step(p, r, 0.3, s.b)
+    xo, so, ggo, sabso = O.fused_step(s.rowptr, s.colidx, s.vals, p, r, 0.3, s.b)
+    np.testing.assert_allclose(x.cpu().numpy(), xo, rtol=1e-12, atol=1e-12 * np.abs(xo).max())
+    assert gg == pytest.approx(ggo, rel=1e-12)
+    J = sysm.diagonal().cpu().numpy()
+    np.testing.assert_allclose(J, O.jacobi_diagonal(O.csr(s.rowptr, s.colidx, s.vals)), rtol=1e-14)
+    res, rr = sysm.residual(p, s.b, want_vector=True)
+    ref = s.b - O.csr(s.rowptr, s.colidx, s.vals) @ p
+    np.testing.assert_allclose(res.cpu().numpy(), ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+
+
+def test_sorted_layout_forced_on_regular_rows_is_bitwise(naj, monkeypatch):
+    """The renumbering keeps each row's stored order, so with no long rows the result is bit-identical."""
+    _say("forced sorted layout, poisson 2d")
+    monkeypatch.setenv("NAJ_LAYOUT", "1")
+    s = W.poisson2d_64()
+    sysm = naj.System(s.rowptr, s.colidx, s.vals)
+    monkeypatch.delenv("NAJ_LAYOUT")
+    assert sysm.info()["layout"] == 1
+    _compare_solve(naj, sysm, s.rowptr, s.colidx, s.vals, s.b, tol=1e-8, max_iter=20000, bitwise=True)
+    x0 = np.random.default_rng(2).standard_normal(s.n)
+    _compare_solve(naj, sysm, s.rowptr, s.colidx, s.vals, s.b, x0=x0, tol=1e-8, max_iter=20000, bitwise=True)
+
+
+def test_sorted_layout_all_rows_long(naj, monkeypatch):
+    """Section 4.1 system with every row long (n = 600 > 128 entries per row): all rows one wavefront each."""
+    _say("forced sorted layout, SDD n=600")
+    monkeypatch.setenv("NAJ_LAYOUT", "1")
+    s = W.sdd_system(600)
+    sysm = naj.System(s.rowptr, s.colidx, s.vals)
+    monkeypatch.delenv("NAJ_LAYOUT")
+    ref = O.sdd_scalar_run(600, tol=1e-8)
+    x, info = sysm.solve(s.b, tol=1e-8, max_iter=5000)
+    assert info.iterations == ref["iterations"] and info.restart_log == ref["restarts"]
+    assert np.abs(x.cpu().numpy() - float(ref["xi"][-1])).max() <= 1e-10
+
+
+def test_irregular_user_diagonal_and_mixed(naj):
+    _say("irregular: user D + mixed")
+    s = W.chung_lu_laplacian(1 << 14, 16, 2.5, seed=91, b_seed=92)
+    J = O.jacobi_diagonal(O.csr(s.rowptr, s.colidx, s.vals))
+    sysd = naj.System(s.rowptr, s.colidx, s.vals, D=1.2 * J)
+    _compare_solve(naj, sysd, s.rowptr, s.colidx, s.vals, s.b, D=1.2 * J, tol=1e-8, max_iter=20000)
+    sysm = naj.System(s.rowptr, s.colidx, s.vals)
+    x, info = sysm.solve(s.b, precision=naj.NAJ_MIXED, trace=True, hist_cap=64)
+    m = O.accelerated_jacobi_mixed(s.rowptr, s.colidx, s.vals, s.b, tol=1e-8)
+    assert info.status == 0 and m.status == 0
+    Q = O.csr(s.rowptr, s.colidx, s.vals)
+    xg = x.cpu().numpy()
+    assert np.linalg.norm(s.b - Q @ xg) / np.linalg.norm(s.b) <= 1e-8
+    # long rows sum in another order, so refinement steps may differ by one at most
+    assert abs(info.confirmations - m.outer) <= 1
