@@ -65,6 +65,22 @@ def bytes_per_residual(n: int, nnz: int) -> int:
     return 12 * nnz + 4 * (n + 1) + 2 * 8 * n
 
 
+def bytes_per_refinement_residual(n: int, nnz: int) -> int:
+    """Float64 residual pass of the mixed loop with the update fused: matrix, row pointers, read x (f64), d (f32)
+    and b, write x + d (f64) and fl32(r) (f32)."""
+    return 12 * nnz + 4 * (n + 1) + 8 * n + 4 * n + 8 * n + 8 * n + 4 * n
+
+
+def solve_bytes(n: int, nnz: int, info, mixed: bool) -> int:
+    """Algorithmic bytes of a whole solve from its pass counts (norm of b = 8n bytes)."""
+    if not mixed:
+        it = info.iterations
+        conf = info.passes - it - 1
+        return 8 * n + it * bytes_per_iteration(n, nnz) + conf * bytes_per_residual(n, nnz)
+    return (8 * n + info.iterations * bytes_per_iteration(n, nnz, s_v=4, s_x=4)
+            + info.confirmations * bytes_per_refinement_residual(n, nnz))
+
+
 def make_workload(name: str):
     from paper_2407_03272_amd import workloads as W
     if name == "laplace3d_128":
@@ -73,6 +89,8 @@ def make_workload(name: str):
         return W.poisson_system((160, 160, 160), 1006, name="laplace3d_160")
     if name == "poisson2d_64":
         return W.poisson2d_64()
+    if name == "chunglu_4m":
+        return W.chung_lu_laplacian()
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -101,6 +119,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="laplace3d_128")
     ap.add_argument("--cpu-sample-iters", type=int, default=200)
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--no-compare", action="store_true", help="skip the second-precision comparison solves")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pmc-sample", action="store_true",
                     help="run only a 1 GiB torch copy (counter calibration) and a 50-iteration solve, for rocprofv3 --pmc")
@@ -113,8 +133,12 @@ def main():
     import torch
     from paper_2407_03272_amd import naj
 
+    def progress(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
     sysobj = make_workload(args.workload)
     n, nnz = sysobj.n, sysobj.nnz
+    progress(f"workload {sysobj.name}: n={n} nnz={nnz}")
     dev = torch.device("cuda:0")
     if args.pmc_sample:
         src = torch.ones(1 << 27, dtype=torch.float64, device=dev)     # 1 GiB
@@ -130,34 +154,43 @@ def main():
     sysm = naj.System(sysobj.rowptr, sysobj.colidx, sysobj.vals, device="cuda:0")
     b = torch.as_tensor(sysobj.b).to(dev)
     x = torch.empty(n, dtype=torch.float64, device=dev)
-    opts = dict(tol=1e-8, max_iter=20000)
+    mixed = args.precision == "mixed"
 
-    for _ in range(args.warmup):
-        sysm.solve(b, out=x, hist_cap=0, **opts)
-    torch.cuda.synchronize()
+    def timed(mixed_: bool, steps: int, warmup: int):
+        opts = dict(tol=1e-8, max_iter=20000, precision=naj.NAJ_MIXED if mixed_ else naj.NAJ_FP64)
+        for _ in range(warmup):
+            sysm.solve(b, out=x, hist_cap=0, **opts)
+        torch.cuda.synchronize()
+        lat, kms, infos = [], [], []
+        t_start = time.perf_counter()
+        for _ in range(steps):
+            t0 = time.perf_counter()
+            _, info = sysm.solve(b, out=x, hist_cap=64 if mixed_ else 0, **opts)
+            lat.append(time.perf_counter() - t0)
+            kms.append(info.kernel_ms)
+            infos.append(info)
+            if info.status != 0:
+                raise SystemExit(f"solve did not converge: status {info.status}")
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t_start
+        return total, lat, kms, infos
 
-    lat, kms, iters, passes = [], [], [], []
-    t_start = time.perf_counter()
-    for _ in range(args.steps):
-        t0 = time.perf_counter()
-        _, info = sysm.solve(b, out=x, hist_cap=0, **opts)
-        lat.append(time.perf_counter() - t0)
-        kms.append(info.kernel_ms)
-        iters.append(info.iterations)
-        passes.append(info.passes)
-        if info.status != 0:
-            raise SystemExit(f"solve did not converge: status {info.status}")
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t_start
-
-    it = iters[-1]
-    conf = passes[-1] - it - 1
-    # every pass of a solve: norm of b (8n bytes), the iterations, the residual confirmations.  The
-    # HIP events bracket all launches of a solve (the trailing launches that return at once included).
-    alg_bytes = 8 * n + it * bytes_per_iteration(n, nnz) + conf * bytes_per_residual(n, nnz)
+    progress("system created")
+    total, lat, kms, infos = timed(mixed, args.steps, args.warmup)
+    progress(f"timed {args.steps} solves: {total / args.steps * 1e3:.2f} ms each")
+    info = infos[-1]
+    alg_bytes = solve_bytes(n, nnz, info, mixed)
     kernel_s = float(np.mean(kms)) / 1e3
     achieved = alg_bytes / kernel_s / 1e9
     solves_s = args.steps / total
+    if mixed:
+        per_launch = bytes_per_iteration(n, nnz, s_v=4, s_x=4)
+        wl = (f"{sysobj.name}: n={n}, nnz={nnz}; float32 inner accelerated Jacobi with float64 reductions inside "
+              f"float64 iterative refinement, x0=0, restart on, K0=2, inner tol 1e-4, final relres <= 1e-8, single solve")
+    else:
+        per_launch = bytes_per_iteration(n, nnz)
+        wl = (f"{sysobj.name}: n={n}, nnz={nnz}, float64, x0=0, restart on, K0=2, tol 1e-8, single solve "
+              f"(plain FP64 one system at a time)")
     line = {
         "metric": "solves/s + HBM GB/s at relres 1e-8 vs plain FP64; p50/p99 solve latency",
         "value": solves_s,
@@ -169,24 +202,38 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+f64" if mixed else "f64",
         "data": "synthetic",
-        "config": {"workload": f"{sysobj.name}: float64 Laplacian, n={n}, nnz={nnz}, b=Q x*, x*~N(0,1), "
-                               f"x0=0, restart on, K0=2, tol 1e-8, single solve (plain FP64 one system at a time)",
-                   "n": n, "nnz": nnz, "precision": "fp64", "tol": 1e-8, "iterations": it,
-                   "restarts": info.restarts, "confirmations": conf, "grid": info.grid},
+        "config": {"workload": wl, "n": n, "nnz": nnz, "precision": args.precision, "tol": 1e-8,
+                   "iterations": info.iterations, "restarts": info.restarts, "confirmations": info.confirmations,
+                   "passes": info.passes, "grid": info.grid, "relres": info.relres,
+                   "layout": sysm.info()["layout"]},
         "p50_ms": float(np.percentile(lat, 50) * 1e3),
         "p99_ms": float(np.percentile(lat, 99) * 1e3),
         "kernel_ms": float(np.mean(kms)),
+        "gbps_solve": achieved,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload),
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None if mixed else measured_traffic(args.workload),
                      "kernel": "k_pass64 (fused iteration pass, one launch per pass)",
-                     "launches_per_solve": passes[-1],
-                     "algorithmic_bytes_per_launch": bytes_per_iteration(n, nnz),
-                     "mean_launch_us": kernel_s / passes[-1] * 1e6},
+                     "launches_per_solve": info.passes,
+                     "algorithmic_bytes_per_launch": per_launch,
+                     "mean_launch_us": kernel_s / info.passes * 1e6},
     }
+    if not args.no_compare:
+        # the same system solved in the other precision, for the mixed-vs-FP64 comparison
+        ctot, clat, ckms, cinfos = timed(not mixed, max(3, args.steps // 2), 1)
+        ci = cinfos[-1]
+        line["compare"] = {"precision": "fp64" if mixed else "mixed", "solves_per_s": len(clat) / ctot,
+                           "p50_ms": float(np.percentile(clat, 50) * 1e3),
+                           "p99_ms": float(np.percentile(clat, 99) * 1e3),
+                           "iterations": ci.iterations, "confirmations": ci.confirmations, "relres": ci.relres,
+                           "gbps_solve": solve_bytes(n, nnz, ci, not mixed) / (float(np.mean(ckms)) / 1e3) / 1e9}
+    it = info.iterations
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(sysobj, it, args.cpu_sample_iters)
+        progress("cpu baseline")
+        its_fp64 = info.iterations if not mixed else line.get("compare", {}).get("iterations", info.iterations)
+        line["cpu_baseline"] = cpu_baseline(sysobj, its_fp64, args.cpu_sample_iters)
     sysm.close()
     print(json.dumps(line), flush=True)
 

@@ -193,7 +193,14 @@ __global__ void __launch_bounds__(kAux) k_step64(SolveArgs a, const double* P, c
                                                  int bz, double* W) {
   __shared__ double sh[3][kAux / kWave];
   double p0 = 0.0, p1 = 0.0, p2 = 0.0;
-  pass_iter64<USER_D, kAux>(a, P, R, W, beta, bz != 0, p0, p1, p2);
+  Momentum<double> m;
+  m.R = R;
+  m.Yn = nullptr;
+  m.beta = beta;
+  m.beta_next = 0.0;
+  m.bz = bz != 0;
+  m.ym = false;
+  pass_iter64<USER_D, kAux>(a, P, m, W, p0, p1, p2);
   block_sum3<kAux>(p0, p1, p2, sh);
   if (threadIdx.x == 0) {
     double* slot = a.part + (size_t)blockIdx.x * kPartStride;
@@ -250,8 +257,11 @@ struct naj_system {
   double* lval = nullptr;
   float* lval32 = nullptr;
   int layout = 0;                  // 0 = slices in caller order; 1 = sorted slices + long rows
-  double* vec[3] = {nullptr, nullptr, nullptr};
-  float* fvec[4] = {nullptr, nullptr, nullptr, nullptr};   // mixed precision: 3 inner iterates + r32 (lazy)
+  std::vector<int64_t> hslice;     // host copy of slice_ptr (for the domain split)
+  int64_t* dom_bounds = nullptr;   // [nxcd+1] device copy of the balanced domain split
+  double* vec[4] = {nullptr, nullptr, nullptr, nullptr};   // x buffers; the 4th only in the materialized form
+  float* fvec[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // mixed: 4 inner iterates + r32 (lazy)
+  int ymode = 0;                   // materialized momentum form (irregular layout: one gathered vector)
   double* part = nullptr;          // 3 * max_grid
   Ctrl* ctrl = nullptr;
   Barrier* bar = nullptr;
@@ -298,6 +308,7 @@ void free_system(naj_system* s) {
   (void)hipFree(s->val32);
   (void)hipFree(s->dinv);
   (void)hipFree(s->perm);
+  (void)hipFree(s->dom_bounds);
   (void)hipFree(s->bperm);
   (void)hipFree(s->lrowptr);
   (void)hipFree(s->lcol);
@@ -390,6 +401,16 @@ naj_status choose_grid(naj_system* s) {
     s->aux_grid = (int)std::max<int64_t>(nxcd, std::min<int64_t>(std::max(ga, nxcd), wa));
     s->max_grid = std::max(s->max_grid, s->aux_grid);
   }
+  if (nxcd > 1 && s->nslices >= nxcd) {
+    // L2 domains get contiguous slice ranges of equal weight: stored entries (12 B each in
+    // float64) plus the 64 rows' vector traffic (about 4 streams of 8 B per row)
+    std::vector<int64_t> wpre(s->nslices + 1), bounds(nxcd + 1);
+    for (int64_t i = 0; i <= s->nslices; ++i) wpre[i] = s->hslice[i] * 12 / kWave + i * 32;
+    balanced_bounds(wpre.data(), s->nslices, nxcd, bounds.data());
+    naj_status rc = dev_alloc(s, &s->dom_bounds, (size_t)nxcd + 1);
+    if (rc != NAJ_OK) return rc;
+    HIP_TRY(hipMemcpy(s->dom_bounds, bounds.data(), sizeof(int64_t) * (nxcd + 1), hipMemcpyHostToDevice));
+  }
   int khz = 0;
   HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, s->device));
   if (khz <= 0) khz = 100000;
@@ -428,6 +449,7 @@ Sell sell_of(const naj_system* s) {
   A.n = s->n;
   A.nslices = s->nslices;
   A.row0 = s->n_long;
+  A.dom_bounds = s->dom_bounds;
   A.n_long = s->n_long;
   A.lrowptr = s->lrowptr;
   A.lcol = s->lcol;
@@ -458,6 +480,8 @@ SolveArgs make_args(naj_system* s, const double* b, const naj_opts& o) {
   a.buf0 = s->vec[0];
   a.buf1 = s->vec[1];
   a.buf2 = s->vec[2];
+  a.buf3 = s->vec[3];
+  a.ymode = s->ymode;
   a.part = s->part;
   a.ctrl = s->ctrl;
   a.bar = s->bar;
@@ -477,7 +501,8 @@ SolveArgs make_args(naj_system* s, const double* b, const naj_opts& o) {
   a.f0 = s->fvec[0];
   a.f1 = s->fvec[1];
   a.f2 = s->fvec[2];
-  a.r32 = s->fvec[3];
+  a.f3 = s->fvec[3];
+  a.r32 = s->fvec[4];
   a.nxcd = s->nxcd;
   a.spin_ticks = s->spin_ticks;
   return a;
@@ -625,6 +650,7 @@ naj_status build_layout(naj_system* s, const int32_t* rowptr, const int32_t* col
   if (rc == NAJ_OK) rc = dev_alloc(s, &s->val32, (size_t)hp[s->nslices]);
   if (rc != NAJ_OK) return rc;
   HIP_TRY(hipMemcpyAsync(s->slice_ptr, hp.data(), sizeof(int64_t) * (s->nslices + 1), hipMemcpyHostToDevice, st));
+  s->hslice = hp;
   if (s->nslices > 0) {
     hipLaunchKernelGGL(k_sell_fill, dim3(blocks_for(s->nslices * kWave, kAux)), dim3(kAux), 0, st, src_rp, src_col,
                        src_val, row0, n, s->nslices, s->slice_ptr, s->col, s->val, s->val32);
@@ -768,7 +794,8 @@ naj_status naj_create_system(int64_t n, int64_t nnz, const int32_t* rowptr, cons
   }
   STEP(build_layout(s, rowptr, colidx, vals, st));
   STEP(choose_grid(s));
-  for (auto& v : s->vec) STEP(dev_alloc(s, &v, (size_t)n));
+  s->ymode = env_int("NAJ_YMODE", s->layout == 1 ? 1 : 0) ? 1 : 0;
+  for (int i = 0; i < 3 + s->ymode; ++i) STEP(dev_alloc(s, &s->vec[i], (size_t)n));
   STEP(dev_alloc(s, &s->part, (size_t)kPartStride * s->max_grid));
   STEP(dev_alloc(s, &s->ctrl, 1));
   STEP(dev_alloc(s, &s->bar, 1));
@@ -827,8 +854,9 @@ naj_status naj_solve(naj_system* s, const double* b, const double* x0, const naj
   rc = ensure_hist(s, hist ? hist_cap : 0, trace ? trace_cap : 0);
   if (rc != NAJ_OK) return rc;
   if (o.precision == NAJ_MIXED && !s->fvec[0]) {
-    for (auto& v : s->fvec) {
-      rc = dev_alloc(s, &v, (size_t)s->n);
+    for (int i = 0; i < 5; ++i) {
+      if (i == 3 && !s->ymode) continue;
+      rc = dev_alloc(s, &s->fvec[i], (size_t)s->n);
       if (rc != NAJ_OK) return rc;
     }
   }
@@ -845,7 +873,7 @@ naj_status naj_solve(naj_system* s, const double* b, const double* x0, const naj
     HIP_TRY(hipMemcpyAsync(s->vec[0], x0, sizeof(double) * s->n, hipMemcpyDeviceToDevice, st));
   }
   if (!x0) HIP_TRY(hipMemsetAsync(s->vec[0], 0, sizeof(double) * s->n, st));
-  hipLaunchKernelGGL(k_solve_init, dim3(1), dim3(64), 0, st, s->ctrl, s->bar, s->counters, o.k0);
+  hipLaunchKernelGGL(k_solve_init, dim3(1), dim3(64), 0, st, s->ctrl, s->bar, s->counters, o.k0, s->ymode);
   HIP_TRY(hipGetLastError());
   SolveArgs a = make_args(s, b_in, o);
   if (!hist) a.hist = nullptr, a.hist_cap = 0;

@@ -56,7 +56,9 @@ struct Ctrl {
   double relres;         // residual of the accepted iterate
   int t;                 // iteration index of the pass about to run (1-based)
   int K_re, K, ell;      // restart bookkeeping of Algorithm 2
-  int iP, iR, iW;        // buffer roles: P = x^{t-1}, R = x^{t-2}, W receives x^t
+  int iP, iR, iW;        // buffer roles: P = x^{t-1}, R = x^{t-2} (or y^t in the materialized form), W receives x^t
+  int iYn;               // materialized form: buffer receiving y^{t+1}, -1 = none (beta_next == 0)
+  double beta_next;      // materialized form: coefficient of y^{t+1} written by the pass about to run
   int beta_zero;         // beta == 0: y = P, R is not read
   int phase;
   int last_confirm;
@@ -106,6 +108,7 @@ struct Sell {
   int64_t nslices;
   int64_t row0;               // first row held by the slices (= n_long)
   int64_t n_long;
+  const int64_t* dom_bounds;  // [nxcd+1] slice ranges of the L2 domains balanced by stored entries, or null
   const int64_t* lrowptr;     // [n_long+1]
   const int32_t* lcol;
   const double* lval;
@@ -119,6 +122,7 @@ struct SolveArgs {
   double* buf0;
   double* buf1;
   double* buf2;
+  double* buf3;               // materialized form: the second y buffer
   double* part;               // [3 * G]
   Ctrl* ctrl;
   Barrier* bar;
@@ -141,7 +145,24 @@ struct SolveArgs {
   float* f0;                  // three float32 inner iterates
   float* f1;
   float* f2;
+  float* f3;
   float* r32;                 // float32 right-hand side of the inner solve
+  int ymode;                  // materialized momentum form (y written by each pass, one gathered vector)
+};
+
+// How a pass forms y^t and whether it writes y^{t+1}.
+//  two-iterate form: y = P + beta (P - R) at every use (R = x^{t-2}); nothing extra written.
+//  materialized form (ym): y^t was written by the previous pass into R (or is P when bz), and this
+//  pass writes y^{t+1} = x^t + beta_next (x^t - x^{t-1}) into Yn (when Yn is not null); if the
+//  restart test then fires, that y^{t+1} is simply not used.  One gathered vector instead of two.
+template <typename T>
+struct Momentum {
+  const T* R;
+  T* Yn;
+  T beta;
+  T beta_next;
+  bool bz;        // y^t = x^{t-1} = P
+  bool ym;
 };
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -152,11 +173,11 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 __device__ __forceinline__ double* pick(const SolveArgs& a, int i) {
-  return i == 0 ? a.buf0 : (i == 1 ? a.buf1 : a.buf2);
+  return i == 0 ? a.buf0 : (i == 1 ? a.buf1 : (i == 2 ? a.buf2 : a.buf3));
 }
 
 __device__ __forceinline__ float* pickf(const SolveArgs& a, int i) {
-  return i == 0 ? a.f0 : (i == 1 ? a.f1 : a.f2);
+  return i == 0 ? a.f0 : (i == 1 ? a.f1 : (i == 2 ? a.f2 : a.f3));
 }
 
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x / kWave); }
@@ -164,16 +185,19 @@ __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane
 using WaveRange = SliceRange;
 
 template <int BS>
-__device__ __forceinline__ WaveRange wave_range(int64_t nslices, int nxcd) {
-  return slice_range(nslices, nxcd, (int)gridDim.x, (int)blockIdx.x, wave_id(), BS / kWave);
+__device__ __forceinline__ WaveRange wave_range(const Sell& A, int nxcd) {
+  return slice_range(A.nslices, nxcd, (int)gridDim.x, (int)blockIdx.x, wave_id(), BS / kWave, A.dom_bounds);
 }
 
 // One slice of the fused pass: u = Q y, g = u - b, x = y - J^{-1} g, d = x - P,
 // with y = P + beta (P - R) formed at every gathered column (y = P when bz).
 template <bool USER_D>
 __device__ __forceinline__ void iter_slice(const SolveArgs& a, int64_t s, int lane, const double* __restrict__ P,
-                                           const double* __restrict__ R, double* __restrict__ W, double beta,
-                                           bool bz, double& ps, double& pgg, double& psabs) {
+                                           const Momentum<double>& m, double* __restrict__ W, double& ps, double& pgg,
+                                           double& psabs) {
+  const double* __restrict__ R = m.R;
+  const double beta = m.beta;
+  const bool bz = m.bz, ym = m.ym;
   const int64_t base = a.A.slice_ptr[s];
   const int width = (int)((a.A.slice_ptr[s + 1] - base) >> 6);
   const int64_t row = a.A.row0 + s * kWave + lane;
@@ -201,6 +225,10 @@ __device__ __forceinline__ void iter_slice(const SolveArgs& a, int64_t s, int la
 #pragma unroll
       for (int j = 0; j < kUnroll; ++j)
         if (k0 + j < width) y[j] = P[c[j]];
+    } else if (ym) {
+#pragma unroll
+      for (int j = 0; j < kUnroll; ++j)
+        if (k0 + j < width) y[j] = R[c[j]];
     } else {
       double pj[kUnroll], rj[kUnroll];
 #pragma unroll
@@ -221,12 +249,13 @@ __device__ __forceinline__ void iter_slice(const SolveArgs& a, int64_t s, int la
       }
   }
   if (live) {
-    const double yi = bz ? Pi : Pi + beta * (Pi - Ri);
+    const double yi = bz ? Pi : (ym ? Ri : Pi + beta * (Pi - Ri));
     const double g = acc - bi;
     const double dv = USER_D ? di : 1.0 / (asum == 0.0 ? 1.0 : asum);
     const double xi = yi - dv * g;
     W[row] = xi;
     const double d = xi - Pi;
+    if (m.Yn) m.Yn[row] = xi + m.beta_next * d;
     const double gd = g * d;
     ps = ps + gd;
     pgg = pgg + g * g;
@@ -274,8 +303,11 @@ __device__ __forceinline__ void resid_slice(const Sell& A, int64_t s, int lane, 
 // exactly converted float32 operands.  zp: the previous iterate is zero.
 template <bool USER_D>
 __device__ __forceinline__ void inner_slice(const SolveArgs& a, int64_t s, int lane, const float* __restrict__ P,
-                                            const float* __restrict__ R, float* __restrict__ W, float beta, bool bz,
-                                            bool zp, double& ps, double& pgg, double& psabs) {
+                                            const Momentum<float>& m, float* __restrict__ W, bool zp, double& ps,
+                                            double& pgg, double& psabs) {
+  const float* __restrict__ R = m.R;
+  const float beta = m.beta;
+  const bool bz = m.bz, ym = m.ym;
   const int64_t base = a.A.slice_ptr[s];
   const int width = (int)((a.A.slice_ptr[s + 1] - base) >> 6);
   const int64_t row = a.A.row0 + s * kWave + lane;
@@ -304,6 +336,10 @@ __device__ __forceinline__ void inner_slice(const SolveArgs& a, int64_t s, int l
 #pragma unroll
       for (int j = 0; j < kUnroll; ++j)
         if (k0 + j < width) y[j] = P[c[j]];
+    } else if (ym) {
+#pragma unroll
+      for (int j = 0; j < kUnroll; ++j)
+        if (k0 + j < width) y[j] = R[c[j]];
     } else {
       float pj[kUnroll], rj[kUnroll];
 #pragma unroll
@@ -324,12 +360,13 @@ __device__ __forceinline__ void inner_slice(const SolveArgs& a, int64_t s, int l
       }
   }
   if (live) {
-    const float yi = (zp || bz) ? Pi : Pi + beta * (Pi - Ri);
+    const float yi = (zp || bz) ? Pi : (ym ? Ri : Pi + beta * (Pi - Ri));
     const float g = acc - bi;
     const float dv = USER_D ? (float)di : 1.0f / (asum == 0.0f ? 1.0f : asum);
     const float xi = yi - dv * g;
     W[row] = xi;
     const float d = xi - Pi;
+    if (m.Yn) m.Yn[row] = xi + m.beta_next * d;
     const double g64 = (double)g, d64 = (double)d;
     const double gd = g64 * d64;
     ps = ps + gd;
@@ -437,12 +474,17 @@ __device__ __forceinline__ void long_row_sums(const int32_t* __restrict__ col, c
 
 template <bool USER_D>
 __device__ __forceinline__ void iter_long(const SolveArgs& a, int64_t r, int lane, const double* __restrict__ P,
-                                          const double* __restrict__ R, double* __restrict__ W, double beta, bool bz,
-                                          double& ps, double& pgg, double& psabs) {
+                                          const Momentum<double>& m, double* __restrict__ W, double& ps, double& pgg,
+                                          double& psabs) {
+  const double* __restrict__ R = m.R;
+  const double beta = m.beta;
+  const bool bz = m.bz, ym = m.ym;
   double acc, asum;
   const int64_t s = a.A.lrowptr[r], e = a.A.lrowptr[r + 1];
   if (bz)
     long_row_sums<double>(a.A.lcol, a.A.lval, s, e, lane, [&](int c) { return P[c]; }, acc, asum);
+  else if (ym)
+    long_row_sums<double>(a.A.lcol, a.A.lval, s, e, lane, [&](int c) { return R[c]; }, acc, asum);
   else
     long_row_sums<double>(a.A.lcol, a.A.lval, s, e, lane,
                           [&](int c) { const double p = P[c]; return p + beta * (p - R[c]); }, acc, asum);
@@ -450,12 +492,13 @@ __device__ __forceinline__ void iter_long(const SolveArgs& a, int64_t r, int lan
   asum = wave_sum(asum);
   if (lane == 0) {
     const double Pi = P[r];
-    const double yi = bz ? Pi : Pi + beta * (Pi - R[r]);
+    const double yi = bz ? Pi : (ym ? R[r] : Pi + beta * (Pi - R[r]));
     const double g = acc - a.b[r];
     const double dv = USER_D ? a.dinv[r] : 1.0 / (asum == 0.0 ? 1.0 : asum);
     const double xi = yi - dv * g;
     W[r] = xi;
     const double dd = xi - Pi;
+    if (m.Yn) m.Yn[r] = xi + m.beta_next * dd;
     const double gd = g * dd;
     ps = ps + gd;
     pgg = pgg + g * g;
@@ -477,14 +520,19 @@ __device__ __forceinline__ void resid_long(const Sell& A, int64_t r, int lane, c
 
 template <bool USER_D>
 __device__ __forceinline__ void inner_long(const SolveArgs& a, int64_t r, int lane, const float* __restrict__ P,
-                                           const float* __restrict__ R, float* __restrict__ W, float beta, bool bz,
-                                           bool zp, double& ps, double& pgg, double& psabs) {
+                                           const Momentum<float>& m, float* __restrict__ W, bool zp, double& ps,
+                                           double& pgg, double& psabs) {
+  const float* __restrict__ R = m.R;
+  const float beta = m.beta;
+  const bool bz = m.bz, ym = m.ym;
   float acc, asum;
   const int64_t s = a.A.lrowptr[r], e = a.A.lrowptr[r + 1];
   if (zp)
     long_row_sums<float>(a.A.lcol, a.A.lval32, s, e, lane, [&](int c) { (void)c; return 0.0f; }, acc, asum);
   else if (bz)
     long_row_sums<float>(a.A.lcol, a.A.lval32, s, e, lane, [&](int c) { return P[c]; }, acc, asum);
+  else if (ym)
+    long_row_sums<float>(a.A.lcol, a.A.lval32, s, e, lane, [&](int c) { return R[c]; }, acc, asum);
   else
     long_row_sums<float>(a.A.lcol, a.A.lval32, s, e, lane,
                          [&](int c) { const float p = P[c]; return p + beta * (p - R[c]); }, acc, asum);
@@ -492,12 +540,13 @@ __device__ __forceinline__ void inner_long(const SolveArgs& a, int64_t r, int la
   asum = wave_sum_f(asum);
   if (lane == 0) {
     const float Pi = zp ? 0.0f : P[r];
-    const float yi = (zp || bz) ? Pi : Pi + beta * (Pi - R[r]);
+    const float yi = (zp || bz) ? Pi : (ym ? R[r] : Pi + beta * (Pi - R[r]));
     const float g = acc - a.r32[r];
     const float dv = USER_D ? (float)a.dinv[r] : 1.0f / (asum == 0.0f ? 1.0f : asum);
     const float xi = yi - dv * g;
     W[r] = xi;
     const float dd = xi - Pi;
+    if (m.Yn) m.Yn[r] = xi + m.beta_next * dd;
     const double g64 = (double)g, d64 = (double)dd;
     const double gd = g64 * d64;
     ps = ps + gd;

@@ -21,6 +21,32 @@
 
 namespace naj {
 
+__device__ __forceinline__ double alpha_next(double alpha) { return (1.0 + sqrt(1.0 + 4.0 * alpha * alpha)) / 2.0; }
+
+// Materialized momentum form: after the roles of a pass are settled, fix the
+// coefficient of y^{t+1} the next pass writes, (alpha_t - 1)/alpha_{t+1} with
+// alpha_t = c->alpha (the value Algorithm 2 uses if that pass does not restart),
+// and the buffer receiving it (-1 when the coefficient is 0: then y^{t+1} = x^t).
+__device__ inline void ymode_plan_next(Ctrl* c) {
+  const double bn = (c->alpha - 1.0) / alpha_next(c->alpha);
+  c->beta_next = bn;
+  c->iYn = bn == 0.0 ? -1 : (c->beta_zero ? 2 : (c->iR == 2 ? 3 : 2));
+}
+
+// Roles after a pass that did not restart, materialized form: x^t becomes the previous
+// iterate, and y^{t+1} is the buffer just written (or x^t itself).
+__device__ inline void ymode_advance(Ctrl* c) {
+  const int p = c->iP;
+  c->iP = c->iW;
+  c->iW = p;
+  if (c->iYn >= 0) {
+    c->iR = c->iYn;
+    c->beta_zero = 0;
+  } else {
+    c->beta_zero = 1;
+  }
+}
+
 // Scalar control after an iteration pass that did not stop: the restart and
 // momentum branches of Algorithm 2, then the iteration cap.
 __device__ inline void apply_step(const SolveArgs& a, Ctrl* c, bool restart) {
@@ -37,16 +63,21 @@ __device__ inline void apply_step(const SolveArgs& a, Ctrl* c, bool restart) {
     // y^{t+1} = x^{t-1} = P and x^t := x^{t-1}: the roles stay as they are
   } else {
     const double alpha = c->alpha;
-    const double an = (1.0 + sqrt(1.0 + 4.0 * alpha * alpha)) / 2.0;
+    const double an = alpha_next(alpha);
     const double beta = (alpha - 1.0) / an;
     c->alpha = an;
     c->beta = beta;
-    c->beta_zero = beta == 0.0 ? 1 : 0;
-    const int p = c->iP, r = c->iR, w = c->iW;
-    c->iP = w;   // x^t becomes the previous iterate
-    c->iR = p;   // x^{t-1} becomes the one before
-    c->iW = r;   // the oldest buffer receives the next iterate
+    if (a.ymode) {
+      ymode_advance(c);
+    } else {
+      c->beta_zero = beta == 0.0 ? 1 : 0;
+      const int p = c->iP, r = c->iR, w = c->iW;
+      c->iP = w;   // x^t becomes the previous iterate
+      c->iR = p;   // x^{t-1} becomes the one before
+      c->iW = r;   // the oldest buffer receives the next iterate
+    }
   }
+  if (a.ymode) ymode_plan_next(c);
   if (t >= a.max_iter) {
     c->status = ST_NOT_CONVERGED;
     c->iterations = a.max_iter;
@@ -99,9 +130,16 @@ __device__ inline void mixed_after_residual(const SolveArgs& a, Ctrl* c, double 
   c->K_re = 0;
   c->K = a.k0;
   c->ell = 0;
-  c->iP = 0;
-  c->iR = 1;
-  c->iW = 2;
+  if (a.ymode) {
+    c->iP = 0;
+    c->iW = 1;
+    c->iR = 2;
+    ymode_plan_next(c);
+  } else {
+    c->iP = 0;
+    c->iR = 1;
+    c->iW = 2;
+  }
   c->phase = PH_INNER32;
 }
 
@@ -144,17 +182,22 @@ __device__ inline void mixed_after_inner(const SolveArgs& a, Ctrl* c, double s, 
     c->beta_zero = 1;
   } else {
     const double alpha = c->alpha;
-    const double an = (1.0 + sqrt(1.0 + 4.0 * alpha * alpha)) / 2.0;
+    const double an = alpha_next(alpha);
     const double beta = (alpha - 1.0) / an;
     c->alpha = an;
     c->beta = beta;
-    c->beta_zero = beta == 0.0 ? 1 : 0;
-    const int p = c->iP, r = c->iR, w = c->iW;
-    c->iP = w;
-    c->iR = p;
-    c->iW = r;
+    if (a.ymode) {
+      ymode_advance(c);
+    } else {
+      c->beta_zero = beta == 0.0 ? 1 : 0;
+      const int p = c->iP, r = c->iR, w = c->iW;
+      c->iP = w;
+      c->iR = p;
+      c->iW = r;
+    }
     c->zp = 0;
   }
+  if (a.ymode) ymode_plan_next(c);
   if (t >= a.max_iter) {
     mixed_finish_inner(a, c, c->iP, a.max_iter);   // d = the last iterate
     return;
@@ -245,8 +288,8 @@ __device__ inline void control_update(const SolveArgs& a, Ctrl* c, double r0, do
 
 // Control fields a pass needs, staged in LDS by thread 0.
 struct PassView {
-  int phase, iP, iR, iW, bz, zp, iX, iXn, iD, update;
-  double beta;
+  int phase, iP, iR, iW, bz, zp, iX, iXn, iD, update, iYn;
+  double beta, beta_next;
 };
 
 __device__ __forceinline__ void load_view(const Ctrl* c, PassView* v) {
@@ -261,17 +304,19 @@ __device__ __forceinline__ void load_view(const Ctrl* c, PassView* v) {
   v->iXn = c->iXn;
   v->iD = c->iD;
   v->update = c->update;
+  v->iYn = c->iYn;
+  v->beta_next = c->beta_next;
 }
 
 // The workgroup's share of one float64 iteration pass (long rows, then slices).
 template <bool USER_D, int BS>
-__device__ __forceinline__ void pass_iter64(const SolveArgs& a, const double* P, const double* R, double* W,
-                                            double beta, bool bz, double& p0, double& p1, double& p2) {
+__device__ __forceinline__ void pass_iter64(const SolveArgs& a, const double* P, const Momentum<double>& m, double* W,
+                                            double& p0, double& p1, double& p2) {
   const int lane = threadIdx.x % kWave;
   const LongRange<BS> lr;
-  for (int64_t r = lr.first; r < a.A.n_long; r += lr.step) iter_long<USER_D>(a, r, lane, P, R, W, beta, bz, p0, p1, p2);
-  const WaveRange wr = wave_range<BS>(a.A.nslices, a.nxcd);
-  for (int64_t s = wr.first; s < wr.end; s += wr.step) iter_slice<USER_D>(a, s, lane, P, R, W, beta, bz, p0, p1, p2);
+  for (int64_t r = lr.first; r < a.A.n_long; r += lr.step) iter_long<USER_D>(a, r, lane, P, m, W, p0, p1, p2);
+  const WaveRange wr = wave_range<BS>(a.A, a.nxcd);
+  for (int64_t s = wr.first; s < wr.end; s += wr.step) iter_slice<USER_D>(a, s, lane, P, m, W, p0, p1, p2);
 }
 
 // The workgroup's share of r = b - Q X (float64); ||r||^2 in p0.
@@ -281,7 +326,7 @@ __device__ __forceinline__ void pass_resid64(const Sell& A, int nxcd, const doub
   const int lane = threadIdx.x % kWave;
   const LongRange<BS> lr;
   for (int64_t r = lr.first; r < A.n_long; r += lr.step) resid_long(A, r, lane, X, b, out, p0);
-  const WaveRange wr = wave_range<BS>(A.nslices, nxcd);
+  const WaveRange wr = wave_range<BS>(A, nxcd);
   for (int64_t s = wr.first; s < wr.end; s += wr.step) resid_slice(A, s, lane, X, b, out, p0);
 }
 
@@ -291,28 +336,38 @@ __device__ __forceinline__ void run_pass(const SolveArgs& a, const PassView& v, 
                                          double& p2) {
   const int lane = threadIdx.x % kWave;
   if (v.phase == PH_ITER) {
-    pass_iter64<USER_D, BS>(a, pick(a, v.iP), pick(a, v.iR), pick(a, v.iW), v.beta, v.bz != 0, p0, p1, p2);
+    Momentum<double> m;
+    m.R = pick(a, v.iR);
+    m.Yn = (a.ymode && v.iYn >= 0) ? pick(a, v.iYn) : nullptr;
+    m.beta = v.beta;
+    m.beta_next = v.beta_next;
+    m.bz = v.bz != 0;
+    m.ym = a.ymode != 0;
+    pass_iter64<USER_D, BS>(a, pick(a, v.iP), m, pick(a, v.iW), p0, p1, p2);
   } else if (v.phase == PH_CONFIRM) {
     pass_resid64<BS>(a.A, a.nxcd, pick(a, v.iW), a.b, nullptr, p0);
   } else if (v.phase == PH_INNER32) {
     const float* P = pickf(a, v.iP);
-    const float* R = pickf(a, v.iR);
     float* W = pickf(a, v.iW);
-    const float beta = (float)v.beta;
-    const bool bz = v.bz != 0, zp = v.zp != 0;
+    Momentum<float> m;
+    m.R = pickf(a, v.iR);
+    m.Yn = (a.ymode && v.iYn >= 0) ? pickf(a, v.iYn) : nullptr;
+    m.beta = (float)v.beta;
+    m.beta_next = (float)v.beta_next;
+    m.bz = v.bz != 0;
+    m.ym = a.ymode != 0;
+    const bool zp = v.zp != 0;
     const LongRange<BS> lr;
-    for (int64_t r = lr.first; r < a.A.n_long; r += lr.step)
-      inner_long<USER_D>(a, r, lane, P, R, W, beta, bz, zp, p0, p1, p2);
-    const WaveRange wr = wave_range<BS>(a.A.nslices, a.nxcd);
-    for (int64_t s = wr.first; s < wr.end; s += wr.step)
-      inner_slice<USER_D>(a, s, lane, P, R, W, beta, bz, zp, p0, p1, p2);
+    for (int64_t r = lr.first; r < a.A.n_long; r += lr.step) inner_long<USER_D>(a, r, lane, P, m, W, zp, p0, p1, p2);
+    const WaveRange wr = wave_range<BS>(a.A, a.nxcd);
+    for (int64_t s = wr.first; s < wr.end; s += wr.step) inner_slice<USER_D>(a, s, lane, P, m, W, zp, p0, p1, p2);
   } else if (v.phase == PH_RESID64) {
     const double* X = pick(a, v.iX);
     const float* D = v.update ? pickf(a, v.iD) : nullptr;
     double* Xn = v.update ? pick(a, v.iXn) : nullptr;
     const LongRange<BS> lr;
     for (int64_t r = lr.first; r < a.A.n_long; r += lr.step) resid_mixed_long(a, r, lane, X, D, Xn, p0, p1);
-    const WaveRange wr = wave_range<BS>(a.A.nslices, a.nxcd);
+    const WaveRange wr = wave_range<BS>(a.A, a.nxcd);
     for (int64_t s = wr.first; s < wr.end; s += wr.step) resid_mixed_slice(a, s, lane, X, D, Xn, p0, p1);
   } else {  // PH_NORMB: every row, flat
     for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < a.A.n; i += (int64_t)gridDim.x * BS) {
@@ -402,6 +457,8 @@ __global__ void __launch_bounds__(BS) k_solve64(SolveArgs a) {
         v.iXn = __hip_atomic_load(&a.ctrl->iXn, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         v.iD = __hip_atomic_load(&a.ctrl->iD, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         v.update = __hip_atomic_load(&a.ctrl->update, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        v.iYn = __hip_atomic_load(&a.ctrl->iYn, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        v.beta_next = __hip_atomic_load(&a.ctrl->beta_next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
     }
     __syncthreads();
@@ -458,7 +515,7 @@ __global__ void __launch_bounds__(BS) k_solve64(SolveArgs a) {
 }
 
 // Clears the control block, the barrier and the arrival counters before a solve.
-__global__ void k_solve_init(Ctrl* c, Barrier* bar, unsigned int* counters, int k0) {
+__global__ void k_solve_init(Ctrl* c, Barrier* bar, unsigned int* counters, int k0, int ymode) {
   for (int i = threadIdx.x; i <= kMaxDomains; i += blockDim.x) counters[(size_t)i * kCounterStride] = 0u;
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     c->alpha = 1.0;
@@ -493,6 +550,14 @@ __global__ void k_solve_init(Ctrl* c, Barrier* bar, unsigned int* counters, int 
     c->inner_total = 0;
     c->inner_restarts = 0;
     c->nr = 0.0;
+    c->iYn = -1;
+    c->beta_next = 0.0;
+    if (ymode) {   // x buffers 0/1, y buffers 2/3
+      c->iP = 0;
+      c->iW = 1;
+      c->iR = 2;
+      ymode_plan_next(c);
+    }
     for (int i = 0; i < kRestartLogCap; ++i) c->restart_log[i] = 0;
     bar->count = 0ULL;
     bar->epoch_done = 0u;

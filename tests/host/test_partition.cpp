@@ -16,10 +16,18 @@ int main() {
     for (int nd : dom_opts)
       for (int G : grid_opts)
         for (long long ns : slice_opts) {
+          // weights: decreasing widths as in a degree-sorted layout
+          std::vector<int64_t> wpre(ns + 1, 0);
+          for (long long s = 0; s < ns; ++s) wpre[s + 1] = wpre[s] + 1 + (ns - s) % 97;
+          std::vector<int64_t> bounds(nd + 1);
+          naj::balanced_bounds(wpre.data(), ns, nd, bounds.data());
+          for (int d = 0; d < nd; ++d)
+            if (bounds[d] > bounds[d + 1]) { std::printf("FAIL bounds not monotone\n"); return 1; }
+          for (int use_bounds = 0; use_bounds < 2; ++use_bounds) {
           std::vector<int> hits(ns, 0);
           for (int w = 0; w < G; ++w)
             for (int v = 0; v < wpb; ++v) {
-              naj::SliceRange r = naj::slice_range(ns, nd, G, w, v, wpb);
+              naj::SliceRange r = naj::slice_range(ns, nd, G, w, v, wpb, use_bounds ? bounds.data() : nullptr);
               if (r.step < 1) { std::printf("FAIL zero step ns=%lld nd=%d G=%d w=%d\n", ns, nd, G, w); return 1; }
               if (r.end > ns) { std::printf("FAIL end beyond slices\n"); return 1; }
               for (long long s = r.first; s < r.end; s += r.step) {
@@ -33,6 +41,7 @@ int main() {
               return 1;
             }
           ++checked;
+          }
         }
   std::printf("ok %ld shapes\n", checked);
   return 0;

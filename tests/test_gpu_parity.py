@@ -363,3 +363,23 @@ def test_irregular_user_diagonal_and_mixed(naj):
     assert np.linalg.norm(s.b - Q @ xg) / np.linalg.norm(s.b) <= 1e-8
     # long rows sum in another order, so refinement steps may differ by one at most
     assert abs(info.confirmations - m.outer) <= 1
+
+
+@pytest.mark.parametrize("mode", ["0", "1"])
+def test_materialized_momentum_form_is_bitwise(naj, mode, monkeypatch):
+    """Each pass writing y^{t+1} = x^t + beta_t (x^t - x^{t-1}) (used unless the restart test fires) gives the
+    same iterates bit for bit as forming y inside the gather; float64 and mixed precision."""
+    _say("materialized y, driver", mode)
+    monkeypatch.setenv("NAJ_YMODE", "1")
+    monkeypatch.setenv("NAJ_MODE", mode)
+    s = W.poisson2d_64()
+    sysm = naj.System(s.rowptr, s.colidx, s.vals)
+    monkeypatch.delenv("NAJ_YMODE")
+    monkeypatch.delenv("NAJ_MODE")
+    _compare_solve(naj, sysm, s.rowptr, s.colidx, s.vals, s.b, tol=1e-8, max_iter=20000, bitwise=True)
+    orc = O.accelerated_jacobi(s.rowptr, s.colidx, s.vals, s.b, tol=1e-8, max_iter=300, restart=False)
+    x, info = sysm.solve(s.b, tol=1e-8, max_iter=300, restart=False)
+    assert np.array_equal(x.cpu().numpy(), orc.x)
+    m = O.accelerated_jacobi_mixed(s.rowptr, s.colidx, s.vals, s.b, tol=1e-8)
+    x, info = sysm.solve(s.b, precision=naj.NAJ_MIXED)
+    assert info.iterations == m.inner_total and np.array_equal(x.cpu().numpy(), m.x)
