@@ -167,6 +167,59 @@ naj_status naj_residual(naj_system *sys, const double *x, const double *b, doubl
 /* naj_diagonal: the diagonal J in use (eq. (J-diag) or the caller's D), device float64[n] out. */
 naj_status naj_diagonal(naj_system *sys, double *out, void *stream);
 
+/*
+ * Batches (many systems, up to NAJ_MAX_RHS right-hand sides each, advanced together).
+ * Every (system, right-hand side) pair runs its own Algorithm 3 (or the mixed
+ * refinement), with its own restart schedule and stopping decision; they share
+ * the passes over the matrices.  An instance's result does not depend on which
+ * other systems are in the batch (the work split and summation order of a
+ * system depend only on the system and its tile size).
+ */
+#define NAJ_MAX_RHS 8
+typedef struct naj_batch naj_batch;
+
+/*
+ * Create a batch over existing systems (not copied; they must outlive the batch).
+ *   nsys            : number of systems, >= 1
+ *   systems         : host array of nsys system handles (same device)
+ *   nrhs            : host array, right-hand sides per system, 1..NAJ_MAX_RHS
+ *   opts            : options shared by every instance (NULL = defaults)
+ * Passes are recorded once as a HIP graph of several launches and replayed.
+ * Errors: NAJ_EINVAL, NAJ_ENOMEM, NAJ_EDEVICE.
+ */
+naj_status naj_batch_create(int32_t nsys, naj_system *const *systems, const int32_t *nrhs, const naj_opts *opts,
+                            void *stream, naj_batch **out);
+
+/*
+ * Solve every instance of the batch.
+ *   b[i], x0[i], x[i]: device float64 arrays of system i, row-interleaved n_i x nrhs_i;
+ *                     x0 (the host array) or any x0[i] may be NULL (zero start); x[i] may not alias b[i]
+ *   res             : host array of sum(nrhs) results, system-major then right-hand side
+ * Returns the worst status over the instances (NAJ_NOT_CONVERGED if any did not converge).
+ */
+naj_status naj_batch_solve(naj_batch *batch, const double *const *b, const double *const *x0, double *const *x,
+                           naj_result *res, void *stream);
+
+/* Batch figures (host outputs, any may be NULL): tiles per pass, workgroups per pass, device bytes owned. */
+naj_status naj_batch_info(const naj_batch *batch, int32_t *ntiles, int32_t *grid, int64_t *device_bytes);
+
+/* Release a batch (the systems stay). NULL is ignored. */
+void naj_batch_destroy(naj_batch *batch);
+
+/*
+ * Autotuner for batch tiles: times tile sizes of 4..64 slices on `sys` solved alone
+ * with `nrhs` right-hand sides for `passes` iterations, and records the fastest in a
+ * process-wide table keyed by the system's features (layout, log2 n, nonzeros per
+ * row, nrhs, precision); batches created afterwards use it.  *best_tile (host, may
+ * be NULL) receives the choice.
+ */
+naj_status naj_autotune_tiles(naj_system *sys, int32_t nrhs, const naj_opts *opts, int32_t passes, void *stream,
+                              int32_t *best_tile);
+
+/* Save / load the tile table (text, one "layout log2n nnz_per_row nrhs precision tile" line per entry). */
+naj_status naj_tune_save(const char *path);
+naj_status naj_tune_load(const char *path);
+
 #ifdef __cplusplus
 }
 #endif

@@ -18,6 +18,9 @@
 #include "../../include/naj.h"
 #include "naj_device.h"
 #include "naj_solve.h"
+#include "naj_batch.h"
+#include <map>
+#include <mutex>
 
 using namespace naj;
 
@@ -135,6 +138,11 @@ __global__ void k_permute_rows(const int32_t* rowptr, const int32_t* colidx, con
       new_val[d + (k - s)] = vals[k];
     }
   }
+}
+
+__global__ void k_fill_ones(double* p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 1.0;
 }
 
 __global__ void k_to_float(const double* in, float* out, int64_t n) {
@@ -716,6 +724,195 @@ naj_status run_solve(naj_system* s, SolveArgs& a, const naj_opts& o, hipStream_t
 
 }  // namespace
 
+// ============================================================================ batch
+
+struct naj_batch {
+  int device = 0;
+  int nsys = 0, ninst = 0, ntiles = 0, grid = 0;
+  std::vector<naj_system*> systems;
+  std::vector<int> nrhs, inst0;
+  naj_opts opts;
+  BatchSys* d_sys = nullptr;
+  BatchInst* d_inst = nullptr;
+  BatchTile* d_tiles = nullptr;
+  unsigned int* d_counters = nullptr;   // per system, 64-word stride; the done counter after them
+  unsigned int* d_done = nullptr;
+  Ctrl* d_ctrl = nullptr;
+  std::vector<BatchInst> h_inst;
+  std::vector<void*> bufs;
+  unsigned int* hdone = nullptr;        // pinned, 2 slots
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int graph_len = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, evc[2] = {nullptr, nullptr};
+  BatchArgs args;
+  int64_t bytes = 0;
+  std::vector<int> tile_slices;
+};
+
+namespace {
+
+// ---- tile sizes: a process-wide table keyed by system features (never by the batch)
+struct TuneKey {
+  int layout, log2n, nnz_row, nrhs, precision;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(layout, log2n, nnz_row, nrhs, precision) < std::tie(o.layout, o.log2n, o.nnz_row, o.nrhs, o.precision);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tune;
+
+TuneKey tune_key(const naj_system* s, int nrhs, int precision) {
+  int l2 = 0;
+  while ((1LL << (l2 + 1)) <= s->n) ++l2;
+  return TuneKey{s->layout, l2, (int)((s->nnz + s->n / 2) / s->n), nrhs, precision};
+}
+
+// Slices per tile for a system: the tuned value if one is recorded for its features,
+// else a default of 16 (four slices per wave), never more than the system has.
+int tile_slices_for(const naj_system* s, int nrhs, int precision) {
+  int t = 16;
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tune.find(tune_key(s, nrhs, precision));
+    if (it != g_tune.end()) t = it->second;
+  }
+  if (s->nslices > 0 && t > s->nslices) t = (int)s->nslices;
+  return std::max(1, t);
+}
+
+void free_batch(naj_batch* bt) {
+  if (!bt) return;
+  if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
+  if (bt->graph) (void)hipGraphDestroy(bt->graph);
+  if (bt->cap) (void)hipStreamDestroy(bt->cap);
+  for (void* p : bt->bufs) (void)hipFree(p);   // every device allocation of the batch, once
+  if (bt->hdone) (void)hipHostFree(bt->hdone);
+  if (bt->ev0) (void)hipEventDestroy(bt->ev0);
+  if (bt->ev1) (void)hipEventDestroy(bt->ev1);
+  for (auto& e : bt->evc)
+    if (e) (void)hipEventDestroy(e);
+  delete bt;
+}
+
+template <typename T>
+naj_status batch_alloc(naj_batch* bt, T** p, size_t count) {
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return fail(e == hipErrorOutOfMemory ? NAJ_ENOMEM : NAJ_EDEVICE, "hipMalloc(%zu bytes): %s", count * sizeof(T),
+                hipGetErrorString(e));
+  }
+  bt->bufs.push_back(*p);
+  bt->bytes += (int64_t)(count * sizeof(T));
+  return NAJ_OK;
+}
+
+naj_status batch_build(naj_batch* bt, hipStream_t st) {
+  const naj_opts& o = bt->opts;
+  const bool mixed = o.precision == NAJ_MIXED;
+  std::vector<BatchSys> hs(bt->nsys);
+  std::vector<BatchTile> ht;
+  bt->ninst = 0;
+  bt->inst0.assign(bt->nsys, 0);
+  bt->tile_slices.assign(bt->nsys, 0);
+  for (int i = 0; i < bt->nsys; ++i) {
+    naj_system* s = bt->systems[i];
+    const int T = tile_slices_for(s, bt->nrhs[i], o.precision);
+    bt->tile_slices[i] = T;
+    BatchSys& S = hs[i];
+    S.A = sell_of(s);
+    S.A.dom_bounds = nullptr;
+    S.dinv = s->dinv;
+    S.inst0 = bt->ninst;
+    S.ninst = bt->nrhs[i];
+    S.tile0 = (int)ht.size();
+    S.ymode = s->ymode;
+    bt->inst0[i] = bt->ninst;
+    bt->ninst += bt->nrhs[i];
+    const int lt = 32;   // long rows per tile
+    for (int64_t l = 0; l < s->n_long; l += lt)
+      ht.push_back(BatchTile{i, 0, 0, (int)l, (int)std::min<int64_t>(s->n_long, l + lt)});
+    for (int64_t sl = 0; sl < s->nslices; sl += T)
+      ht.push_back(BatchTile{i, (int)sl, (int)std::min<int64_t>(s->nslices, sl + T), 0, 0});
+    if ((int)ht.size() == S.tile0) ht.push_back(BatchTile{i, 0, 0, 0, 0});
+    S.ntiles = (int)ht.size() - S.tile0;
+  }
+  bt->ntiles = (int)ht.size();
+  naj_status rc = NAJ_OK;
+  if ((rc = batch_alloc(bt, &bt->d_sys, (size_t)bt->nsys)) != NAJ_OK) return rc;
+  if ((rc = batch_alloc(bt, &bt->d_inst, (size_t)bt->ninst)) != NAJ_OK) return rc;
+  if ((rc = batch_alloc(bt, &bt->d_tiles, (size_t)bt->ntiles)) != NAJ_OK) return rc;
+  if ((rc = batch_alloc(bt, &bt->d_counters, (size_t)(bt->nsys + 1) * 64)) != NAJ_OK) return rc;
+  if ((rc = batch_alloc(bt, &bt->d_ctrl, (size_t)bt->ninst)) != NAJ_OK) return rc;
+  bt->d_done = bt->d_counters + (size_t)bt->nsys * 64;
+  bt->h_inst.assign(bt->ninst, BatchInst{});
+  for (int i = 0; i < bt->nsys; ++i) {
+    naj_system* s = bt->systems[i];
+    hs[i].counter = bt->d_counters + (size_t)i * 64;
+    for (int j = 0; j < bt->nrhs[i]; ++j) {
+      BatchInst& I = bt->h_inst[bt->inst0[i] + j];
+      I.ctrl = bt->d_ctrl + bt->inst0[i] + j;
+      for (int q = 0; q < 4; ++q) {
+        I.x[q] = nullptr;
+        if (q < 3 + s->ymode && (rc = batch_alloc(bt, &I.x[q], (size_t)s->n)) != NAJ_OK) return rc;
+      }
+      for (int q = 0; q < 5; ++q) {
+        I.f[q] = nullptr;
+        if (mixed && (q != 3 || s->ymode) && (rc = batch_alloc(bt, &I.f[q], (size_t)s->n)) != NAJ_OK) return rc;
+      }
+      if ((rc = batch_alloc(bt, &I.b, (size_t)s->n)) != NAJ_OK) return rc;
+      if ((rc = batch_alloc(bt, &I.part, (size_t)kPartStride * hs[i].ntiles)) != NAJ_OK) return rc;
+    }
+  }
+  HIP_TRY(hipMemcpyAsync(bt->d_sys, hs.data(), sizeof(BatchSys) * bt->nsys, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(bt->d_inst, bt->h_inst.data(), sizeof(BatchInst) * bt->ninst, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(bt->d_tiles, ht.data(), sizeof(BatchTile) * bt->ntiles, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemsetAsync(bt->d_counters, 0, sizeof(unsigned int) * (bt->nsys + 1) * 64, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  // grid: every resident workgroup, at most one per tile
+  int occ = 0, cus = 0;
+  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_batch_pass, kBatchBlock, 0));
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, bt->device));
+  cus = prop.multiProcessorCount;
+  bt->grid = std::max(1, std::min(bt->ntiles, std::max(1, occ) * cus));
+  BatchArgs& A = bt->args;
+  A.tiles = bt->d_tiles;
+  A.ntiles = bt->ntiles;
+  A.sys = bt->d_sys;
+  A.inst = bt->d_inst;
+  A.done = bt->d_done;
+  A.tol = o.tol;
+  A.inner_tol = o.inner_tol;
+  A.max_iter = o.max_iter;
+  A.restart = o.restart ? 1 : 0;
+  A.confirm_gap = o.confirm_gap;
+  A.k0 = o.k0;
+  A.precision = mixed ? 1 : 0;
+  A.max_refine = o.max_refine;
+  // a chunk of passes captured once as a graph and replayed
+  if (bt->exec) {
+    (void)hipGraphExecDestroy(bt->exec);
+    bt->exec = nullptr;
+  }
+  if (bt->graph) {
+    (void)hipGraphDestroy(bt->graph);
+    bt->graph = nullptr;
+  }
+  bt->graph_len = std::max(1, env_int("NAJ_GRAPH_LEN", 8));
+  HIP_TRY(hipStreamBeginCapture(bt->cap, hipStreamCaptureModeThreadLocal));
+  for (int q = 0; q < bt->graph_len; ++q)
+    hipLaunchKernelGGL(k_batch_pass, dim3(bt->grid), dim3(kBatchBlock), 0, bt->cap, bt->args);
+  HIP_TRY(hipStreamEndCapture(bt->cap, &bt->graph));
+  HIP_TRY(hipGraphInstantiate(&bt->exec, bt->graph, nullptr, nullptr, 0));
+  return NAJ_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 void naj_opts_default(naj_opts* o) {
@@ -738,6 +935,7 @@ const char* naj_version(void) { return "naj 0.1 gfx950"; }
 naj_status naj_create_system(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* colidx, const double* vals,
                              const double* D, void* stream, naj_system** out) {
   g_err.clear();
+  (void)hipGetLastError();   // drop a stale error left by unrelated earlier runtime calls
   if (!out) return fail(NAJ_EINVAL, "out is NULL");
   *out = nullptr;
   if (n < 1 || n >= (1LL << 31) - 64) return fail(NAJ_EINVAL, "n must be in [1, 2^31-64) (got %lld)", (long long)n);
@@ -840,6 +1038,7 @@ naj_status naj_solve(naj_system* s, const double* b, const double* x0, const naj
                      naj_result* res, double* hist, int32_t hist_cap, int32_t* restart_log, int32_t log_cap,
                      double* trace, int32_t trace_cap, void* stream) {
   g_err.clear();
+  (void)hipGetLastError();   // drop a stale error left by unrelated earlier runtime calls
   if (!s) return fail(NAJ_EINVAL, "system is NULL");
   if (!b || !x || !res) return fail(NAJ_EINVAL, "b, x and res are required");
   if (x == b) return fail(NAJ_EINVAL, "x must not alias b");
@@ -931,6 +1130,7 @@ naj_status naj_solve(naj_system* s, const double* b, const double* x0, const naj
 naj_status naj_step(naj_system* s, const double* p, const double* r, double beta, const double* b, double* x,
                     double* red, void* stream) {
   g_err.clear();
+  (void)hipGetLastError();   // drop a stale error left by unrelated earlier runtime calls
   if (!s || !p || !b || !x || !red) return fail(NAJ_EINVAL, "null argument");
   if (x == p || x == r || x == b) return fail(NAJ_EINVAL, "x must not alias p, r or b");
   if (beta != 0.0 && !r) return fail(NAJ_EINVAL, "r is required when beta != 0");
@@ -1006,6 +1206,244 @@ naj_status naj_diagonal(naj_system* s, double* out, void* stream) {
     HIP_TRY(hipGetLastError());
   }
   HIP_TRY(hipStreamSynchronize(st));
+  return NAJ_OK;
+}
+
+
+naj_status naj_batch_create(int32_t nsys, naj_system* const* systems, const int32_t* nrhs, const naj_opts* opts,
+                            void* stream, naj_batch** out) {
+  g_err.clear();
+  if (!out) return fail(NAJ_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (nsys < 1 || !systems || !nrhs) return fail(NAJ_EINVAL, "need nsys >= 1, systems and nrhs");
+  naj_opts o;
+  if (opts) o = *opts; else naj_opts_default(&o);
+  naj_status rc = check_opts(o);
+  if (rc != NAJ_OK) return rc;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  for (int i = 0; i < nsys; ++i) {
+    if (!systems[i]) return fail(NAJ_EINVAL, "system %d is NULL", i);
+    if (nrhs[i] < 1 || nrhs[i] > kMaxRhs) return fail(NAJ_EINVAL, "nrhs[%d] = %d outside [1, %d]", i, nrhs[i], kMaxRhs);
+    if (systems[i]->device != dev) return fail(NAJ_EINVAL, "system %d lives on another device", i);
+  }
+  naj_batch* bt = new naj_batch();
+  bt->device = dev;
+  bt->nsys = nsys;
+  bt->systems.assign(systems, systems + nsys);
+  bt->nrhs.assign(nrhs, nrhs + nsys);
+  bt->opts = o;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipStreamCreateWithFlags(&bt->cap, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreate(&bt->ev0);
+  if (e == hipSuccess) e = hipEventCreate(&bt->ev1);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&bt->evc[0], hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&bt->evc[1], hipEventDisableTiming);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&bt->hdone, 2 * sizeof(unsigned int), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    free_batch(bt);
+    return fail(NAJ_EDEVICE, "batch setup: %s", hipGetErrorString(e));
+  }
+  rc = batch_build(bt, st);
+  if (rc != NAJ_OK) {
+    free_batch(bt);
+    return rc;
+  }
+  *out = bt;
+  return NAJ_OK;
+}
+
+void naj_batch_destroy(naj_batch* bt) {
+  if (!bt) return;
+  (void)hipDeviceSynchronize();
+  free_batch(bt);
+}
+
+naj_status naj_batch_info(const naj_batch* bt, int32_t* ntiles, int32_t* grid, int64_t* device_bytes) {
+  if (!bt) return fail(NAJ_EINVAL, "batch is NULL");
+  if (ntiles) *ntiles = bt->ntiles;
+  if (grid) *grid = bt->grid;
+  if (device_bytes) *device_bytes = bt->bytes;
+  return NAJ_OK;
+}
+
+naj_status naj_batch_solve(naj_batch* bt, const double* const* b, const double* const* x0, double* const* x,
+                           naj_result* res, void* stream) {
+  g_err.clear();
+  (void)hipGetLastError();   // drop a stale error left by unrelated earlier runtime calls
+  if (!bt || !b || !x || !res) return fail(NAJ_EINVAL, "batch, b, x and res are required");
+  for (int i = 0; i < bt->nsys; ++i)
+    if (!b[i] || !x[i]) return fail(NAJ_EINVAL, "b[%d] and x[%d] are required", i, i);
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipSetDevice(bt->device));
+  const naj_opts& o = bt->opts;
+  const int nthreads = std::max(bt->ninst, bt->nsys);
+  hipLaunchKernelGGL(k_batch_init, dim3((nthreads + 255) / 256), dim3(256), 0, st, bt->args, bt->nsys, bt->ninst);
+  HIP_TRY(hipGetLastError());
+  for (int i = 0; i < bt->nsys; ++i) {
+    naj_system* s = bt->systems[i];
+    const int k = bt->nrhs[i];
+    const dim3 g1(blocks_for(s->n, kAux * 4)), b1(kAux);
+    for (int j = 0; j < k; ++j) {
+      const BatchInst& I = bt->h_inst[bt->inst0[i] + j];
+      hipLaunchKernelGGL(k_batch_load, g1, b1, 0, st, b[i], k, j, s->perm, s->n, I.b);
+      hipLaunchKernelGGL(k_batch_load, g1, b1, 0, st, x0 ? x0[i] : nullptr, k, j, s->perm, s->n, I.x[0]);
+    }
+  }
+  HIP_TRY(hipGetLastError());
+  // passes: graph replays, the host checking the previous replay's done count while the next runs
+  const int64_t per_inst = o.precision == NAJ_MIXED
+                               ? 2 + (int64_t)(o.max_refine + 1) * (1 + (int64_t)o.max_iter)
+                               : 2 + (int64_t)o.max_iter + (int64_t)o.max_iter / std::max(1, o.confirm_gap) + 1;
+  const int64_t max_replays = per_inst / bt->graph_len + 2;
+  int64_t replays = 0;
+  int cur = 0, prev = -1;
+  bool finished = false;
+  HIP_TRY(hipEventRecord(bt->ev0, st));
+  for (;;) {
+    HIP_TRY(hipGraphLaunch(bt->exec, st));
+    ++replays;
+    HIP_TRY(hipMemcpyAsync(&bt->hdone[cur], bt->d_done, sizeof(unsigned int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipEventRecord(bt->evc[cur], st));
+    if (prev >= 0) {
+      HIP_TRY(hipEventSynchronize(bt->evc[prev]));
+      if ((int)bt->hdone[prev] >= bt->ninst) {
+        finished = true;
+        break;
+      }
+    }
+    if (replays >= max_replays) {
+      HIP_TRY(hipEventSynchronize(bt->evc[cur]));
+      finished = (int)bt->hdone[cur] >= bt->ninst;
+      break;
+    }
+    prev = cur;
+    cur ^= 1;
+  }
+  HIP_TRY(hipEventRecord(bt->ev1, st));
+  if (!finished) return fail(NAJ_EDEVICE, "batch did not finish within %lld passes", (long long)replays * bt->graph_len);
+  for (int i = 0; i < bt->nsys; ++i) {
+    naj_system* s = bt->systems[i];
+    const int k = bt->nrhs[i];
+    for (int j = 0; j < k; ++j) {
+      const BatchInst& I = bt->h_inst[bt->inst0[i] + j];
+      hipLaunchKernelGGL(k_batch_store, dim3(blocks_for(s->n, kAux * 4)), dim3(kAux), 0, st, I.ctrl, I.x[0], I.x[1],
+                         I.x[2], k, j, s->perm, s->n, x[i]);
+    }
+  }
+  HIP_TRY(hipGetLastError());
+  std::vector<Ctrl> hc(bt->ninst);
+  HIP_TRY(hipMemcpyAsync(hc.data(), bt->d_ctrl, sizeof(Ctrl) * bt->ninst, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, bt->ev0, bt->ev1));
+  naj_status worst = NAJ_OK;
+  for (int q = 0; q < bt->ninst; ++q) {
+    const Ctrl& c = hc[q];
+    naj_result& r = res[q];
+    r.status = c.status;
+    r.iterations = o.precision == NAJ_MIXED ? c.inner_total : c.iterations;
+    r.restarts = o.precision == NAJ_MIXED ? c.inner_restarts : c.restarts;
+    r.confirmations = o.precision == NAJ_MIXED ? c.outer : c.confirms;
+    r.relres = c.relres;
+    r.hist_len = 0;
+    r.nrestart_log = 0;
+    r.kernel_ms = ms;
+    r.passes = c.passes;
+    r.grid = bt->grid;
+    if (c.status < 0 && (worst >= 0 || c.status < worst)) worst = (naj_status)c.status;
+    if (worst >= 0 && c.status == ST_NOT_CONVERGED) worst = NAJ_NOT_CONVERGED;
+  }
+  if (worst == NAJ_EBREAKDOWN) return fail(NAJ_EBREAKDOWN, "NaN/Inf in a reduction of at least one instance");
+  return worst;
+}
+
+// Times each candidate tile size on one system solved alone (a batch of one) for `passes`
+// passes of the batch kernel, and records the fastest for the system's features.
+naj_status naj_autotune_tiles(naj_system* s, int32_t nrhs, const naj_opts* opts, int32_t passes, void* stream,
+                              int32_t* best_tile) {
+  g_err.clear();
+  if (!s || nrhs < 1 || nrhs > kMaxRhs) return fail(NAJ_EINVAL, "bad system or nrhs");
+  naj_opts o;
+  if (opts) o = *opts; else naj_opts_default(&o);
+  o.max_iter = std::max(1, passes);
+  o.tol = 1e-300;
+  o.inner_tol = 1e-300 < o.inner_tol ? o.inner_tol : 1e-4;
+  const int cands[] = {4, 8, 16, 32, 64};
+  hipStream_t st = (hipStream_t)stream;
+  double* dbuf = nullptr;
+  HIP_TRY(hipMalloc((void**)&dbuf, sizeof(double) * s->n * nrhs * 2));
+  HIP_TRY(hipMemsetAsync(dbuf, 0, sizeof(double) * s->n * nrhs * 2, st));
+  hipLaunchKernelGGL(k_fill_ones, dim3(blocks_for(s->n * nrhs, kAux * 4)), dim3(kAux), 0, st, dbuf, s->n * nrhs);
+  double* xb = dbuf + (size_t)s->n * nrhs;
+  const TuneKey key = tune_key(s, nrhs, o.precision);
+  int best = 16;
+  float best_ms = 1e30f;
+  std::vector<naj_result> res(nrhs);
+  for (int T : cands) {
+    if (T > std::max<int64_t>(1, s->nslices) && T != cands[0]) break;
+    {
+      std::lock_guard<std::mutex> g(g_tune_mu);
+      g_tune[key] = T;
+    }
+    naj_batch* bt = nullptr;
+    naj_system* arr[1] = {s};
+    int32_t k[1] = {nrhs};
+    naj_status rc = naj_batch_create(1, arr, k, &o, stream, &bt);
+    if (rc != NAJ_OK) {
+      (void)hipFree(dbuf);
+      return rc;
+    }
+    const double* bb[1] = {dbuf};
+    double* xx[1] = {xb};
+    float ms = 1e30f;
+    for (int rep = 0; rep < 2; ++rep) {
+      rc = naj_batch_solve(bt, bb, nullptr, xx, res.data(), stream);
+      if (rc < 0 && rc != NAJ_EBREAKDOWN) {
+        naj_batch_destroy(bt);
+        (void)hipFree(dbuf);
+        return rc;
+      }
+      ms = std::min(ms, (float)res[0].kernel_ms);
+    }
+    naj_batch_destroy(bt);
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = T;
+    }
+  }
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune[key] = best;
+  }
+  (void)hipFree(dbuf);
+  if (best_tile) *best_tile = best;
+  return NAJ_OK;
+}
+
+// Tile-size table: one "layout log2n nnz_per_row nrhs precision tile" line per entry.
+naj_status naj_tune_save(const char* path) {
+  if (!path) return fail(NAJ_EINVAL, "path is NULL");
+  FILE* f = fopen(path, "w");
+  if (!f) return fail(NAJ_EINVAL, "cannot write %s", path);
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  for (const auto& kv : g_tune)
+    fprintf(f, "%d %d %d %d %d %d\n", kv.first.layout, kv.first.log2n, kv.first.nnz_row, kv.first.nrhs,
+            kv.first.precision, kv.second);
+  fclose(f);
+  return NAJ_OK;
+}
+
+naj_status naj_tune_load(const char* path) {
+  if (!path) return fail(NAJ_EINVAL, "path is NULL");
+  FILE* f = fopen(path, "r");
+  if (!f) return fail(NAJ_EINVAL, "cannot read %s", path);
+  TuneKey k;
+  int t = 0;
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  while (fscanf(f, "%d %d %d %d %d %d", &k.layout, &k.log2n, &k.nnz_row, &k.nrhs, &k.precision, &t) == 6)
+    if (t >= 1 && t <= 4096) g_tune[k] = t;
+  fclose(f);
   return NAJ_OK;
 }
 

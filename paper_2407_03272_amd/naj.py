@@ -67,7 +67,15 @@ _SIGS = {
     "naj_step": (ctypes.c_int, [_P, _P, _P, _D, _P, _P, _P, _P]),
     "naj_residual": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "naj_diagonal": (ctypes.c_int, [_P, _P, _P]),
+    "naj_batch_create": (ctypes.c_int, [_I32, _P, _P, ctypes.POINTER(NajOpts), _P, ctypes.POINTER(_P)]),
+    "naj_batch_solve": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    "naj_batch_info": (ctypes.c_int, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I64)]),
+    "naj_batch_destroy": (None, [_P]),
+    "naj_autotune_tiles": (ctypes.c_int, [_P, _I32, ctypes.POINTER(NajOpts), _I32, _P, ctypes.POINTER(_I32)]),
+    "naj_tune_save": (ctypes.c_int, [ctypes.c_char_p]),
+    "naj_tune_load": (ctypes.c_int, [ctypes.c_char_p]),
 }
+NAJ_MAX_RHS = 8
 
 
 def header_functions(path: str = HEADER_PATH) -> list[str]:
@@ -252,3 +260,82 @@ class System:
         with torch.cuda.device(self.device):
             _check(load().naj_diagonal(self._h, _ptr(out), _stream_ptr(stream)))
         return out
+
+
+class Batch:
+    """Many systems with several right-hand sides each, solved together (naj_batch_*).
+
+    systems: list of System; nrhs: list of ints (1..NAJ_MAX_RHS); options as in naj_opts.
+    solve(bs, x0s=None) takes per-system right-hand sides of shape (n_i, nrhs_i) (or (n_i,) when
+    nrhs_i == 1) and returns (list of x, list of per-instance SolveInfo, kernel_ms).
+    """
+
+    def __init__(self, systems, nrhs, stream=None, **opts):
+        torch = _torch()
+        self.systems = list(systems)
+        self.nrhs = [int(k) for k in nrhs]
+        self.device = self.systems[0].device
+        o = default_opts(**opts)
+        self.opts = o
+        arr = (_P * len(self.systems))(*[s._h for s in self.systems])
+        ks = (_I32 * len(self.systems))(*self.nrhs)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(load().naj_batch_create(len(self.systems), arr, ks, ctypes.byref(o), _stream_ptr(stream),
+                                           ctypes.byref(h)))
+        self._h = h
+
+    def info(self) -> dict:
+        nt, g, by = _I32(), _I32(), _I64()
+        _check(load().naj_batch_info(self._h, ctypes.byref(nt), ctypes.byref(g), ctypes.byref(by)))
+        return dict(ntiles=nt.value, grid=g.value, device_bytes=by.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().naj_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, bs, x0s=None, outs=None, stream=None):
+        torch = _torch()
+        nsys = len(self.systems)
+        bt = [self.systems[i]._dev(bs[i], torch.float64) for i in range(nsys)]
+        x0t = None if x0s is None else [None if x0s[i] is None else self.systems[i]._dev(x0s[i], torch.float64)
+                                        for i in range(nsys)]
+        xs = outs if outs is not None else [torch.empty_like(bt[i]) for i in range(nsys)]
+        bp = (_P * nsys)(*[t.data_ptr() for t in bt])
+        xp = (_P * nsys)(*[t.data_ptr() for t in xs])
+        x0p = None if x0t is None else (_P * nsys)(*[0 if t is None else t.data_ptr() for t in x0t])
+        ninst = sum(self.nrhs)
+        res = (NajResult * ninst)()
+        with torch.cuda.device(self.device):
+            st = load().naj_batch_solve(self._h, bp, x0p, xp, res, _stream_ptr(stream))
+        if st < 0 and st != NAJ_EBREAKDOWN:
+            _check(st)
+        infos = [SolveInfo(r.status, r.iterations, r.restarts, r.confirmations, r.relres, kernel_ms=r.kernel_ms,
+                           passes=r.passes, grid=r.grid) for r in res]
+        return xs, infos, (res[0].kernel_ms if ninst else 0.0)
+
+
+def autotune_tiles(system: System, nrhs: int, passes: int = 20, stream=None, **opts) -> int:
+    """naj_autotune_tiles: time tile sizes on `system` alone and record the fastest; returns it."""
+    torch = _torch()
+    o = default_opts(**opts)
+    best = _I32()
+    with torch.cuda.device(system.device):
+        _check(load().naj_autotune_tiles(system._h, int(nrhs), ctypes.byref(o), int(passes), _stream_ptr(stream),
+                                         ctypes.byref(best)))
+    return best.value
+
+
+def tune_save(path: str):
+    _check(load().naj_tune_save(path.encode()))
+
+
+def tune_load(path: str):
+    _check(load().naj_tune_load(path.encode()))

@@ -284,3 +284,92 @@ def rhs_in_range(rowptr, colidx, vals, seed: int, nrhs: int = 1) -> np.ndarray:
     rng = np.random.default_rng(seed)
     z = rng.standard_normal((n, nrhs)) if nrhs > 1 else rng.standard_normal(n)
     return np.asarray(A @ z)
+
+
+# ----------------------------------------------------------------------------
+# P1 finite-element stiffness systems (batched workload)
+# ----------------------------------------------------------------------------
+
+def _grid_simplices(m: int, dim: int) -> np.ndarray:
+    """Simplices of the regular grid with m nodes per side: 2 triangles per square (2D),
+    6 Kuhn tetrahedra per cube (3D).  Node (i0, i1[, i2]) has index i0 + m*(i1 + m*i2)."""
+    if dim == 2:
+        i, j = np.meshgrid(np.arange(m - 1), np.arange(m - 1), indexing="ij")
+        i, j = i.ravel(), j.ravel()
+        n00 = i + m * j
+        n10 = n00 + 1
+        n01 = n00 + m
+        n11 = n01 + 1
+        return np.concatenate([np.stack([n00, n10, n11], 1), np.stack([n00, n11, n01], 1)])
+    i, j, k = np.meshgrid(np.arange(m - 1), np.arange(m - 1), np.arange(m - 1), indexing="ij")
+    base = (i + m * (j + m * k)).ravel()
+    step = [1, m, m * m]
+    tets = []
+    import itertools
+    for p in itertools.permutations(range(3)):   # Kuhn: one tetrahedron per axis order
+        v0 = base
+        v1 = v0 + step[p[0]]
+        v2 = v1 + step[p[1]]
+        v3 = v2 + step[p[2]]
+        tets.append(np.stack([v0, v1, v2, v3], 1))
+    return np.concatenate(tets)
+
+
+def fe_p1_system(n_target: int, dim: int, seed: int, nrhs: int = 8, jitter: float | None = None,
+                 reaction_factor: float = 10.0) -> CsrSystem:
+    """SPD P1 stiffness system on a jittered grid of the unit square (dim 2) or cube (dim 3).
+
+    m = round(n_target^(1/dim)) nodes per side, every node an unknown (natural boundary condition).
+    Interior nodes are moved uniformly by up to jitter*h per coordinate (0.2 in 2D, 0.1 in 3D), redrawn
+    until every element has positive volume.  Per-element diffusion kappa_e = exp(Z), Z ~ N(0,1); a lumped
+    reaction term c_r = reaction_factor * mean(kappa_e) times the lumped mass makes the matrix SPD.
+    nrhs right-hand sides ~ N(0,1), row-interleaved (n x nrhs).
+    """
+    rng = np.random.default_rng(seed)
+    m = max(2, int(round(n_target ** (1.0 / dim))))
+    n = m ** dim
+    h = 1.0 / (m - 1)
+    jit = (0.2 if dim == 2 else 0.1) if jitter is None else jitter
+    axes = np.meshgrid(*[np.linspace(0.0, 1.0, m)] * dim, indexing="ij")
+    # node index i0 + m*i1 (+ m^2 i2): first axis fastest
+    X = np.stack([a.transpose(tuple(reversed(range(dim)))).ravel() for a in axes], 1)
+    X = np.stack([X[:, k] for k in range(dim)], 1)
+    coords = [np.arange(n) // (m ** k) % m for k in range(dim)]
+    X = np.stack([c * h for c in coords], 1)
+    interior = np.all([(c > 0) & (c < m - 1) for c in coords], axis=0)
+    T = _grid_simplices(m, dim)
+    for _ in range(20):
+        Xj = X.copy()
+        Xj[interior] += rng.uniform(-jit * h, jit * h, size=(int(interior.sum()), dim))
+        A = np.concatenate([np.ones((T.shape[0], dim + 1, 1)), Xj[T]], axis=2)
+        det = np.linalg.det(A)
+        if np.all(det > 0) or np.all(det < 0):
+            break
+    else:
+        Xj = X
+        A = np.concatenate([np.ones((T.shape[0], dim + 1, 1)), Xj[T]], axis=2)
+        det = np.linalg.det(A)
+    vol = np.abs(det) / (1.0 if dim == 1 else (2.0 if dim == 2 else 6.0))
+    grads = np.linalg.inv(A)[:, 1:, :]                 # (E, dim, dim+1): gradient of each barycentric function
+    kappa = np.exp(rng.standard_normal(T.shape[0]))
+    Ke = np.einsum("e,eki,ekj->eij", kappa * vol, grads, grads)
+    rows = np.repeat(T, dim + 1, axis=1).ravel()
+    cols = np.tile(T, (1, dim + 1)).ravel()
+    K = sp.coo_matrix((Ke.ravel(), (rows, cols)), shape=(n, n)).tocsr()
+    lumped = np.bincount(T.ravel(), weights=np.repeat(vol / (dim + 1), dim + 1), minlength=n)
+    K = (K + sp.diags(reaction_factor * kappa.mean() * lumped)).tocsr()
+    K.sum_duplicates()
+    K.sort_indices()
+    b = rng.standard_normal((n, nrhs)) if nrhs > 1 else rng.standard_normal(n)
+    return CsrSystem(K.indptr.astype(np.int32), K.indices.astype(np.int32), K.data.astype(np.float64), b, None,
+                     f"fe{dim}d_n{n}", {"dim": dim, "m": m, "n": n, "seed": seed})
+
+
+def fe_batch(nsys: int = 512, n_lo: float = 1e3, n_hi: float = 2e5, seed: int = 1004, nrhs: int = 8):
+    """Sizes log-uniform in [n_lo, n_hi], dimension 2 or 3 with probability 1/2 each; one seed per system."""
+    rng = np.random.default_rng(seed)
+    sizes = np.exp(rng.uniform(np.log(n_lo), np.log(n_hi), nsys))
+    dims = rng.integers(2, 4, nsys)
+    seeds = rng.integers(0, 2 ** 31 - 1, nsys)
+    for k in range(nsys):
+        yield fe_p1_system(int(sizes[k]), int(dims[k]), int(seeds[k]), nrhs=nrhs)
