@@ -112,6 +112,129 @@ def cpu_baseline(sysobj, iterations_needed: int, sample_iters: int) -> dict:
                       f"scaled to one full solve"}
 
 
+def bench_fe_batch(args, progress):
+    """512 P1 finite-element systems (2D/3D, n log-uniform in [1e3, 2e5], lognormal coefficients), 8 right-hand
+    sides each, solved together in mixed precision by graph-replayed batch passes with autotuned tiles.
+    One step = the whole batch (4096 solves).  Compared with the same batch in float64 and with plain float64
+    one-system-at-a-time solves (a sample of them, scaled)."""
+    import torch
+    from paper_2407_03272_amd import naj
+    from paper_2407_03272_amd import workloads as W
+
+    nrhs = 8
+    systems = W.fe_batch(args.nsys, nrhs=nrhs, workers=min(8, os.cpu_count() or 1))
+    progress(f"generated {len(systems)} systems, sum n = {sum(x.n for x in systems)}, "
+             f"sum nnz = {sum(x.nnz for x in systems)}")
+    syss = [naj.System(x.rowptr, x.colidx, x.vals) for x in systems]
+    progress("systems created")
+    reps = {}
+    for x, sm in zip(systems, syss):
+        key = (sm.info()["layout"], int(np.log2(x.n)), int(round(x.nnz / x.n)))
+        reps.setdefault(key, sm)
+    prec = naj.NAJ_MIXED if args.precision == "mixed" else naj.NAJ_FP64
+    tiles = {}
+    for key, sm in sorted(reps.items()):
+        tiles[str(key)] = naj.autotune_tiles(sm, nrhs, passes=20, precision=prec)
+    progress(f"autotuned {len(reps)} feature keys")
+    bs = [torch.as_tensor(x.b).cuda() for x in systems]
+
+    def run_batch(precision, steps, warmup):
+        bt = naj.Batch(syss, [nrhs] * len(syss), tol=1e-8, max_iter=20000, precision=precision)
+        outs = [torch.empty_like(b) for b in bs]
+        for _ in range(warmup):
+            t0 = time.perf_counter()
+            _, winf, _ = bt.solve(bs, outs=outs)
+            progress(f"warm-up batch solve ({'mixed' if precision == naj.NAJ_MIXED else 'fp64'}): "
+                     f"{time.perf_counter() - t0:.2f} s, max iterations {max(i.iterations for i in winf)}")
+        torch.cuda.synchronize()
+        times, kms = [], []
+        t_all = time.perf_counter()
+        for _ in range(steps):
+            t0 = time.perf_counter()
+            _, infos, ms = bt.solve(bs, outs=outs)
+            times.append(time.perf_counter() - t0)
+            kms.append(ms)
+            progress(f"batch solve: {times[-1]:.2f} s")
+            bad = [i.status for i in infos if i.status != 0]
+            if bad:
+                raise SystemExit(f"batch: {len(bad)} instances did not converge")
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t_all
+        info = bt.info()
+        bt.close()
+        return total, times, kms, infos, info
+
+    total, times, kms, infos, binfo = run_batch(prec, args.steps, args.warmup)
+    ninst = len(infos)
+    progress(f"batch: {total / args.steps * 1e3:.1f} ms per {ninst} solves")
+    # algorithmic bytes: matrix once per system pass, vectors per instance pass
+    alg = 0
+    for i, x in enumerate(systems):
+        inf = infos[i * nrhs:(i + 1) * nrhs]
+        n, nnz = x.n, x.nnz
+        if prec == naj.NAJ_MIXED:
+            alg += max(v.iterations for v in inf) * (8 * nnz + 4 * (n + 1))
+            alg += max(v.confirmations for v in inf) * (12 * nnz + 4 * (n + 1))
+            alg += sum(v.iterations * 16 * n + v.confirmations * 32 * n + 8 * n for v in inf)
+        else:
+            alg += max(v.passes for v in inf) * (12 * nnz + 4 * (n + 1))
+            alg += sum(v.passes * 32 * n for v in inf)
+    kernel_s = float(np.mean(kms)) / 1e3
+    achieved = alg / kernel_s / 1e9
+    line = {
+        "metric": "solves/s + HBM GB/s at relres 1e-8 vs plain FP64; p50/p99 solve latency",
+        "value": ninst * args.steps / total,
+        "unit": "solves/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": total / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if prec == naj.NAJ_MIXED else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{len(systems)} P1 finite-element systems (2D/3D, n log-uniform 1e3..2e5, seed 1004) x "
+                               f"{nrhs} right-hand sides, one batch of graph-replayed passes, autotuned tiles, "
+                               f"{'float32 inner + float64 refinement' if prec == naj.NAJ_MIXED else 'float64'}, "
+                               f"relres <= 1e-8 per solve; one step = all {ninst} solves",
+                   "systems": len(systems), "nrhs": nrhs, "sum_n": int(sum(x.n for x in systems)),
+                   "sum_nnz": int(sum(x.nnz for x in systems)), "tiles": binfo["ntiles"], "grid": binfo["grid"],
+                   "tile_table": tiles,
+                   "iterations_min_median_max": [int(np.min([i.iterations for i in infos])),
+                                                 int(np.median([i.iterations for i in infos])),
+                                                 int(np.max([i.iterations for i in infos]))]},
+        "p50_ms": float(np.percentile(times, 50) * 1e3),
+        "p99_ms": float(np.percentile(times, 99) * 1e3),
+        "kernel_ms": float(np.mean(kms)),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_batch_pass (one launch per batch pass, graph-replayed)",
+                     "algorithmic_bytes_per_batch_solve": alg},
+    }
+    if not args.no_compare:
+        other = naj.NAJ_FP64 if prec == naj.NAJ_MIXED else naj.NAJ_MIXED
+        ctot, ctimes, ckms, cinfos, _ = run_batch(other, max(2, args.steps // 2), 1)
+        line["compare_batch"] = {"precision": "fp64" if other == naj.NAJ_FP64 else "mixed",
+                                 "solves_per_s": ninst * len(ctimes) / ctot,
+                                 "ms_per_batch": ctot / len(ctimes) * 1e3}
+        progress("batch comparison done")
+        # plain float64, one system and one right-hand side at a time (every 16th system, all 8 rhs)
+        sample = list(range(0, len(systems), 16))
+        t0 = time.perf_counter()
+        nsol = 0
+        for i in sample:
+            for j in range(nrhs):
+                bj = bs[i][:, j].contiguous()
+                _, inf = syss[i].solve(bj, tol=1e-8, max_iter=20000, hist_cap=0)
+                nsol += 1
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        # scale the sample to the whole batch by the sampled systems' share of rows
+        share = sum(systems[i].n for i in sample) / sum(x.n for x in systems)
+        line["compare_one_at_a_time"] = {"precision": "fp64", "sampled_solves": nsol,
+                                         "sample_seconds": dt,
+                                         "solves_per_s_est": ninst / (dt / share)}
+        progress("one-at-a-time comparison done")
+    return line
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +244,7 @@ def main():
     ap.add_argument("--cpu-sample-iters", type=int, default=200)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--no-compare", action="store_true", help="skip the second-precision comparison solves")
+    ap.add_argument("--nsys", type=int, default=512, help="systems in the fe_batch workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pmc-sample", action="store_true",
                     help="run only a 1 GiB torch copy (counter calibration) and a 50-iteration solve, for rocprofv3 --pmc")
@@ -136,6 +260,11 @@ def main():
     def progress(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
+    if args.workload == "fe_batch":
+        if args.precision == "fp64" and "--precision" not in sys.argv:
+            args.precision = "mixed"
+        print(json.dumps(bench_fe_batch(args, progress)), flush=True)
+        return
     sysobj = make_workload(args.workload)
     n, nnz = sysobj.n, sysobj.nnz
     progress(f"workload {sysobj.name}: n={n} nnz={nnz}")

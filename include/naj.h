@@ -62,7 +62,8 @@ typedef struct naj_opts {
     int32_t precision;      /* NAJ_FP64 or NAJ_MIXED; default NAJ_FP64                                 */
     double  inner_tol;      /* mixed: inner stop ||Q y - r|| / ||r|| <= inner_tol; default 1e-4        */
     int32_t max_refine;     /* mixed: maximum float64 refinement steps; default 50                     */
-    int32_t reserved;       /* must be 0                                                               */
+    int32_t inner_stall;    /* mixed: an inner solve also stops when its monitor has not fallen below  */
+                            /* 0.9 x its best value for this many iterations (>= 1); default 200       */
 } naj_opts;
 
 /* Per-right-hand-side result of a solve (host struct). */

@@ -223,15 +223,18 @@ class MixedResult:
 
 
 def inner_solve_fp32(Q32: sp.csr_matrix, dinv32: np.ndarray, r32: np.ndarray, *, inner_tol: float,
-                     max_iter: int, restart: bool, k0: int):
+                     max_iter: int, restart: bool, k0: int, stall: int = 200):
     """Algorithm 3 on Q d = r in float32 from d^0 = 0 with float64 reductions.
 
     The product, the Jacobi-type step and the momentum step are float32
     operations (float32 accumulation in the row sums; the momentum coefficient
     rounded to float32).  The restart inner product and the monitor norm are
     accumulated in float64 from the exactly converted float32 operands.  The
-    solve stops when ||Q y^t - r|| / ||r|| <= inner_tol and returns x^t, or
-    returns the last iterate after ``max_iter`` iterations.
+    solve stops when ||Q y^t - r|| / ||r|| <= inner_tol and returns x^t; or
+    when that monitor has not fallen below 0.9 times its best value for
+    ``stall`` iterations (float32 rounding of the row sums bounds how far the
+    float32 residual can fall, about eps32 times the condition number) and
+    returns x^t; or returns the last iterate after ``max_iter`` iterations.
     Returns (d, iterations, restarts, finite).
     """
     n = Q32.shape[0]
@@ -243,6 +246,7 @@ def inner_solve_fp32(Q32: sp.csr_matrix, dinv32: np.ndarray, r32: np.ndarray, *,
     alpha = 1.0
     K_re, K = 0, int(k0)
     restarts = []
+    best, best_t = math.inf, 0
     for t in range(1, max_iter + 1):
         u = Q32 @ y
         g = (u - r32).astype(f32)
@@ -254,6 +258,10 @@ def inner_solve_fp32(Q32: sp.csr_matrix, dinv32: np.ndarray, r32: np.ndarray, *,
         if not (math.isfinite(mon) and math.isfinite(s)):
             return x_prev, t, restarts, False
         if mon <= inner_tol:
+            return x, t, restarts, True
+        if mon <= 0.9 * best:
+            best, best_t = mon, t
+        if stall > 0 and t - best_t >= stall:
             return x, t, restarts, True
         if restart and t > K_re + K and s >= 0.0:
             K_re, K = t, 2 * K
@@ -271,7 +279,7 @@ def inner_solve_fp32(Q32: sp.csr_matrix, dinv32: np.ndarray, r32: np.ndarray, *,
 
 def accelerated_jacobi_mixed(rowptr, colidx, vals, b, x0=None, *, tol: float = 1e-8, max_refine: int = 50,
                              inner_tol: float = 1e-4, inner_max_iter: int = 20000, restart: bool = True,
-                             k0: int = 2, D: np.ndarray | None = None) -> MixedResult:
+                             k0: int = 2, D: np.ndarray | None = None, inner_stall: int = 200) -> MixedResult:
     """Float32 inner Algorithm 3 inside float64 iterative refinement.
 
     Outer step k = 0, 1, ...: r_k = b - Q x_k with float64 values and
@@ -313,7 +321,7 @@ def accelerated_jacobi_mixed(rowptr, colidx, vals, b, x0=None, *, tol: float = 1
         if k == max_refine or not np.any(r32):
             break
         d, it, rs, finite = inner_solve_fp32(Q32, dinv32, r32, inner_tol=inner_tol, max_iter=inner_max_iter,
-                                             restart=restart, k0=k0)
+                                             restart=restart, k0=k0, stall=inner_stall)
         out.inner_total += it
         out.inner_iters.append(it)
         out.inner_restarts.append(rs)

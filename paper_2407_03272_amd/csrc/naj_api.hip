@@ -476,7 +476,7 @@ naj_status check_opts(const naj_opts& o) {
     if (!(o.inner_tol > 0.0 && o.inner_tol < 1.0)) return fail(NAJ_EINVAL, "inner_tol must be in (0,1)");
     if (o.max_refine < 1) return fail(NAJ_EINVAL, "max_refine must be >= 1");
   }
-  if (o.reserved != 0) return fail(NAJ_EINVAL, "reserved field must be 0");
+  if (o.inner_stall < 1) return fail(NAJ_EINVAL, "inner_stall must be >= 1 (got %d)", o.inner_stall);
   return NAJ_OK;
 }
 
@@ -505,6 +505,7 @@ SolveArgs make_args(naj_system* s, const double* b, const naj_opts& o) {
   a.k0 = o.k0;
   a.precision = o.precision == NAJ_MIXED ? 1 : 0;
   a.max_refine = o.max_refine;
+  a.inner_stall = o.inner_stall;
   a.inner_tol = o.inner_tol;
   a.f0 = s->fvec[0];
   a.f1 = s->fvec[1];
@@ -893,6 +894,7 @@ naj_status batch_build(naj_batch* bt, hipStream_t st) {
   A.k0 = o.k0;
   A.precision = mixed ? 1 : 0;
   A.max_refine = o.max_refine;
+  A.inner_stall = o.inner_stall;
   // a chunk of passes captured once as a graph and replayed
   if (bt->exec) {
     (void)hipGraphExecDestroy(bt->exec);
@@ -925,7 +927,7 @@ void naj_opts_default(naj_opts* o) {
   o->precision = NAJ_FP64;
   o->inner_tol = 1e-4;
   o->max_refine = 50;
-  o->reserved = 0;
+  o->inner_stall = 200;
 }
 
 const char* naj_last_error(void) { return g_err.c_str(); }

@@ -59,6 +59,7 @@ struct BatchArgs {
   int k0;
   int precision;
   int max_refine;
+  int inner_stall;
 };
 
 __device__ __forceinline__ SolveArgs batch_args(const BatchArgs& ba, const BatchSys& S, const BatchInst& I) {
@@ -87,6 +88,7 @@ __device__ __forceinline__ SolveArgs batch_args(const BatchArgs& ba, const Batch
   a.spin_ticks = 0;
   a.precision = ba.precision;
   a.max_refine = ba.max_refine;
+  a.inner_stall = ba.inner_stall;
   a.inner_tol = ba.inner_tol;
   a.f0 = I.f[0];
   a.f1 = I.f[1];

@@ -81,6 +81,8 @@ struct Ctrl {
   int inner_total;       // inner iterations summed over refinement steps
   int inner_restarts;    // inner restarts summed
   double nr;             // ||fl32(r)||_2 of the current inner right-hand side
+  double best_mon;       // inner solve: best monitor value so far (for the stall rule)
+  int best_t;            // inner solve: iteration of that value
   int restart_log[kRestartLogCap];
 };
 
@@ -141,6 +143,7 @@ struct SolveArgs {
   // mixed precision
   int precision;              // 0 float64, 1 float32 inner solve + float64 refinement
   int max_refine;
+  int inner_stall;
   double inner_tol;
   float* f0;                  // three float32 inner iterates
   float* f1;

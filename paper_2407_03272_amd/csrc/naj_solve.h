@@ -127,6 +127,8 @@ __device__ inline void mixed_after_residual(const SolveArgs& a, Ctrl* c, double 
   c->beta = 0.0;
   c->beta_zero = 1;
   c->zp = 1;
+  c->best_mon = __builtin_inf();
+  c->best_t = 0;
   c->K_re = 0;
   c->K = a.k0;
   c->ell = 0;
@@ -170,6 +172,14 @@ __device__ inline void mixed_after_inner(const SolveArgs& a, Ctrl* c, double s, 
   }
   if (mon <= a.inner_tol) {
     mixed_finish_inner(a, c, c->iW, t);     // d = x^t
+    return;
+  }
+  if (mon <= 0.9 * c->best_mon) {
+    c->best_mon = mon;
+    c->best_t = t;
+  }
+  if (a.inner_stall > 0 && t - c->best_t >= a.inner_stall) {
+    mixed_finish_inner(a, c, c->iW, t);     // stalled at the float32 rounding level: d = x^t
     return;
   }
   const bool restart = a.restart && (t > c->K_re + c->K) && (s >= 0.0);

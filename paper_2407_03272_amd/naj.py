@@ -38,7 +38,7 @@ class NajError(RuntimeError):
 class NajOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("restart", ctypes.c_int32),
                 ("k0", ctypes.c_int32), ("confirm_gap", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int32), ("inner_stall", ctypes.c_int32)]
 
 
 class NajResult(ctypes.Structure):

@@ -330,29 +330,25 @@ def fe_p1_system(n_target: int, dim: int, seed: int, nrhs: int = 8, jitter: floa
     n = m ** dim
     h = 1.0 / (m - 1)
     jit = (0.2 if dim == 2 else 0.1) if jitter is None else jitter
-    axes = np.meshgrid(*[np.linspace(0.0, 1.0, m)] * dim, indexing="ij")
-    # node index i0 + m*i1 (+ m^2 i2): first axis fastest
-    X = np.stack([a.transpose(tuple(reversed(range(dim)))).ravel() for a in axes], 1)
-    X = np.stack([X[:, k] for k in range(dim)], 1)
     coords = [np.arange(n) // (m ** k) % m for k in range(dim)]
     X = np.stack([c * h for c in coords], 1)
     interior = np.all([(c > 0) & (c < m - 1) for c in coords], axis=0)
     T = _grid_simplices(m, dim)
+    ones = np.ones((T.shape[0], dim + 1, 1))
+    ref_sign = np.sign(np.linalg.det(np.concatenate([ones, X[T]], axis=2)))   # orientation of each grid simplex
     for _ in range(20):
         Xj = X.copy()
         Xj[interior] += rng.uniform(-jit * h, jit * h, size=(int(interior.sum()), dim))
-        A = np.concatenate([np.ones((T.shape[0], dim + 1, 1)), Xj[T]], axis=2)
+        A = np.concatenate([ones, Xj[T]], axis=2)
         det = np.linalg.det(A)
-        if np.all(det > 0) or np.all(det < 0):
+        if np.all(np.sign(det) == ref_sign):          # no element inverted or degenerate
             break
     else:
-        Xj = X
-        A = np.concatenate([np.ones((T.shape[0], dim + 1, 1)), Xj[T]], axis=2)
-        det = np.linalg.det(A)
+        raise RuntimeError("could not jitter the grid without inverting an element")
     vol = np.abs(det) / (1.0 if dim == 1 else (2.0 if dim == 2 else 6.0))
     grads = np.linalg.inv(A)[:, 1:, :]                 # (E, dim, dim+1): gradient of each barycentric function
     kappa = np.exp(rng.standard_normal(T.shape[0]))
-    Ke = np.einsum("e,eki,ekj->eij", kappa * vol, grads, grads)
+    Ke = (kappa * vol)[:, None, None] * (grads.transpose(0, 2, 1) @ grads)
     rows = np.repeat(T, dim + 1, axis=1).ravel()
     cols = np.tile(T, (1, dim + 1)).ravel()
     K = sp.coo_matrix((Ke.ravel(), (rows, cols)), shape=(n, n)).tocsr()
@@ -365,11 +361,27 @@ def fe_p1_system(n_target: int, dim: int, seed: int, nrhs: int = 8, jitter: floa
                      f"fe{dim}d_n{n}", {"dim": dim, "m": m, "n": n, "seed": seed})
 
 
-def fe_batch(nsys: int = 512, n_lo: float = 1e3, n_hi: float = 2e5, seed: int = 1004, nrhs: int = 8):
-    """Sizes log-uniform in [n_lo, n_hi], dimension 2 or 3 with probability 1/2 each; one seed per system."""
+def fe_batch_specs(nsys: int = 512, n_lo: float = 1e3, n_hi: float = 2e5, seed: int = 1004):
+    """(n_target, dim, seed) of each batch member: sizes log-uniform in [n_lo, n_hi], dimension 2 or 3 with
+    probability 1/2 each, one seed per system."""
     rng = np.random.default_rng(seed)
     sizes = np.exp(rng.uniform(np.log(n_lo), np.log(n_hi), nsys))
     dims = rng.integers(2, 4, nsys)
     seeds = rng.integers(0, 2 ** 31 - 1, nsys)
-    for k in range(nsys):
-        yield fe_p1_system(int(sizes[k]), int(dims[k]), int(seeds[k]), nrhs=nrhs)
+    return [(int(sizes[k]), int(dims[k]), int(seeds[k])) for k in range(nsys)]
+
+
+def _fe_from_spec(args):
+    n, d, sd, nrhs = args
+    return fe_p1_system(n, d, sd, nrhs=nrhs)
+
+
+def fe_batch(nsys: int = 512, n_lo: float = 1e3, n_hi: float = 2e5, seed: int = 1004, nrhs: int = 8,
+             workers: int = 1):
+    """The batch members of fe_batch_specs, built in order (in `workers` processes when > 1)."""
+    specs = [(n, d, sd, nrhs) for n, d, sd in fe_batch_specs(nsys, n_lo, n_hi, seed)]
+    if workers <= 1:
+        return [_fe_from_spec(a) for a in specs]
+    from concurrent.futures import ProcessPoolExecutor
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(_fe_from_spec, specs, chunksize=4))

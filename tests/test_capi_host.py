@@ -21,7 +21,7 @@ def test_library_exports_every_declared_symbol():
 def test_opts_defaults_and_struct_layout():
     o = naj.default_opts()
     assert o.tol == 1e-8 and o.max_iter == 20000 and o.restart == 1 and o.k0 == 2
-    assert o.confirm_gap == 8 and o.precision == naj.NAJ_FP64 and o.reserved == 0
+    assert o.confirm_gap == 8 and o.precision == naj.NAJ_FP64 and o.inner_stall == 200
     assert ctypes.sizeof(naj.NajOpts) == 48
     assert ctypes.sizeof(naj.NajResult) == 48
 
