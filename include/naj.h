@@ -62,8 +62,9 @@ typedef struct naj_opts {
     int32_t precision;      /* NAJ_FP64 or NAJ_MIXED; default NAJ_FP64                                 */
     double  inner_tol;      /* mixed: inner stop ||Q y - r|| / ||r|| <= inner_tol; default 1e-4        */
     int32_t max_refine;     /* mixed: maximum float64 refinement steps; default 50                     */
-    int32_t inner_stall;    /* mixed: an inner solve also stops when its monitor has not fallen below  */
-                            /* 0.9 x its best value for this many iterations (>= 1); default 200       */
+    int32_t inner_stall;    /* mixed: once an inner monitor has fallen to <= 1/2, the inner solve also */
+                            /* stops when the monitor has not fallen below 0.9 x its best value for    */
+                            /* this many iterations (the float32 rounding floor); >= 1; default 200    */
 } naj_opts;
 
 /* Per-right-hand-side result of a solve (host struct). */

@@ -58,6 +58,9 @@ STATUS_OK = 0
 STATUS_NOT_CONVERGED = 1
 STATUS_BREAKDOWN = -4
 
+# The stall test of the float32 inner solve applies once its monitor has halved.
+STALL_ARM = 0.5
+
 
 def csr(rowptr, colidx, vals, dtype=np.float64) -> sp.csr_matrix:
     n = len(rowptr) - 1
@@ -230,11 +233,16 @@ def inner_solve_fp32(Q32: sp.csr_matrix, dinv32: np.ndarray, r32: np.ndarray, *,
     operations (float32 accumulation in the row sums; the momentum coefficient
     rounded to float32).  The restart inner product and the monitor norm are
     accumulated in float64 from the exactly converted float32 operands.  The
-    solve stops when ||Q y^t - r|| / ||r|| <= inner_tol and returns x^t; or
-    when that monitor has not fallen below 0.9 times its best value for
-    ``stall`` iterations (float32 rounding of the row sums bounds how far the
-    float32 residual can fall, about eps32 times the condition number) and
-    returns x^t; or returns the last iterate after ``max_iter`` iterations.
+    solve stops when ||Q y^t - r|| / ||r|| <= inner_tol and returns x^t; or,
+    once the recorded best monitor value is <= STALL_ARM, when the monitor has
+    not fallen below 0.9 times that best value for ``stall`` iterations
+    (float32 rounding of the row sums bounds how far the float32 residual can
+    fall, about eps32 times the condition number) and returns x^t; or returns
+    the last iterate after ``max_iter`` iterations.  The best value is updated
+    only when the monitor falls to 0.9 times it or below.  Before the monitor
+    has halved, a plateau is the slow start of the method on a smooth
+    right-hand side (it lasts about the square root of the condition number),
+    not the float32 floor, so the stall test is not applied.
     Returns (d, iterations, restarts, finite).
     """
     n = Q32.shape[0]
@@ -261,7 +269,7 @@ def inner_solve_fp32(Q32: sp.csr_matrix, dinv32: np.ndarray, r32: np.ndarray, *,
             return x, t, restarts, True
         if mon <= 0.9 * best:
             best, best_t = mon, t
-        if stall > 0 and t - best_t >= stall:
+        if stall > 0 and best <= STALL_ARM and t - best_t >= stall:
             return x, t, restarts, True
         if restart and t > K_re + K and s >= 0.0:
             K_re, K = t, 2 * K

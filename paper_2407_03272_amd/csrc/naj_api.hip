@@ -734,12 +734,15 @@ struct naj_batch {
   std::vector<int> nrhs, inst0;
   naj_opts opts;
   BatchSys* d_sys = nullptr;
-  BatchInst* d_inst = nullptr;
   BatchTile* d_tiles = nullptr;
-  unsigned int* d_counters = nullptr;   // per system, 64-word stride; the done counter after them
+  int* d_active = nullptr;              // active item list [ntiles] and its length
+  int* d_nactive = nullptr;
+  int* d_sact = nullptr;                // active system list [nsys] and its length
+  int* d_nsact = nullptr;
+  PassView* d_vt = nullptr;             // pass views, kMaxRhs per system
   unsigned int* d_done = nullptr;
   Ctrl* d_ctrl = nullptr;
-  std::vector<BatchInst> h_inst;
+  std::vector<BatchSys> h_sys;          // host copy of the per-system records (device pointers)
   std::vector<void*> bufs;
   unsigned int* hdone = nullptr;        // pinned, 2 slots
   hipStream_t cap = nullptr;
@@ -770,10 +773,10 @@ TuneKey tune_key(const naj_system* s, int nrhs, int precision) {
   return TuneKey{s->layout, l2, (int)((s->nnz + s->n / 2) / s->n), nrhs, precision};
 }
 
-// Slices per tile for a system: the tuned value if one is recorded for its features,
-// else a default of 16 (four slices per wave), never more than the system has.
+// Slices per item (one wavefront's unit of work) for a system: the tuned value if one is
+// recorded for its features, else a default of 2, never more than the system has.
 int tile_slices_for(const naj_system* s, int nrhs, int precision) {
-  int t = 16;
+  int t = 2;
   {
     std::lock_guard<std::mutex> g(g_tune_mu);
     auto it = g_tune.find(tune_key(s, nrhs, precision));
@@ -814,7 +817,8 @@ naj_status batch_alloc(naj_batch* bt, T** p, size_t count) {
 naj_status batch_build(naj_batch* bt, hipStream_t st) {
   const naj_opts& o = bt->opts;
   const bool mixed = o.precision == NAJ_MIXED;
-  std::vector<BatchSys> hs(bt->nsys);
+  std::vector<BatchSys>& hs = bt->h_sys;
+  hs.assign(bt->nsys, BatchSys{});
   std::vector<BatchTile> ht;
   bt->ninst = 0;
   bt->inst0.assign(bt->nsys, 0);
@@ -827,13 +831,14 @@ naj_status batch_build(naj_batch* bt, hipStream_t st) {
     S.A = sell_of(s);
     S.A.dom_bounds = nullptr;
     S.dinv = s->dinv;
-    S.inst0 = bt->ninst;
-    S.ninst = bt->nrhs[i];
+    S.nrhs = bt->nrhs[i];
+    S.lk = 0;
+    while ((1 << S.lk) < S.nrhs) ++S.lk;
     S.tile0 = (int)ht.size();
     S.ymode = s->ymode;
     bt->inst0[i] = bt->ninst;
     bt->ninst += bt->nrhs[i];
-    const int lt = 32;   // long rows per tile
+    const int lt = 4;   // long rows per item
     for (int64_t l = 0; l < s->n_long; l += lt)
       ht.push_back(BatchTile{i, 0, 0, (int)l, (int)std::min<int64_t>(s->n_long, l + lt)});
     for (int64_t sl = 0; sl < s->nslices; sl += T)
@@ -844,48 +849,54 @@ naj_status batch_build(naj_batch* bt, hipStream_t st) {
   bt->ntiles = (int)ht.size();
   naj_status rc = NAJ_OK;
   if ((rc = batch_alloc(bt, &bt->d_sys, (size_t)bt->nsys)) != NAJ_OK) return rc;
-  if ((rc = batch_alloc(bt, &bt->d_inst, (size_t)bt->ninst)) != NAJ_OK) return rc;
   if ((rc = batch_alloc(bt, &bt->d_tiles, (size_t)bt->ntiles)) != NAJ_OK) return rc;
-  if ((rc = batch_alloc(bt, &bt->d_counters, (size_t)(bt->nsys + 1) * 64)) != NAJ_OK) return rc;
+  if ((rc = batch_alloc(bt, &bt->d_active, (size_t)bt->ntiles)) != NAJ_OK) return rc;
+  if ((rc = batch_alloc(bt, &bt->d_nactive, (size_t)64)) != NAJ_OK) return rc;
+  if ((rc = batch_alloc(bt, &bt->d_sact, (size_t)bt->nsys)) != NAJ_OK) return rc;
+  if ((rc = batch_alloc(bt, &bt->d_nsact, (size_t)64)) != NAJ_OK) return rc;
+  if ((rc = batch_alloc(bt, &bt->d_done, (size_t)64)) != NAJ_OK) return rc;
+  if ((rc = batch_alloc(bt, &bt->d_vt, (size_t)bt->nsys * kMaxRhs)) != NAJ_OK) return rc;
   if ((rc = batch_alloc(bt, &bt->d_ctrl, (size_t)bt->ninst)) != NAJ_OK) return rc;
-  bt->d_done = bt->d_counters + (size_t)bt->nsys * 64;
-  bt->h_inst.assign(bt->ninst, BatchInst{});
   for (int i = 0; i < bt->nsys; ++i) {
     naj_system* s = bt->systems[i];
-    hs[i].counter = bt->d_counters + (size_t)i * 64;
-    for (int j = 0; j < bt->nrhs[i]; ++j) {
-      BatchInst& I = bt->h_inst[bt->inst0[i] + j];
-      I.ctrl = bt->d_ctrl + bt->inst0[i] + j;
-      for (int q = 0; q < 4; ++q) {
-        I.x[q] = nullptr;
-        if (q < 3 + s->ymode && (rc = batch_alloc(bt, &I.x[q], (size_t)s->n)) != NAJ_OK) return rc;
-      }
-      for (int q = 0; q < 5; ++q) {
-        I.f[q] = nullptr;
-        if (mixed && (q != 3 || s->ymode) && (rc = batch_alloc(bt, &I.f[q], (size_t)s->n)) != NAJ_OK) return rc;
-      }
-      if ((rc = batch_alloc(bt, &I.b, (size_t)s->n)) != NAJ_OK) return rc;
-      if ((rc = batch_alloc(bt, &I.part, (size_t)kPartStride * hs[i].ntiles)) != NAJ_OK) return rc;
-    }
+    BatchSys& S = hs[i];
+    const size_t nv = (size_t)s->n << S.lk;
+    S.ctrl = bt->d_ctrl + bt->inst0[i];
+    S.vt = bt->d_vt + (size_t)i * kMaxRhs;
+    // every byte offset into the vector blocks must fit 32 bits
+    if (nv * sizeof(double) * 4 >= (1ull << 32))
+      return fail(NAJ_EINVAL, "system %d: n x right-hand sides too large for a batch (solve it alone)", i);
+    S.xs = (uint32_t)(nv * sizeof(double));
+    S.fs = (uint32_t)(nv * sizeof(float));
+    S.xb = nullptr;
+    S.fb = nullptr;
+    if ((rc = batch_alloc(bt, &S.xb, nv * (3 + s->ymode))) != NAJ_OK) return rc;
+    if (mixed && (rc = batch_alloc(bt, &S.fb, nv * 5)) != NAJ_OK) return rc;
+    if ((rc = batch_alloc(bt, &S.b, nv)) != NAJ_OK) return rc;
+    if ((rc = batch_alloc(bt, &S.part, (size_t)kPartStride * S.ntiles * S.nrhs)) != NAJ_OK) return rc;
   }
   HIP_TRY(hipMemcpyAsync(bt->d_sys, hs.data(), sizeof(BatchSys) * bt->nsys, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(bt->d_inst, bt->h_inst.data(), sizeof(BatchInst) * bt->ninst, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(bt->d_tiles, ht.data(), sizeof(BatchTile) * bt->ntiles, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemsetAsync(bt->d_counters, 0, sizeof(unsigned int) * (bt->nsys + 1) * 64, st));
   HIP_TRY(hipStreamSynchronize(st));
-  // grid: every resident workgroup, at most one per tile
+  // grid: every resident workgroup, at most one wavefront per item
   int occ = 0, cus = 0;
-  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_batch_pass, kBatchBlock, 0));
+  const void* pass_fn = mixed ? (const void*)k_batch_pass<true> : (const void*)k_batch_pass<false>;
+  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, pass_fn, kBatchBlock, 0));
   hipDeviceProp_t prop;
   HIP_TRY(hipGetDeviceProperties(&prop, bt->device));
   cus = prop.multiProcessorCount;
-  bt->grid = std::max(1, std::min(bt->ntiles, std::max(1, occ) * cus));
+  occ = std::min(std::max(1, occ), std::max(1, env_int("NAJ_BATCH_WG_PER_CU", occ)));
+  bt->grid = std::max(1, std::min((bt->ntiles + kBatchWaves - 1) / kBatchWaves, occ * cus));
   BatchArgs& A = bt->args;
   A.tiles = bt->d_tiles;
-  A.ntiles = bt->ntiles;
   A.sys = bt->d_sys;
-  A.inst = bt->d_inst;
+  A.nsys = bt->nsys;
+  A.active = bt->d_active;
+  A.nactive = bt->d_nactive;
+  A.sact = bt->d_sact;
+  A.nsact = bt->d_nsact;
   A.done = bt->d_done;
+  A.nxcd = std::max(1, std::min(kMaxDomains, env_int("NAJ_NXCD", (cus % 8 == 0) ? 8 : 1)));
   A.tol = o.tol;
   A.inner_tol = o.inner_tol;
   A.max_iter = o.max_iter;
@@ -895,7 +906,8 @@ naj_status batch_build(naj_batch* bt, hipStream_t st) {
   A.precision = mixed ? 1 : 0;
   A.max_refine = o.max_refine;
   A.inner_stall = o.inner_stall;
-  // a chunk of passes captured once as a graph and replayed
+  // a chunk of passes captured once as a graph and replayed: the active lists are rebuilt
+  // at the head of each chunk, then graph_len passes (item kernel + decision kernel) run
   if (bt->exec) {
     (void)hipGraphExecDestroy(bt->exec);
     bt->exec = nullptr;
@@ -906,8 +918,12 @@ naj_status batch_build(naj_batch* bt, hipStream_t st) {
   }
   bt->graph_len = std::max(1, env_int("NAJ_GRAPH_LEN", 8));
   HIP_TRY(hipStreamBeginCapture(bt->cap, hipStreamCaptureModeThreadLocal));
-  for (int q = 0; q < bt->graph_len; ++q)
-    hipLaunchKernelGGL(k_batch_pass, dim3(bt->grid), dim3(kBatchBlock), 0, bt->cap, bt->args);
+  hipLaunchKernelGGL(k_batch_compact, dim3(1), dim3(kCompactBlock), 0, bt->cap, bt->args);
+  for (int q = 0; q < bt->graph_len; ++q) {
+    if (mixed) hipLaunchKernelGGL(k_batch_pass<true>, dim3(bt->grid), dim3(kBatchBlock), 0, bt->cap, bt->args);
+    else hipLaunchKernelGGL(k_batch_pass<false>, dim3(bt->grid), dim3(kBatchBlock), 0, bt->cap, bt->args);
+    hipLaunchKernelGGL(k_batch_decide, dim3(bt->nsys), dim3(kDecideBlock), 0, bt->cap, bt->args);
+  }
   HIP_TRY(hipStreamEndCapture(bt->cap, &bt->graph));
   HIP_TRY(hipGraphInstantiate(&bt->exec, bt->graph, nullptr, nullptr, 0));
   return NAJ_OK;
@@ -1279,18 +1295,15 @@ naj_status naj_batch_solve(naj_batch* bt, const double* const* b, const double* 
   hipStream_t st = (hipStream_t)stream;
   HIP_TRY(hipSetDevice(bt->device));
   const naj_opts& o = bt->opts;
-  const int nthreads = std::max(bt->ninst, bt->nsys);
-  hipLaunchKernelGGL(k_batch_init, dim3((nthreads + 255) / 256), dim3(256), 0, st, bt->args, bt->nsys, bt->ninst);
+  hipLaunchKernelGGL(k_batch_init, dim3(bt->nsys), dim3(kMaxRhs), 0, st, bt->args);
   HIP_TRY(hipGetLastError());
   for (int i = 0; i < bt->nsys; ++i) {
     naj_system* s = bt->systems[i];
-    const int k = bt->nrhs[i];
-    const dim3 g1(blocks_for(s->n, kAux * 4)), b1(kAux);
-    for (int j = 0; j < k; ++j) {
-      const BatchInst& I = bt->h_inst[bt->inst0[i] + j];
-      hipLaunchKernelGGL(k_batch_load, g1, b1, 0, st, b[i], k, j, s->perm, s->n, I.b);
-      hipLaunchKernelGGL(k_batch_load, g1, b1, 0, st, x0 ? x0[i] : nullptr, k, j, s->perm, s->n, I.x[0]);
-    }
+    const BatchSys& S = bt->h_sys[i];
+    const int kp = 1 << S.lk;
+    const dim3 g1(blocks_for(s->n * kp, kAux * 4)), b1(kAux);
+    hipLaunchKernelGGL(k_batch_load, g1, b1, 0, st, b[i], S.nrhs, kp, s->perm, s->n, S.b);
+    hipLaunchKernelGGL(k_batch_load, g1, b1, 0, st, x0 ? x0[i] : nullptr, S.nrhs, kp, s->perm, s->n, S.xb);
   }
   HIP_TRY(hipGetLastError());
   // passes: graph replays, the host checking the previous replay's done count while the next runs
@@ -1327,11 +1340,8 @@ naj_status naj_batch_solve(naj_batch* bt, const double* const* b, const double* 
   for (int i = 0; i < bt->nsys; ++i) {
     naj_system* s = bt->systems[i];
     const int k = bt->nrhs[i];
-    for (int j = 0; j < k; ++j) {
-      const BatchInst& I = bt->h_inst[bt->inst0[i] + j];
-      hipLaunchKernelGGL(k_batch_store, dim3(blocks_for(s->n, kAux * 4)), dim3(kAux), 0, st, I.ctrl, I.x[0], I.x[1],
-                         I.x[2], k, j, s->perm, s->n, x[i]);
-    }
+    hipLaunchKernelGGL(k_batch_store, dim3(blocks_for(s->n * k, kAux * 4)), dim3(kAux), 0, st, bt->d_sys, i, k, s->perm,
+                       s->n, x[i]);
   }
   HIP_TRY(hipGetLastError());
   std::vector<Ctrl> hc(bt->ninst);
@@ -1371,7 +1381,7 @@ naj_status naj_autotune_tiles(naj_system* s, int32_t nrhs, const naj_opts* opts,
   o.max_iter = std::max(1, passes);
   o.tol = 1e-300;
   o.inner_tol = 1e-300 < o.inner_tol ? o.inner_tol : 1e-4;
-  const int cands[] = {4, 8, 16, 32, 64};
+  const int cands[] = {1, 2, 4, 8, 16};
   hipStream_t st = (hipStream_t)stream;
   double* dbuf = nullptr;
   HIP_TRY(hipMalloc((void**)&dbuf, sizeof(double) * s->n * nrhs * 2));

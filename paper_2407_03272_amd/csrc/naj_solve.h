@@ -21,6 +21,8 @@
 
 namespace naj {
 
+constexpr double kStallArm = 0.5;   // inner monitor level from which the stall test applies
+
 __device__ __forceinline__ double alpha_next(double alpha) { return (1.0 + sqrt(1.0 + 4.0 * alpha * alpha)) / 2.0; }
 
 // Materialized momentum form: after the roles of a pass are settled, fix the
@@ -178,7 +180,9 @@ __device__ inline void mixed_after_inner(const SolveArgs& a, Ctrl* c, double s, 
     c->best_mon = mon;
     c->best_t = t;
   }
-  if (a.inner_stall > 0 && t - c->best_t >= a.inner_stall) {
+  // the stall test applies once the monitor has halved (before that a plateau is the slow
+  // start on a smooth right-hand side, not the float32 rounding level)
+  if (a.inner_stall > 0 && c->best_mon <= kStallArm && t - c->best_t >= a.inner_stall) {
     mixed_finish_inner(a, c, c->iW, t);     // stalled at the float32 rounding level: d = x^t
     return;
   }

@@ -150,7 +150,7 @@ def test_autotune_records_a_tile_size(naj, tmp_path):
     s = W.fe_p1_system(3000, 2, 31, nrhs=4)
     sysm = naj.System(s.rowptr, s.colidx, s.vals)
     best = naj.autotune_tiles(sysm, 4, passes=20)
-    assert best in (4, 8, 16, 32, 64)
+    assert best in (1, 2, 4, 8, 16)
     path = str(tmp_path / "tiles.txt")
     naj.tune_save(path)
     text = open(path).read()
