@@ -209,7 +209,7 @@ naj_status naj_batch_info(const naj_batch *batch, int32_t *ntiles, int32_t *grid
 void naj_batch_destroy(naj_batch *batch);
 
 /*
- * Autotuner for batch tiles: times tile sizes of 4..64 slices on `sys` solved alone
+ * Autotuner for batch work items: times item sizes of 1..16 slices on `sys` solved alone
  * with `nrhs` right-hand sides for `passes` iterations, and records the fastest in a
  * process-wide table keyed by the system's features (layout, log2 n, nonzeros per
  * row, nrhs, precision); batches created afterwards use it.  *best_tile (host, may
@@ -221,6 +221,70 @@ naj_status naj_autotune_tiles(naj_system *sys, int32_t nrhs, const naj_opts *opt
 /* Save / load the tile table (text, one "layout log2n nnz_per_row nrhs precision tile" line per entry). */
 naj_status naj_tune_save(const char *path);
 naj_status naj_tune_load(const char *path);
+
+/*
+ * Serving loop (continuous batching).  A server owns a device memory budget and a
+ * fixed number of slots.  Each admitted request (one system, 1..NAJ_MAX_RHS
+ * right-hand sides, its own tolerance) occupies a slot and draws its matrix,
+ * vectors and work items from the budget; the server advances every occupied slot
+ * together, one pass of Algorithm 3 (or of the mixed refinement) per slot at a time,
+ * and a request admitted while others run joins at the next chunk of passes.  A
+ * request's result is bit-identical to the same request served alone (its work split
+ * and summation order depend only on its system).  Options other than the tolerance
+ * (precision, max_iter, restart, k0, inner_tol, max_refine, inner_stall, confirm_gap)
+ * are the server's.  One host thread drives a server; calls on one server must not
+ * overlap.
+ */
+typedef struct naj_server naj_server;
+
+/*
+ * Create a server.
+ *   mem_budget      : bytes of device memory for all requests (one allocation)
+ *   max_slots       : requests served at once, 1..65536
+ *   opts            : server options (NULL = defaults; its tol is the default request tolerance)
+ *   stream          : stream the passes run on (admission uses a stream of its own)
+ * Errors: NAJ_EINVAL, NAJ_ENOMEM (budget not allocatable), NAJ_EDEVICE.
+ */
+naj_status naj_server_create(int64_t mem_budget, int32_t max_slots, const naj_opts *opts, void *stream,
+                             naj_server **out);
+
+/*
+ * Admit a request: build its system (as naj_create_system, inside the budget) and
+ * queue its right-hand sides.  Device inputs rowptr/colidx/vals/D and b (row-interleaved
+ * n x nrhs) / x0 (may be NULL) are copied before the call returns; x (device, n x nrhs,
+ * caller-owned) receives the answer when naj_server_result is called.  tol <= 0 takes the
+ * server's.  *ticket identifies the request.
+ * Returns NAJ_EBUSY when no slot or not enough budget is free now (nothing was kept:
+ * try again after a result has been taken), NAJ_ENOMEM when the request can never fit
+ * the budget, NAJ_EINVAL for bad arguments or input.
+ */
+naj_status naj_server_admit(naj_server *sv, int64_t n, int64_t nnz, const int32_t *rowptr, const int32_t *colidx,
+                            const double *vals, const double *D, int32_t nrhs, const double *b, const double *x0,
+                            double tol, double *x, int64_t *ticket);
+
+/*
+ * Advance the server: replay `chunks` chunks of passes over every occupied slot (0 =
+ * run none, only collect what has finished), and return in done[0..*ndone) (host, at
+ * most cap entries) the tickets of requests found finished since the last call.  A
+ * request is found one chunk after the chunk it finished in (the host reads the flags
+ * of the previous chunk while the next one runs).
+ */
+naj_status naj_server_step(naj_server *sv, int32_t chunks, int64_t *done, int32_t cap, int32_t *ndone);
+
+/*
+ * Take the result of a finished request: its answer is written to the x given at
+ * admission, res (host, nrhs entries) receives the per-right-hand-side results, and the
+ * request's slot and memory are released.  NAJ_EBUSY: not finished yet; NAJ_EINVAL:
+ * unknown ticket.  Returns the worst status of the request's right-hand sides.
+ */
+naj_status naj_server_result(naj_server *sv, int64_t ticket, naj_result *res);
+
+/* Server figures (host outputs, any may be NULL): budget bytes in use / total, slots in use / total. */
+naj_status naj_server_info(const naj_server *sv, int64_t *bytes_used, int64_t *bytes_total, int32_t *slots_used,
+                           int32_t *slots_total);
+
+/* Release a server and every request still in it. NULL is ignored. */
+void naj_server_destroy(naj_server *sv);
 
 #ifdef __cplusplus
 }

@@ -21,6 +21,7 @@
 #include "naj_batch.h"
 #include <map>
 #include <mutex>
+#include <unordered_map>
 
 using namespace naj;
 
@@ -247,6 +248,97 @@ __global__ void k_reduce_fixed(const double* part, int G, double* out) {
 
 // ---------------------------------------------------------------------------- system object
 
+namespace naj {
+
+// First-fit allocation of ranges of [0, size) with a coalescing free list, all on the
+// host.  Used for a pool of device memory and for a table of work items.
+struct RangeAlloc {
+  size_t size = 0;
+  size_t in_use = 0;
+  std::map<size_t, size_t> free_;            // offset -> length
+  std::unordered_map<size_t, size_t> used_;  // offset -> length
+
+  void reset(size_t n) {
+    size = n;
+    in_use = 0;
+    free_.clear();
+    used_.clear();
+    if (n) free_[0] = n;
+  }
+  bool alloc(size_t len, size_t* off) {
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < len) continue;
+      *off = it->first;
+      const size_t rest = it->second - len;
+      free_.erase(it);
+      if (rest) free_[*off + len] = rest;
+      used_[*off] = len;
+      in_use += len;
+      return true;
+    }
+    return false;
+  }
+  void release(size_t off) {
+    auto u = used_.find(off);
+    if (u == used_.end()) return;
+    size_t start = off, len = u->second;
+    used_.erase(u);
+    in_use -= len;
+    auto next = free_.lower_bound(start);
+    if (next != free_.end() && next->first == start + len) {   // merge with the following range
+      len += next->second;
+      next = free_.erase(next);
+    }
+    if (next != free_.begin()) {                               // and with the preceding one
+      auto prev = std::prev(next);
+      if (prev->first + prev->second == start) {
+        start = prev->first;
+        len += prev->second;
+        free_.erase(prev);
+      }
+    }
+    free_[start] = len;
+  }
+  size_t largest_free() const {
+    size_t m = 0;
+    for (const auto& kv : free_) m = std::max(m, kv.second);
+    return m;
+  }
+};
+
+// A sub-allocator over one device allocation (256-byte granules): allocation and release
+// are host bookkeeping only, so they never synchronize the device.  A serving loop draws
+// every buffer of its requests from one.
+struct Pool {
+  static constexpr size_t kAlign = 256;
+  char* base = nullptr;
+  RangeAlloc ranges;
+
+  hipError_t init(size_t bytes) {
+    const size_t n = (bytes + kAlign - 1) / kAlign;
+    hipError_t e = hipMalloc((void**)&base, n * kAlign);
+    if (e != hipSuccess) {
+      base = nullptr;
+      return e;
+    }
+    ranges.reset(n);
+    return hipSuccess;
+  }
+  void* alloc(size_t bytes) {
+    size_t off = 0;
+    if (!ranges.alloc(std::max<size_t>(1, (bytes + kAlign - 1) / kAlign), &off)) return nullptr;
+    return base + off * kAlign;
+  }
+  void release(void* p) {
+    if (p) ranges.release((size_t)((char*)p - base) / kAlign);
+  }
+  size_t size() const { return ranges.size * kAlign; }
+  size_t in_use() const { return ranges.in_use * kAlign; }
+  size_t largest_free() const { return ranges.largest_free() * kAlign; }
+};
+
+}  // namespace naj
+
 struct naj_system {
   int device = 0;
   int64_t n = 0, nnz = 0;
@@ -291,14 +383,30 @@ struct naj_system {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipEvent_t evc[2] = {nullptr, nullptr};
   int* hflag = nullptr;            // pinned host slots for the phase word
+  Pool* pool = nullptr;            // device memory source (null: the runtime allocator)
+  bool lean = false;               // matrix only: no single-solve workspace (batch and server members)
 };
 
 namespace {
 
+hipError_t sys_malloc(naj_system* s, void** p, size_t bytes) {
+  if (s->pool) {
+    *p = s->pool->alloc(bytes);
+    return *p ? hipSuccess : hipErrorOutOfMemory;
+  }
+  return hipMalloc(p, bytes);
+}
+
+void sys_free(naj_system* s, void* p) {
+  if (!p) return;
+  if (s->pool) s->pool->release(p);
+  else (void)hipFree(p);
+}
+
 template <typename T>
 naj_status dev_alloc(naj_system* s, T** p, size_t count) {
   if (count == 0) count = 1;
-  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+  hipError_t e = sys_malloc(s, (void**)p, count * sizeof(T));
   if (e != hipSuccess) {
     *p = nullptr;
     return fail(e == hipErrorOutOfMemory ? NAJ_ENOMEM : NAJ_EDEVICE, "hipMalloc(%zu bytes): %s", count * sizeof(T),
@@ -310,27 +418,13 @@ naj_status dev_alloc(naj_system* s, T** p, size_t count) {
 
 void free_system(naj_system* s) {
   if (!s) return;
-  (void)hipFree(s->slice_ptr);
-  (void)hipFree(s->col);
-  (void)hipFree(s->val);
-  (void)hipFree(s->val32);
-  (void)hipFree(s->dinv);
-  (void)hipFree(s->perm);
-  (void)hipFree(s->dom_bounds);
-  (void)hipFree(s->bperm);
-  (void)hipFree(s->lrowptr);
-  (void)hipFree(s->lcol);
-  (void)hipFree(s->lval);
-  (void)hipFree(s->lval32);
-  for (auto& v : s->vec) (void)hipFree(v);
-  for (auto& v : s->fvec) (void)hipFree(v);
-  (void)hipFree(s->part);
-  (void)hipFree(s->ctrl);
-  (void)hipFree(s->bar);
-  (void)hipFree(s->counters);
-  (void)hipFree(s->hist);
-  (void)hipFree(s->trace);
-  (void)hipFree(s->scal);
+  for (void* p : {(void*)s->slice_ptr, (void*)s->col, (void*)s->val, (void*)s->val32, (void*)s->dinv, (void*)s->perm,
+                  (void*)s->dom_bounds, (void*)s->bperm, (void*)s->lrowptr, (void*)s->lcol, (void*)s->lval,
+                  (void*)s->lval32, (void*)s->part, (void*)s->ctrl, (void*)s->bar, (void*)s->counters, (void*)s->hist,
+                  (void*)s->trace, (void*)s->scal})
+    sys_free(s, p);
+  for (auto& v : s->vec) sys_free(s, v);
+  for (auto& v : s->fvec) sys_free(s, v);
   if (s->ev0) (void)hipEventDestroy(s->ev0);
   if (s->ev1) (void)hipEventDestroy(s->ev1);
   for (auto& e : s->evc)
@@ -359,7 +453,7 @@ const void* solve_kernel(bool user_d) {
   return user_d ? (const void*)k_solve64<true, kSmallBlock> : (const void*)k_solve64<false, kSmallBlock>;
 }
 
-naj_status choose_grid(naj_system* s) {
+naj_status choose_grid(naj_system* s, hipStream_t st) {
   hipDeviceProp_t prop;
   HIP_TRY(hipGetDeviceProperties(&prop, s->device));
   s->cus = prop.multiProcessorCount;
@@ -417,7 +511,8 @@ naj_status choose_grid(naj_system* s) {
     balanced_bounds(wpre.data(), s->nslices, nxcd, bounds.data());
     naj_status rc = dev_alloc(s, &s->dom_bounds, (size_t)nxcd + 1);
     if (rc != NAJ_OK) return rc;
-    HIP_TRY(hipMemcpy(s->dom_bounds, bounds.data(), sizeof(int64_t) * (nxcd + 1), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpyAsync(s->dom_bounds, bounds.data(), sizeof(int64_t) * (nxcd + 1), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));   // bounds is a local
   }
   int khz = 0;
   HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, s->device));
@@ -430,7 +525,7 @@ naj_status choose_grid(naj_system* s) {
 
 naj_status ensure_hist(naj_system* s, int hist_cap, int trace_cap) {
   if (hist_cap > s->hist_cap_dev) {
-    (void)hipFree(s->hist);
+    sys_free(s, s->hist);
     s->hist = nullptr;
     s->hist_cap_dev = 0;
     naj_status st = dev_alloc(s, &s->hist, (size_t)hist_cap);
@@ -438,7 +533,7 @@ naj_status ensure_hist(naj_system* s, int hist_cap, int trace_cap) {
     s->hist_cap_dev = hist_cap;
   }
   if (trace_cap > s->trace_cap_dev) {
-    (void)hipFree(s->trace);
+    sys_free(s, s->trace);
     s->trace = nullptr;
     s->trace_cap_dev = 0;
     naj_status st = dev_alloc(s, &s->trace, (size_t)trace_cap * 2);
@@ -598,11 +693,11 @@ naj_status build_layout(naj_system* s, const int32_t* rowptr, const int32_t* col
     int32_t* iperm_d = nullptr;
     rc = dev_alloc(s, &s->perm, (size_t)n);
     if (rc != NAJ_OK) return rc;
-    HIP_TRY(hipMalloc((void**)&iperm_d, sizeof(int32_t) * n));
-    HIP_TRY(hipMalloc((void**)&new_rp_d, sizeof(int64_t) * (n + 1)));
-    HIP_TRY(hipMalloc((void**)&tmp_rp32, sizeof(int32_t) * (n + 1)));
-    HIP_TRY(hipMalloc((void**)&tmp_col, sizeof(int32_t) * std::max<int64_t>(1, s->nnz)));
-    HIP_TRY(hipMalloc((void**)&tmp_val, sizeof(double) * std::max<int64_t>(1, s->nnz)));
+    HIP_TRY(sys_malloc(s, (void**)&iperm_d, sizeof(int32_t) * n));
+    HIP_TRY(sys_malloc(s, (void**)&new_rp_d, sizeof(int64_t) * (n + 1)));
+    HIP_TRY(sys_malloc(s, (void**)&tmp_rp32, sizeof(int32_t) * (n + 1)));
+    HIP_TRY(sys_malloc(s, (void**)&tmp_col, sizeof(int32_t) * std::max<int64_t>(1, s->nnz)));
+    HIP_TRY(sys_malloc(s, (void**)&tmp_val, sizeof(double) * std::max<int64_t>(1, s->nnz)));
     HIP_TRY(hipMemcpyAsync(s->perm, perm.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(iperm_d, iperm.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(new_rp_d, nrp.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, st));
@@ -612,12 +707,12 @@ naj_status build_layout(naj_system* s, const int32_t* rowptr, const int32_t* col
     HIP_TRY(hipGetLastError());
     if (s->dinv) {   // caller's diagonal into solver order
       double* t = nullptr;
-      HIP_TRY(hipMalloc((void**)&t, sizeof(double) * n));
+      HIP_TRY(sys_malloc(s, (void**)&t, sizeof(double) * n));
       hipLaunchKernelGGL(k_gather, dim3(blocks_for(n, kAux)), dim3(kAux), 0, st, s->dinv, s->perm, t, n);
       HIP_TRY(hipGetLastError());
       HIP_TRY(hipMemcpyAsync(s->dinv, t, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
       HIP_TRY(hipStreamSynchronize(st));
-      (void)hipFree(t);
+      sys_free(s, t);
     }
     // long rows: the prefix of the renumbered CSR
     const int64_t lnnz = nrp[nlong];
@@ -635,7 +730,7 @@ naj_status build_layout(naj_system* s, const int32_t* rowptr, const int32_t* col
       HIP_TRY(hipGetLastError());
     }
     HIP_TRY(hipStreamSynchronize(st));
-    (void)hipFree(iperm_d);
+    sys_free(s, iperm_d);
     src_rp = tmp_rp32;
     src_col = tmp_col;
     src_val = tmp_val;
@@ -666,10 +761,10 @@ naj_status build_layout(naj_system* s, const int32_t* rowptr, const int32_t* col
     HIP_TRY(hipGetLastError());
   }
   HIP_TRY(hipStreamSynchronize(st));
-  if (new_rp_d) (void)hipFree(new_rp_d);
-  if (tmp_rp32) (void)hipFree(tmp_rp32);
-  if (tmp_col) (void)hipFree(tmp_col);
-  if (tmp_val) (void)hipFree(tmp_val);
+  sys_free(s, new_rp_d);
+  sys_free(s, tmp_rp32);
+  sys_free(s, tmp_col);
+  sys_free(s, tmp_val);
   return NAJ_OK;
 }
 
@@ -832,6 +927,7 @@ naj_status batch_build(naj_batch* bt, hipStream_t st) {
     S.A.dom_bounds = nullptr;
     S.dinv = s->dinv;
     S.nrhs = bt->nrhs[i];
+    S.tol = o.tol;
     S.lk = 0;
     while ((1 << S.lk) < S.nrhs) ++S.lk;
     S.tile0 = (int)ht.size();
@@ -896,6 +992,7 @@ naj_status batch_build(naj_batch* bt, hipStream_t st) {
   A.sact = bt->d_sact;
   A.nsact = bt->d_nsact;
   A.done = bt->d_done;
+  A.slot_done = nullptr;
   A.nxcd = std::max(1, std::min(kMaxDomains, env_int("NAJ_NXCD", (cus % 8 == 0) ? 8 : 1)));
   A.tol = o.tol;
   A.inner_tol = o.inner_tol;
@@ -950,8 +1047,11 @@ const char* naj_last_error(void) { return g_err.c_str(); }
 
 const char* naj_version(void) { return "naj 0.1 gfx950"; }
 
-naj_status naj_create_system(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* colidx, const double* vals,
-                             const double* D, void* stream, naj_system** out) {
+// System creation; with a pool every device buffer comes from it, and a lean system holds the
+// matrix only (its right-hand sides are solved by a batch or a server).
+static naj_status create_system_impl(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* colidx,
+                                     const double* vals, const double* D, void* stream, Pool* pool, bool lean,
+                                     naj_system** out) {
   g_err.clear();
   (void)hipGetLastError();   // drop a stale error left by unrelated earlier runtime calls
   if (!out) return fail(NAJ_EINVAL, "out is NULL");
@@ -961,6 +1061,8 @@ naj_status naj_create_system(int64_t n, int64_t nnz, const int32_t* rowptr, cons
   if (!rowptr || (nnz > 0 && (!colidx || !vals))) return fail(NAJ_EINVAL, "null CSR pointer");
   hipStream_t st = (hipStream_t)stream;
   naj_system* s = new naj_system();
+  s->pool = pool;
+  s->lean = lean;
   naj_status rc = NAJ_OK;
   int* flag = nullptr;
   int hflag = 0;
@@ -980,7 +1082,7 @@ naj_status naj_create_system(int64_t n, int64_t nnz, const int32_t* rowptr, cons
   HSTEP(hipGetDevice(&s->device));
   s->n = n;
   s->nnz = nnz;
-  HSTEP(hipMalloc((void**)&flag, sizeof(int)));
+  HSTEP(sys_malloc(s, (void**)&flag, sizeof(int)));
   HSTEP(hipMemsetAsync(flag, 0, sizeof(int), st));
   hipLaunchKernelGGL(k_check_rowptr, dim3(blocks_for(n, kAux)), dim3(kAux), 0, st, rowptr, n, nnz, flag);
   HSTEP(hipGetLastError());
@@ -1009,30 +1111,37 @@ naj_status naj_create_system(int64_t n, int64_t nnz, const int32_t* rowptr, cons
     goto bad;
   }
   STEP(build_layout(s, rowptr, colidx, vals, st));
-  STEP(choose_grid(s));
+  STEP(choose_grid(s, st));
   s->ymode = env_int("NAJ_YMODE", s->layout == 1 ? 1 : 0) ? 1 : 0;
-  for (int i = 0; i < 3 + s->ymode; ++i) STEP(dev_alloc(s, &s->vec[i], (size_t)n));
-  STEP(dev_alloc(s, &s->part, (size_t)kPartStride * s->max_grid));
-  STEP(dev_alloc(s, &s->ctrl, 1));
-  STEP(dev_alloc(s, &s->bar, 1));
-  STEP(dev_alloc(s, &s->counters, (size_t)kCounterWords));
-  HSTEP(hipMemsetAsync(s->counters, 0, sizeof(unsigned int) * kCounterWords, st));
-  STEP(dev_alloc(s, &s->scal, 8));
-  HSTEP(hipEventCreate(&s->ev0));
-  HSTEP(hipEventCreate(&s->ev1));
-  HSTEP(hipEventCreateWithFlags(&s->evc[0], hipEventDisableTiming));
-  HSTEP(hipEventCreateWithFlags(&s->evc[1], hipEventDisableTiming));
-  HSTEP(hipHostMalloc((void**)&s->hflag, 2 * sizeof(int), hipHostMallocDefault));
+  if (!lean) {   // workspace of the single-solve drivers
+    for (int i = 0; i < 3 + s->ymode; ++i) STEP(dev_alloc(s, &s->vec[i], (size_t)n));
+    STEP(dev_alloc(s, &s->part, (size_t)kPartStride * s->max_grid));
+    STEP(dev_alloc(s, &s->ctrl, 1));
+    STEP(dev_alloc(s, &s->bar, 1));
+    STEP(dev_alloc(s, &s->counters, (size_t)kCounterWords));
+    HSTEP(hipMemsetAsync(s->counters, 0, sizeof(unsigned int) * kCounterWords, st));
+    STEP(dev_alloc(s, &s->scal, 8));
+    HSTEP(hipEventCreate(&s->ev0));
+    HSTEP(hipEventCreate(&s->ev1));
+    HSTEP(hipEventCreateWithFlags(&s->evc[0], hipEventDisableTiming));
+    HSTEP(hipEventCreateWithFlags(&s->evc[1], hipEventDisableTiming));
+    HSTEP(hipHostMalloc((void**)&s->hflag, 2 * sizeof(int), hipHostMallocDefault));
+  }
   HSTEP(hipStreamSynchronize(st));
-  (void)hipFree(flag);
+  sys_free(s, flag);
   *out = s;
   return NAJ_OK;
 bad:
-  if (flag) (void)hipFree(flag);
+  if (flag) sys_free(s, flag);
   free_system(s);
   return rc;
 #undef STEP
 #undef HSTEP
+}
+
+naj_status naj_create_system(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* colidx, const double* vals,
+                             const double* D, void* stream, naj_system** out) {
+  return create_system_impl(n, nnz, rowptr, colidx, vals, D, stream, nullptr, false, out);
 }
 
 void naj_destroy_system(naj_system* s) {
@@ -1460,3 +1569,5 @@ naj_status naj_tune_load(const char* path) {
 }
 
 }  // extern "C"
+
+#include "naj_server_impl.h"

@@ -48,6 +48,8 @@ struct BatchSys {
   double* part;                 // [nrhs][ntiles][kPartStride]
   Ctrl* ctrl;                   // [nrhs]
   PassView* vt;                 // [kMaxRhs] the pass view of each right-hand side (done beyond nrhs)
+  double tol;                   // relative residual tolerance of this system's right-hand sides
+  int gen;                      // tag written to slot_done when every instance has finished
   int lk, nrhs;                 // log2 of the lanes per row (kp = 1 << lk), right-hand sides
   int tile0, ntiles;
   int ymode;
@@ -68,6 +70,7 @@ struct BatchArgs {
   int* sact;                    // those systems
   int* nsact;
   unsigned int* done;           // instances that have finished (status set)
+  int* slot_done;               // per system: set once all its instances have finished (null: not kept)
   int nxcd;                     // L2 domains the workgroups are spread over
   // options shared by the batch
   double tol;
@@ -84,7 +87,7 @@ struct BatchArgs {
 // The fields of SolveArgs that the scalar control reads.
 __device__ __forceinline__ SolveArgs batch_ctrl_args(const BatchArgs& ba, const BatchSys& S) {
   SolveArgs a = {};
-  a.tol = ba.tol;
+  a.tol = S.tol;
   a.max_iter = ba.max_iter;
   a.restart = ba.restart;
   a.confirm_gap = ba.confirm_gap;
@@ -172,6 +175,7 @@ __device__ __forceinline__ BatchSys uniform_sys(const BatchSys& g) {
   S.dinv = uni(g.dinv);
   S.xb = uni(g.xb);
   S.fb = uni(g.fb);
+  S.tol = __builtin_bit_cast(double, uni(__builtin_bit_cast(int64_t, g.tol)));
   S.xs = uni(g.xs);
   S.fs = uni(g.fs);
   S.b = uni(g.b);
@@ -183,6 +187,7 @@ __device__ __forceinline__ BatchSys uniform_sys(const BatchSys& g) {
   S.tile0 = uni(g.tile0);
   S.ntiles = uni(g.ntiles);
   S.ymode = uni(g.ymode);
+  S.gen = uni(g.gen);
   return S;
 }
 
@@ -1060,6 +1065,11 @@ __global__ void __launch_bounds__(kDecideBlock) k_batch_decide(BatchArgs ba) {
     }
     __syncthreads();
   }
+  if (ba.slot_done && threadIdx.x == 0) {
+    bool all = true;
+    for (int j = 0; j < S.nrhs; ++j) all = all && S.vt[j].phase == PH_DONE;
+    if (all) ba.slot_done[sys] = S.gen;
+  }
 }
 
 // The active lists: the systems with an unfinished instance, and their items, in system
@@ -1116,21 +1126,9 @@ __global__ void __launch_bounds__(kCompactBlock) k_batch_compact(BatchArgs ba) {
   }
 }
 
-// Per solve: clear every instance's control block (as k_solve_init), write the views of
-// the first pass, and clear the done counter.  One workgroup of kMaxRhs threads per system.
-__global__ void k_batch_init(BatchArgs ba) {
-  const int i = blockIdx.x;
-  if (i >= ba.nsys) return;
-  const BatchSys& S = ba.sys[i];
-  const int j = threadIdx.x;
-  if (i == 0 && j == 0) *ba.done = 0u;
-  if (j >= kMaxRhs) return;
-  if (j >= S.nrhs) {
-    PassView v = {};
-    v.phase = PH_DONE;
-    S.vt[j] = v;
-    return;
-  }
+// Control block of instance j of a system at the start of a solve (as k_solve_init), and
+// its first pass view.
+__device__ inline void batch_ctrl_start(const BatchArgs& ba, const BatchSys& S, int j) {
   Ctrl* c = S.ctrl + j;
   c->alpha = 1.0;
   c->beta = 0.0;
@@ -1176,6 +1174,59 @@ __global__ void k_batch_init(BatchArgs ba) {
   }
   for (int q = 0; q < kRestartLogCap; ++q) c->restart_log[q] = 0;
   load_view(c, S.vt + j);
+}
+
+__device__ inline void batch_view_done(const BatchSys& S, int j) {
+  PassView v = {};
+  v.phase = PH_DONE;
+  S.vt[j] = v;
+}
+
+// Per solve: start every instance's control block and clear the done counter.  One
+// workgroup of kMaxRhs threads per system.
+__global__ void k_batch_init(BatchArgs ba) {
+  const int i = blockIdx.x;
+  if (i >= ba.nsys) return;
+  const BatchSys& S = ba.sys[i];
+  const int j = threadIdx.x;
+  if (i == 0 && j == 0) *ba.done = 0u;
+  if (j >= kMaxRhs) return;
+  if (j < S.nrhs) batch_ctrl_start(ba, S, j);
+  else batch_view_done(S, j);
+}
+
+// Serving loop: a request enters slot `slot`: its record, its work items (long rows four
+// per item, then `tslices` slices per item) and its control blocks.  Runs on the pass
+// stream between chunks of passes, so the next active-list rebuild picks the slot up.
+__global__ void k_server_admit(BatchArgs ba, int slot, BatchSys rec, int tslices, int nlt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    const_cast<BatchSys*>(ba.sys)[slot] = rec;
+    ba.slot_done[slot] = 0;
+  }
+  if (i < kMaxRhs) {
+    if (i < rec.nrhs) batch_ctrl_start(ba, rec, i);
+    else batch_view_done(rec, i);
+  }
+  if (i < rec.ntiles) {
+    BatchTile t;
+    t.sys = slot;
+    if (i < nlt) {
+      t.s0 = t.s1 = 0;
+      t.l0 = i * 4;
+      t.l1 = (int)min((int64_t)t.l0 + 4, rec.A.n_long);
+    } else {
+      t.l0 = t.l1 = 0;
+      t.s0 = (i - nlt) * tslices;
+      t.s1 = (int)min((int64_t)t.s0 + tslices, rec.A.nslices);
+    }
+    const_cast<BatchTile*>(ba.tiles)[rec.tile0 + i] = t;
+  }
+}
+
+// Serving loop: a slot is emptied (no instance, so the active-list rebuild skips it).
+__global__ void k_server_clear(BatchArgs ba, int slot) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) const_cast<BatchSys*>(ba.sys)[slot].nrhs = 0;
 }
 
 // Right-hand sides (or starting points) of one system into its interleaved buffer:

@@ -74,6 +74,13 @@ _SIGS = {
     "naj_autotune_tiles": (ctypes.c_int, [_P, _I32, ctypes.POINTER(NajOpts), _I32, _P, ctypes.POINTER(_I32)]),
     "naj_tune_save": (ctypes.c_int, [ctypes.c_char_p]),
     "naj_tune_load": (ctypes.c_int, [ctypes.c_char_p]),
+    "naj_server_create": (ctypes.c_int, [_I64, _I32, ctypes.POINTER(NajOpts), _P, ctypes.POINTER(_P)]),
+    "naj_server_admit": (ctypes.c_int, [_P, _I64, _I64, _P, _P, _P, _P, _I32, _P, _P, _D, _P, ctypes.POINTER(_I64)]),
+    "naj_server_step": (ctypes.c_int, [_P, _I32, _P, _I32, ctypes.POINTER(_I32)]),
+    "naj_server_result": (ctypes.c_int, [_P, _I64, ctypes.POINTER(NajResult)]),
+    "naj_server_info": (ctypes.c_int, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I32),
+                                       ctypes.POINTER(_I32)]),
+    "naj_server_destroy": (None, [_P]),
 }
 NAJ_MAX_RHS = 8
 
@@ -339,3 +346,98 @@ def tune_save(path: str):
 
 def tune_load(path: str):
     _check(load().naj_tune_load(path.encode()))
+
+
+class Server:
+    """Serving loop over the naj_server_* entry points (continuous batching).
+
+    Requests (one system, 1..NAJ_MAX_RHS right-hand sides, their own tolerance) are
+    admitted while others run; ``step`` advances every admitted request and returns the
+    tickets that finished; ``result`` hands back the answer and frees the request's
+    slot and memory.  The passes run on ``stream`` (a torch stream of its own by default,
+    so that uploads on other streams do not wait for them).
+    """
+
+    def __init__(self, mem_budget: int, max_slots: int = 64, device="cuda:0", stream=None, **opts):
+        torch = _torch()
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        self.upload = torch.cuda.Stream(device=self.device)
+        o = default_opts(**opts)
+        h = _P()
+        with torch.cuda.device(self.device):
+            _check(load().naj_server_create(int(mem_budget), int(max_slots), ctypes.byref(o),
+                                            ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+        self._req = {}     # ticket -> (x tensor, nrhs, inputs kept alive until admitted)
+        self._done = (_I64 * 4096)()
+
+    def _dev(self, a, dtype):
+        torch = _torch()
+        if isinstance(a, torch.Tensor):
+            return a.to(device=self.device, dtype=dtype).contiguous()
+        return torch.as_tensor(np.ascontiguousarray(a)).to(device=self.device, dtype=dtype).contiguous()
+
+    def admit(self, rowptr, colidx, vals, b, x0=None, D=None, tol: float = 0.0):
+        """Returns a ticket, or None when the server is busy (no slot or budget free now)."""
+        torch = _torch()
+        with torch.cuda.device(self.device), torch.cuda.stream(self.upload):
+            rp = self._dev(rowptr, torch.int32)
+            ci = self._dev(colidx, torch.int32)
+            va = self._dev(vals, torch.float64)
+            bb = self._dev(b, torch.float64)
+            x0t = None if x0 is None else self._dev(x0, torch.float64)
+            Dt = None if D is None else self._dev(D, torch.float64)
+            x = torch.empty_like(bb)
+        self.upload.synchronize()
+        n = rp.numel() - 1
+        nrhs = 1 if bb.dim() == 1 else int(bb.shape[1])
+        t = _I64()
+        with torch.cuda.device(self.device):
+            st = load().naj_server_admit(self._h, n, ci.numel(), rp.data_ptr(), ci.data_ptr(), va.data_ptr(),
+                                         None if Dt is None else Dt.data_ptr(), nrhs, bb.data_ptr(),
+                                         None if x0t is None else x0t.data_ptr(), float(tol), x.data_ptr(),
+                                         ctypes.byref(t))
+        if st == NAJ_EBUSY:
+            return None
+        _check(st)
+        self._req[t.value] = (x, nrhs)
+        return t.value
+
+    def step(self, chunks: int = 1) -> list:
+        """Run `chunks` chunks of passes (0: none); returns the tickets found finished."""
+        torch = _torch()
+        nd = _I32()
+        with torch.cuda.device(self.device):
+            _check(load().naj_server_step(self._h, int(chunks), self._done, len(self._done), ctypes.byref(nd)))
+        return [self._done[i] for i in range(nd.value)]
+
+    def result(self, ticket: int):
+        """(x on the device, list of SolveInfo) of a finished request; frees its slot."""
+        torch = _torch()
+        x, nrhs = self._req[ticket]
+        res = (NajResult * nrhs)()
+        with torch.cuda.device(self.device):
+            st = load().naj_server_result(self._h, int(ticket), res)
+        if st < 0 and st != NAJ_EBREAKDOWN:
+            _check(st)
+        del self._req[ticket]
+        return x, [SolveInfo(r.status, r.iterations, r.restarts, r.confirmations, r.relres, passes=r.passes,
+                             grid=r.grid) for r in res]
+
+    def info(self) -> dict:
+        bu, bt, su, stt = _I64(), _I64(), _I32(), _I32()
+        _check(load().naj_server_info(self._h, ctypes.byref(bu), ctypes.byref(bt), ctypes.byref(su), ctypes.byref(stt)))
+        return dict(bytes_used=bu.value, bytes_total=bt.value, slots_used=su.value, slots_total=stt.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().naj_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
