@@ -235,6 +235,163 @@ def bench_fe_batch(args, progress):
     return line
 
 
+def serve_trace(nreq: int, seed: int = 1005, rate: float = 200.0, fe_pool: int = 128, workers: int = 8):
+    """Request trace of the serving workload: Poisson arrivals at `rate` per second; 70% P1
+    finite-element systems drawn from the first `fe_pool` members of the batch generator
+    (seed 1004), 30% 3D 7-point Dirichlet Laplacians with m ~ U{16..100} per side; one
+    right-hand side each, N(0,1); tolerance 1e-6 or 1e-8 with probability 1/2 each."""
+    from concurrent.futures import ProcessPoolExecutor
+    from paper_2407_03272_amd import workloads as W
+    rng = np.random.default_rng(seed)
+    arr = np.cumsum(rng.exponential(1.0 / rate, nreq))
+    kind = rng.random(nreq) < 0.7
+    fe_idx = rng.integers(0, fe_pool, nreq)
+    ms = rng.integers(16, 101, nreq)
+    tols = np.where(rng.random(nreq) < 0.5, 1e-6, 1e-8)
+    bseeds = rng.integers(0, 2 ** 31 - 1, nreq)
+    specs = W.fe_batch_specs(512, 1e3, 2e5, 1004)
+    need = sorted(set(int(k) for k, f in zip(fe_idx, kind) if f))
+    with ProcessPoolExecutor(max_workers=max(1, workers)) as ex:
+        fe_sys = dict(zip(need, ex.map(W._fe_from_spec, [(*specs[k], 1) for k in need], chunksize=2)))
+    lap = {m: W.poisson_dirichlet((m, m, m)) for m in sorted(set(int(m) for m, f in zip(ms, kind) if not f))}
+    reqs = []
+    for i in range(nreq):
+        r = np.random.default_rng(int(bseeds[i]))
+        if kind[i]:
+            s = fe_sys[int(fe_idx[i])]
+            rowptr, colidx, vals = s.rowptr, s.colidx, s.vals
+        else:
+            rowptr, colidx, vals = lap[int(ms[i])]
+        b = r.standard_normal(len(rowptr) - 1)
+        reqs.append(dict(t=float(arr[i]), sys=W.CsrSystem(rowptr, colidx, vals, b), b=b, tol=float(tols[i]),
+                         fe=bool(kind[i])))
+    return reqs
+
+
+def run_server(naj, reqs, budget, slots, closed_loop, progress, label):
+    """Replays the trace through a server: admission as requests arrive (all at t=0 when
+    closed_loop), continuous batching, result copied to the host.  Returns per-request
+    latencies (arrival -> answer on the host) and the makespan."""
+    import torch
+    from collections import deque
+    srv = naj.Server(budget, slots, max_rhs=1, precision=naj.NAJ_MIXED, tol=1e-8, max_iter=20000)
+    arr = np.zeros(len(reqs)) if closed_loop else np.array([r["t"] for r in reqs])
+    lat = np.full(len(reqs), np.nan)
+    tickets, queue = {}, deque()
+    nxt, ndone, busy_max, bad = 0, 0, 0, 0
+    last_report = 0.0
+    host = {"admit": 0.0, "step": 0.0, "result": 0.0, "steps": 0}
+    t0 = time.perf_counter()
+    while ndone < len(reqs):
+        now = time.perf_counter() - t0
+        while nxt < len(reqs) and arr[nxt] <= now:
+            queue.append(nxt)
+            nxt += 1
+        ta = time.perf_counter()
+        while queue:
+            i = queue[0]
+            r = reqs[i]
+            t = srv.admit(r["sys"].rowptr, r["sys"].colidx, r["sys"].vals, r["b"], tol=r["tol"])
+            if t is None:
+                break
+            tickets[t] = i
+            queue.popleft()
+        tb = time.perf_counter()
+        busy_max = max(busy_max, len(queue))
+        active = len(tickets) > 0
+        fin = srv.step(1 if active else 0)
+        tc = time.perf_counter()
+        for t in fin:
+            i = tickets.pop(t)
+            x, infos = srv.result(t)
+            xh = x.cpu()
+            lat[i] = time.perf_counter() - t0 - arr[i]
+            bad += int(infos[0].status != 0)
+            ndone += 1
+        td = time.perf_counter()
+        host["admit"] += tb - ta
+        host["step"] += tc - tb
+        host["result"] += td - tc
+        host["steps"] += 1
+        if not active and not queue and nxt < len(reqs):
+            wait = arr[nxt] - (time.perf_counter() - t0)
+            if wait > 0:
+                time.sleep(min(wait, 0.002))
+        if time.perf_counter() - t0 - last_report > 5.0:
+            last_report = time.perf_counter() - t0
+            progress(f"{label}: {ndone}/{len(reqs)} done, {len(tickets)} in flight, {len(queue)} queued")
+    makespan = time.perf_counter() - t0
+    srv.close()
+    progress(f"{label}: host seconds admit {host['admit']:.2f}, step {host['step']:.2f}, result {host['result']:.2f} "
+             f"over {host['steps']} loop turns, makespan {makespan:.2f}")
+    return lat, makespan, busy_max, bad
+
+
+def bench_serve(args, progress):
+    """Serving loop under a Poisson request trace (continuous batching, mixed precision)."""
+    import torch
+    from paper_2407_03272_amd import naj
+    nreq, warm = args.serve_requests, min(200, args.serve_requests // 10)
+    reqs = serve_trace(nreq, workers=min(16, os.cpu_count() or 1))
+    progress(f"trace: {nreq} requests over {reqs[-1]['t']:.2f} s, "
+             f"{sum(r['fe'] for r in reqs)} finite-element, {sum(not r['fe'] for r in reqs)} Laplacians")
+    budget = int(args.serve_budget_mb) << 20
+    # open loop at the trace's arrival times
+    lat, span, qmax, bad = run_server(naj, reqs, budget, args.serve_slots, False, progress, "open loop")
+    if bad:
+        raise SystemExit(f"serve: {bad} requests did not converge")
+    L = lat[warm:] * 1e3
+    first = reqs[warm]["t"]
+    achieved = (nreq - warm) / (span - first)
+    progress(f"open loop: p50 {np.percentile(L, 50):.1f} ms, p99 {np.percentile(L, 99):.1f} ms, "
+             f"{achieved:.1f} solves/s")
+    # closed loop: every request queued at t = 0 (saturation throughput)
+    clat, cspan, _, cbad = run_server(naj, reqs, budget, args.serve_slots, True, progress, "closed loop")
+    sat = nreq / cspan
+    progress(f"closed loop: {sat:.1f} solves/s")
+    out = {
+        "metric": "solves/s + HBM GB/s at relres 1e-8 vs plain FP64; p50/p99 solve latency",
+        "value": achieved, "unit": "solves/s", "n_gpus": 1, "steps": nreq - warm, "warmup": warm,
+        "ms_per_step": (span - first) / (nreq - warm) * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"serving loop: {nreq} requests, Poisson arrivals at 200/s (seed 1005); 70% P1 "
+                               "finite-element systems from the batch generator, 30% 3D 7-point Dirichlet Laplacians "
+                               "with m ~ U{16..100}; tol 1e-6 or 1e-8; 1 right-hand side each; memory-budgeted "
+                               "admission, continuous batching, float32 inner + float64 refinement; latency = arrival "
+                               "to answer on the host, CSR upload included",
+                   "budget_mb": args.serve_budget_mb, "slots": args.serve_slots},
+        "p50_ms": float(np.percentile(L, 50)), "p99_ms": float(np.percentile(L, 99)),
+        "p50_ms_fe": float(np.percentile(lat[warm:][[r["fe"] for r in reqs[warm:]]] * 1e3, 50)),
+        "p50_ms_laplacian": float(np.percentile(lat[warm:][[not r["fe"] for r in reqs[warm:]]] * 1e3, 50)),
+        "max_queue": int(qmax),
+        "closed_loop_solves_per_s": sat,
+        "closed_loop_p50_ms": float(np.percentile(clat * 1e3, 50)),
+        "roofline": None,
+    }
+    if args.serve_small_budget_mb:
+        slat, sspan, sq, sbad = run_server(naj, reqs, int(args.serve_small_budget_mb) << 20, args.serve_slots, False,
+                                           progress, "small budget")
+        S = slat[warm:] * 1e3
+        out["small_budget"] = {"budget_mb": args.serve_small_budget_mb, "p50_ms": float(np.percentile(S, 50)),
+                               "p99_ms": float(np.percentile(S, 99)), "max_queue": int(sq),
+                               "solves_per_s": (nreq - warm) / (sspan - first)}
+    if not args.no_compare:
+        # plain float64, one request at a time (a sample of the trace, system built per request as in serving)
+        sample = reqs[warm: warm + args.serve_fp64_sample]
+        t0 = time.perf_counter()
+        for r in sample:
+            s = r["sys"]
+            sm = naj.System(s.rowptr, s.colidx, s.vals)
+            x, inf = sm.solve(r["b"], tol=r["tol"], max_iter=20000, hist_cap=0)
+            xh = x.cpu()
+            sm.close()
+        dt = time.perf_counter() - t0
+        out["compare_one_at_a_time"] = {"precision": "fp64", "sampled_requests": len(sample), "seconds": dt,
+                                        "solves_per_s": len(sample) / dt}
+        progress(f"float64 one at a time: {len(sample) / dt:.1f} solves/s")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -246,6 +403,11 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip the second-precision comparison solves")
     ap.add_argument("--nsys", type=int, default=512, help="systems in the fe_batch workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=2200, help="requests in the serve workload trace")
+    ap.add_argument("--serve-budget-mb", type=int, default=8192, help="serve workload memory budget")
+    ap.add_argument("--serve-small-budget-mb", type=int, default=512, help="second serve run with this budget (0: none)")
+    ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--serve-fp64-sample", type=int, default=200)
     ap.add_argument("--pmc-sample", action="store_true",
                     help="run only a 1 GiB torch copy (counter calibration) and a 50-iteration solve, for rocprofv3 --pmc")
     args = ap.parse_args()
@@ -260,6 +422,9 @@ def main():
     def progress(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
+    if args.workload == "serve":
+        print(json.dumps(bench_serve(args, progress)), flush=True)
+        return
     if args.workload == "fe_batch":
         if args.precision == "fp64" and "--precision" not in sys.argv:
             args.precision = "mixed"

@@ -241,12 +241,13 @@ typedef struct naj_server naj_server;
  * Create a server.
  *   mem_budget      : bytes of device memory for all requests (one allocation)
  *   max_slots       : requests served at once, 1..65536
+ *   max_rhs         : most right-hand sides of one request, 1..NAJ_MAX_RHS (kernels are sized for it)
  *   opts            : server options (NULL = defaults; its tol is the default request tolerance)
  *   stream          : stream the passes run on (admission uses a stream of its own)
  * Errors: NAJ_EINVAL, NAJ_ENOMEM (budget not allocatable), NAJ_EDEVICE.
  */
-naj_status naj_server_create(int64_t mem_budget, int32_t max_slots, const naj_opts *opts, void *stream,
-                             naj_server **out);
+naj_status naj_server_create(int64_t mem_budget, int32_t max_slots, int32_t max_rhs, const naj_opts *opts,
+                             void *stream, naj_server **out);
 
 /*
  * Admit a request: build its system (as naj_create_system, inside the budget) and

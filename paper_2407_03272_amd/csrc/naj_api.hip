@@ -976,7 +976,9 @@ naj_status batch_build(naj_batch* bt, hipStream_t st) {
   HIP_TRY(hipStreamSynchronize(st));
   // grid: every resident workgroup, at most one wavefront per item
   int occ = 0, cus = 0;
-  const void* pass_fn = mixed ? (const void*)k_batch_pass<true> : (const void*)k_batch_pass<false>;
+  int kpmax = 1;
+  for (const BatchSys& S : hs) kpmax = std::max(kpmax, 1 << S.lk);
+  const void* pass_fn = batch_pass_kernel(mixed, kpmax);
   HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, pass_fn, kBatchBlock, 0));
   hipDeviceProp_t prop;
   HIP_TRY(hipGetDeviceProperties(&prop, bt->device));
@@ -1017,8 +1019,8 @@ naj_status batch_build(naj_batch* bt, hipStream_t st) {
   HIP_TRY(hipStreamBeginCapture(bt->cap, hipStreamCaptureModeThreadLocal));
   hipLaunchKernelGGL(k_batch_compact, dim3(1), dim3(kCompactBlock), 0, bt->cap, bt->args);
   for (int q = 0; q < bt->graph_len; ++q) {
-    if (mixed) hipLaunchKernelGGL(k_batch_pass<true>, dim3(bt->grid), dim3(kBatchBlock), 0, bt->cap, bt->args);
-    else hipLaunchKernelGGL(k_batch_pass<false>, dim3(bt->grid), dim3(kBatchBlock), 0, bt->cap, bt->args);
+    void* kargs[] = {&bt->args};
+    HIP_TRY(hipLaunchKernel(pass_fn, dim3(bt->grid), dim3(kBatchBlock), kargs, 0, bt->cap));
     hipLaunchKernelGGL(k_batch_decide, dim3(bt->nsys), dim3(kDecideBlock), 0, bt->cap, bt->args);
   }
   HIP_TRY(hipStreamEndCapture(bt->cap, &bt->graph));

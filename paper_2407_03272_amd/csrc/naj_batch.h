@@ -946,7 +946,7 @@ __device__ __forceinline__ void item_phase(const BatchSys& S, const BatchTile& T
 // One item for every lane's instance, one phase after another (each phase present among
 // the system's right-hand sides runs once; MIXED selects the phases of the refinement
 // loop, else those of the float64 solve).  Leaves right-hand side j's sums in lane j.
-template <bool MIXED>
+template <bool MIXED, int KPMAX>
 __device__ __forceinline__ void batch_item(const BatchSys& S, const BatchTile& T, const PassView& v, int lane,
                                            double& p0, double& p1, double& p2) {
   const int kp = 1 << S.lk;
@@ -968,9 +968,9 @@ __device__ __forceinline__ void batch_item(const BatchSys& S, const BatchTile& T
   if (MIXED && !S.ymode && __any(v.phase == PH_INNER32)) {
     // two-iterate float32 inner slices in the row form; a right-hand side is in one phase
     // only, so one of the two terms added to lane j is zero
-    if (kp == 8) tile_inner_rows<8>(S, T, S.vt, lane, p0, p1);
-    else if (kp == 4) tile_inner_rows<4>(S, T, S.vt, lane, p0, p1);
-    else if (kp == 2) tile_inner_rows<2>(S, T, S.vt, lane, p0, p1);
+    if (KPMAX >= 8 && kp == 8) tile_inner_rows<(KPMAX >= 8 ? 8 : 1)>(S, T, S.vt, lane, p0, p1);
+    else if (KPMAX >= 4 && kp == 4) tile_inner_rows<(KPMAX >= 4 ? 4 : 1)>(S, T, S.vt, lane, p0, p1);
+    else if (KPMAX >= 2 && kp == 2) tile_inner_rows<(KPMAX >= 2 ? 2 : 1)>(S, T, S.vt, lane, p0, p1);
     else tile_inner_rows<1>(S, T, S.vt, lane, p0, p1);
   }
 }
@@ -978,8 +978,10 @@ __device__ __forceinline__ void batch_item(const BatchSys& S, const BatchTile& T
 // One pass of every active instance of the batch.  Each wavefront takes items of the
 // active list on its own (no workgroup barrier): the list is cut into one contiguous
 // range per L2 domain, and the domain's wavefronts take its items in turn.  The next
-// item's index and descriptor are loaded while the current one is worked on.
-template <bool MIXED>
+// item's index and descriptor are loaded while the current one is worked on.  KPMAX is
+// the most right-hand-side lanes of any system (the row form's registers grow with it,
+// so a kernel for one right-hand side per system stays lean).
+template <bool MIXED, int KPMAX>
 __global__ void __launch_bounds__(kBatchBlock) k_batch_pass(BatchArgs ba) {
   const int lane = threadIdx.x % kWave;
   const int nact = uni(*gptr(ba.nactive));
@@ -1021,7 +1023,7 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch_pass(BatchArgs ba) {
     }
     if (live) {
       double p0, p1, p2;
-      batch_item<MIXED>(S, T, v, lane, p0, p1, p2);
+      batch_item<MIXED, KPMAX>(S, T, v, lane, p0, p1, p2);
       if (lane < S.nrhs && v.phase != PH_DONE) {
         double* slot = S.part + ((size_t)lane * S.ntiles + (t - S.tile0)) * kPartStride;
         slot[0] = p0;
@@ -1032,6 +1034,15 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch_pass(BatchArgs ba) {
     p = pn;
     t = uni(tn);
   }
+}
+
+// The pass kernel for a precision and the most right-hand-side lanes of any system.
+inline const void* batch_pass_kernel(bool mixed, int kpmax) {
+  if (!mixed) return (const void*)k_batch_pass<false, 8>;
+  if (kpmax <= 1) return (const void*)k_batch_pass<true, 1>;
+  if (kpmax <= 2) return (const void*)k_batch_pass<true, 2>;
+  if (kpmax <= 4) return (const void*)k_batch_pass<true, 4>;
+  return (const void*)k_batch_pass<true, 8>;
 }
 
 // After a pass: for every system with an unfinished instance (one workgroup each), the

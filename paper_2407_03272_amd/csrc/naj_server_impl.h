@@ -19,6 +19,7 @@ struct naj_server {
   int device = 0;
   naj_opts opts;
   int max_slots = 0;
+  int max_rhs = 0;
   int tile_cap = 0;
   hipStream_t st = nullptr;    // passes (the caller's stream)
   hipStream_t adm = nullptr;   // admission: system builds and uploads
@@ -34,12 +35,12 @@ struct naj_server {
   int* d_nsact = nullptr;
   unsigned int* d_done = nullptr;
   int* d_slot_done = nullptr;
-  int* h_flags = nullptr;      // pinned, 2 x max_slots: slot_done after a chunk
+  static constexpr int kRing = 4;   // chunks in flight at most
+  int* h_flags = nullptr;      // pinned, kRing x max_slots: slot_done after each chunk in flight
   Ctrl* h_ctrl = nullptr;      // pinned, kMaxRhs: a finished request's control blocks
-  hipEvent_t evc[2] = {nullptr, nullptr};
+  hipEvent_t evc[kRing] = {};
   hipEvent_t ev_adm = nullptr;
-  bool inflight[2] = {false, false};
-  int cur = 0;
+  int head = 0, count = 0;     // ring of chunks in flight: oldest at head
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int graph_len = 8;
@@ -109,29 +110,37 @@ void server_scan(naj_server* sv, int buf) {
   }
 }
 
-naj_status server_drain(naj_server* sv) {
-  for (int q = 0; q < 2; ++q) {
-    const int b = sv->cur ^ 1 ^ q;   // older chunk first
-    if (!sv->inflight[b]) continue;
-    HIP_TRY(hipEventSynchronize(sv->evc[b]));
-    sv->inflight[b] = false;
-    server_scan(sv, b);
+// Retires the oldest chunk in flight (waiting for it when `block`): its flags are read.
+// Returns false when there is none, or it has not finished and block is false.
+bool server_retire(naj_server* sv, bool block, naj_status* rc) {
+  *rc = NAJ_OK;
+  if (sv->count == 0) return false;
+  const int b = sv->head;
+  hipError_t e = block ? hipEventSynchronize(sv->evc[b]) : hipEventQuery(sv->evc[b]);
+  if (e == hipErrorNotReady) return false;
+  if (e != hipSuccess) {
+    *rc = fail(NAJ_EDEVICE, "chunk event: %s", hipGetErrorString(e));
+    return false;
   }
-  return NAJ_OK;
+  server_scan(sv, b);
+  sv->head = (sv->head + 1) % naj_server::kRing;
+  sv->count -= 1;
+  return true;
 }
 
 }  // namespace
 
 extern "C" {
 
-naj_status naj_server_create(int64_t mem_budget, int32_t max_slots, const naj_opts* opts, void* stream,
-                             naj_server** out) {
+naj_status naj_server_create(int64_t mem_budget, int32_t max_slots, int32_t max_rhs, const naj_opts* opts,
+                             void* stream, naj_server** out) {
   g_err.clear();
   (void)hipGetLastError();
   if (!out) return fail(NAJ_EINVAL, "out is NULL");
   *out = nullptr;
   if (mem_budget < (1 << 20)) return fail(NAJ_EINVAL, "mem_budget must be at least 1 MiB");
   if (max_slots < 1 || max_slots > 65536) return fail(NAJ_EINVAL, "max_slots must be in [1, 65536]");
+  if (max_rhs < 1 || max_rhs > kMaxRhs) return fail(NAJ_EINVAL, "max_rhs must be in [1, %d]", kMaxRhs);
   naj_opts o;
   if (opts) o = *opts;
   else naj_opts_default(&o);
@@ -173,15 +182,17 @@ naj_status naj_server_create(int64_t mem_budget, int32_t max_slots, const naj_op
   SV_TRY(hipMemsetAsync(sv->d_slot_done, 0, sizeof(int) * max_slots, sv->st));
   SV_TRY(hipMemsetAsync(sv->d_nactive, 0, sizeof(int) * 64, sv->st));
   SV_TRY(hipMemsetAsync(sv->d_nsact, 0, sizeof(int) * 64, sv->st));
-  SV_TRY(hipHostMalloc((void**)&sv->h_flags, sizeof(int) * 2 * max_slots, hipHostMallocDefault));
+  SV_TRY(hipHostMalloc((void**)&sv->h_flags, sizeof(int) * naj_server::kRing * max_slots, hipHostMallocDefault));
   SV_TRY(hipHostMalloc((void**)&sv->h_ctrl, sizeof(Ctrl) * kMaxRhs, hipHostMallocDefault));
-  SV_TRY(hipEventCreateWithFlags(&sv->evc[0], hipEventDisableTiming));
-  SV_TRY(hipEventCreateWithFlags(&sv->evc[1], hipEventDisableTiming));
+  for (int q = 0; q < naj_server::kRing; ++q) SV_TRY(hipEventCreateWithFlags(&sv->evc[q], hipEventDisableTiming));
   SV_TRY(hipEventCreateWithFlags(&sv->ev_adm, hipEventDisableTiming));
   SV_TRY(hipStreamCreateWithFlags(&sv->adm, hipStreamNonBlocking));
   const bool mixed = o.precision == NAJ_MIXED;
   int occ = 0;
-  const void* pass_fn = mixed ? (const void*)k_batch_pass<true> : (const void*)k_batch_pass<false>;
+  int kpmax = 1;
+  while (kpmax < max_rhs) kpmax <<= 1;
+  sv->max_rhs = max_rhs;
+  const void* pass_fn = batch_pass_kernel(mixed, kpmax);
   SV_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, pass_fn, kBatchBlock, 0));
   hipDeviceProp_t prop;
   SV_TRY(hipGetDeviceProperties(&prop, sv->device));
@@ -214,8 +225,8 @@ naj_status naj_server_create(int64_t mem_budget, int32_t max_slots, const naj_op
   if (ce == hipSuccess) {
     hipLaunchKernelGGL(k_batch_compact, dim3(1), dim3(kCompactBlock), 0, cap, A);
     for (int q = 0; q < sv->graph_len; ++q) {
-      if (mixed) hipLaunchKernelGGL(k_batch_pass<true>, dim3(sv->grid), dim3(kBatchBlock), 0, cap, A);
-      else hipLaunchKernelGGL(k_batch_pass<false>, dim3(sv->grid), dim3(kBatchBlock), 0, cap, A);
+      void* kargs[] = {&A};
+      if (ce == hipSuccess) ce = hipLaunchKernel(pass_fn, dim3(sv->grid), dim3(kBatchBlock), kargs, 0, cap);
       hipLaunchKernelGGL(k_batch_decide, dim3(max_slots), dim3(kDecideBlock), 0, cap, A);
     }
     ce = hipStreamEndCapture(cap, &sv->graph);
@@ -235,7 +246,7 @@ naj_status naj_server_admit(naj_server* sv, int64_t n, int64_t nnz, const int32_
   g_err.clear();
   (void)hipGetLastError();
   if (!sv || !ticket || !b || !x) return fail(NAJ_EINVAL, "server, b, x and ticket are required");
-  if (nrhs < 1 || nrhs > kMaxRhs) return fail(NAJ_EINVAL, "nrhs must be in [1, %d]", kMaxRhs);
+  if (nrhs < 1 || nrhs > sv->max_rhs) return fail(NAJ_EINVAL, "nrhs must be in [1, %d] (the server's max_rhs)", sv->max_rhs);
   if (n < 1) return fail(NAJ_EINVAL, "n must be >= 1");
   if (!(tol > 0.0)) tol = sv->opts.tol;
   const bool mixed = sv->opts.precision == NAJ_MIXED;
@@ -329,31 +340,29 @@ naj_status naj_server_step(naj_server* sv, int32_t chunks, int64_t* done, int32_
   if (!sv || (cap > 0 && !done) || !ndone) return fail(NAJ_EINVAL, "server and ndone are required");
   *ndone = 0;
   HIP_TRY(hipSetDevice(sv->device));
+  naj_status rc = NAJ_OK;
   bool active = false;
   for (const auto& sl : sv->slots) active = active || (sl.used && !sl.done);
   if (!active || chunks <= 0) {
-    naj_status rc = server_drain(sv);
+    while (server_retire(sv, true, &rc)) {   // nothing to run: collect every chunk in flight
+    }
     if (rc != NAJ_OK) return rc;
   } else {
     for (int c = 0; c < chunks; ++c) {
-      const int b = sv->cur;
-      if (sv->inflight[b]) {   // this buffer's previous chunk: read it before reusing the buffer
-        HIP_TRY(hipEventSynchronize(sv->evc[b]));
-        sv->inflight[b] = false;
-        server_scan(sv, b);
+      if (sv->count == naj_server::kRing) {   // ring full: wait for the oldest chunk
+        server_retire(sv, true, &rc);
+        if (rc != NAJ_OK) return rc;
       }
+      const int b = (sv->head + sv->count) % naj_server::kRing;
       HIP_TRY(hipGraphLaunch(sv->exec, sv->st));
       HIP_TRY(hipMemcpyAsync(sv->h_flags + (size_t)b * sv->max_slots, sv->d_slot_done, sizeof(int) * sv->max_slots,
                              hipMemcpyDeviceToHost, sv->st));
       HIP_TRY(hipEventRecord(sv->evc[b], sv->st));
-      sv->inflight[b] = true;
-      sv->cur ^= 1;
-      const int prev = sv->cur;   // the other buffer: the chunk before this one
-      if (sv->inflight[prev] && hipEventQuery(sv->evc[prev]) == hipSuccess) {
-        sv->inflight[prev] = false;
-        server_scan(sv, prev);
-      }
+      sv->count += 1;
     }
+    while (server_retire(sv, false, &rc)) {   // every chunk that has already finished
+    }
+    if (rc != NAJ_OK) return rc;
   }
   int k = 0;
   while (k < cap && !sv->ready.empty()) {
@@ -375,14 +384,17 @@ naj_status naj_server_result(naj_server* sv, int64_t ticket, naj_result* res) {
   if (!sl.done) return fail(NAJ_EBUSY, "request %lld has not finished", (long long)ticket);
   HIP_TRY(hipSetDevice(sv->device));
   naj_system* s = sl.sys;
-  hipLaunchKernelGGL(k_batch_store, dim3(blocks_for(s->n * sl.nrhs, kAux * 4)), dim3(kAux), 0, sv->st, sv->d_sys, slot,
+  // A request is found finished only after the chunk it finished in has completed, and no
+  // later pass touches it, so its answer is read on the admission stream without waiting
+  // for the chunks still in flight.  The slot leaves the table in pass-stream order.
+  hipLaunchKernelGGL(k_batch_store, dim3(blocks_for(s->n * sl.nrhs, kAux * 4)), dim3(kAux), 0, sv->adm, sv->d_sys, slot,
                      sl.nrhs, s->perm, s->n, sl.x);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemcpyAsync(sv->h_ctrl, sv->d_ctrl + (size_t)slot * kMaxRhs, sizeof(Ctrl) * sl.nrhs,
-                         hipMemcpyDeviceToHost, sv->st));
+                         hipMemcpyDeviceToHost, sv->adm));
   hipLaunchKernelGGL(k_server_clear, dim3(1), dim3(64), 0, sv->st, sv->args, slot);
   HIP_TRY(hipGetLastError());
-  HIP_TRY(hipStreamSynchronize(sv->st));
+  HIP_TRY(hipStreamSynchronize(sv->adm));
   const bool mixed = sv->opts.precision == NAJ_MIXED;
   naj_status worst = NAJ_OK;
   for (int j = 0; j < sl.nrhs; ++j) {
@@ -401,7 +413,7 @@ naj_status naj_server_result(naj_server* sv, int64_t ticket, naj_result* res) {
     if (c.status < 0 && (worst >= 0 || c.status < worst)) worst = (naj_status)c.status;
     if (worst >= 0 && c.status == ST_NOT_CONVERGED) worst = NAJ_NOT_CONVERGED;
   }
-  server_release_slot(sv, slot);   // the stream is idle: nothing reads the slot's memory any more
+  server_release_slot(sv, slot);   // nothing reads the slot's memory any more
   if (worst == NAJ_EBREAKDOWN) return fail(NAJ_EBREAKDOWN, "NaN/Inf in a reduction of the request");
   return worst;
 }

@@ -74,7 +74,7 @@ _SIGS = {
     "naj_autotune_tiles": (ctypes.c_int, [_P, _I32, ctypes.POINTER(NajOpts), _I32, _P, ctypes.POINTER(_I32)]),
     "naj_tune_save": (ctypes.c_int, [ctypes.c_char_p]),
     "naj_tune_load": (ctypes.c_int, [ctypes.c_char_p]),
-    "naj_server_create": (ctypes.c_int, [_I64, _I32, ctypes.POINTER(NajOpts), _P, ctypes.POINTER(_P)]),
+    "naj_server_create": (ctypes.c_int, [_I64, _I32, _I32, ctypes.POINTER(NajOpts), _P, ctypes.POINTER(_P)]),
     "naj_server_admit": (ctypes.c_int, [_P, _I64, _I64, _P, _P, _P, _P, _I32, _P, _P, _D, _P, ctypes.POINTER(_I64)]),
     "naj_server_step": (ctypes.c_int, [_P, _I32, _P, _I32, ctypes.POINTER(_I32)]),
     "naj_server_result": (ctypes.c_int, [_P, _I64, ctypes.POINTER(NajResult)]),
@@ -358,7 +358,8 @@ class Server:
     so that uploads on other streams do not wait for them).
     """
 
-    def __init__(self, mem_budget: int, max_slots: int = 64, device="cuda:0", stream=None, **opts):
+    def __init__(self, mem_budget: int, max_slots: int = 64, max_rhs: int = NAJ_MAX_RHS, device="cuda:0",
+                 stream=None, **opts):
         torch = _torch()
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
@@ -366,7 +367,7 @@ class Server:
         o = default_opts(**opts)
         h = _P()
         with torch.cuda.device(self.device):
-            _check(load().naj_server_create(int(mem_budget), int(max_slots), ctypes.byref(o),
+            _check(load().naj_server_create(int(mem_budget), int(max_slots), int(max_rhs), ctypes.byref(o),
                                             ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
         self._h = h
         self._req = {}     # ticket -> (x tensor, nrhs, inputs kept alive until admitted)
