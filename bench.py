@@ -281,6 +281,7 @@ def run_server(naj, reqs, budget, slots, closed_loop, progress, label):
     nxt, ndone, busy_max, bad = 0, 0, 0, 0
     last_report = 0.0
     host = {"admit": 0.0, "step": 0.0, "result": 0.0, "steps": 0}
+    staged = None
     t0 = time.perf_counter()
     while ndone < len(reqs):
         now = time.perf_counter() - t0
@@ -291,11 +292,15 @@ def run_server(naj, reqs, budget, slots, closed_loop, progress, label):
         while queue:
             i = queue[0]
             r = reqs[i]
-            t = srv.admit(r["sys"].rowptr, r["sys"].colidx, r["sys"].vals, r["b"], tol=r["tol"])
+            if staged is None or staged[0] != i:   # upload once; a busy server is retried with the same copies
+                staged = (i, srv.stage(r["sys"].rowptr, r["sys"].colidx, r["sys"].vals, r["b"]))
+            rp, ci, va, bb, _, _ = staged[1]
+            t = srv.admit(rp, ci, va, bb, tol=r["tol"])
             if t is None:
                 break
             tickets[t] = i
             queue.popleft()
+            staged = None
         tb = time.perf_counter()
         busy_max = max(busy_max, len(queue))
         active = len(tickets) > 0

@@ -209,7 +209,7 @@ __global__ void __launch_bounds__(kAux) k_step64(SolveArgs a, const double* P, c
   m.beta_next = 0.0;
   m.bz = bz != 0;
   m.ym = false;
-  pass_iter64<USER_D, kAux>(a, P, m, W, p0, p1, p2);
+  pass_iter64<USER_D, kAux, false>(a, P, m, W, p0, p1, p2);
   block_sum3<kAux>(p0, p1, p2, sh);
   if (threadIdx.x == 0) {
     double* slot = a.part + (size_t)blockIdx.x * kPartStride;
@@ -443,14 +443,20 @@ int blocks_for(int64_t work, int per_block) {
 constexpr int kModePass = 0, kModeSmall = 1, kModePersistent = 2;
 constexpr int kSmallBlock = 1024;
 
-const void* pass_kernel(bool user_d, int bs) {
-  if (bs == 1024) return user_d ? (const void*)k_pass64<true, 1024> : (const void*)k_pass64<false, 1024>;
-  if (bs == 512) return user_d ? (const void*)k_pass64<true, 512> : (const void*)k_pass64<false, 512>;
-  return user_d ? (const void*)k_pass64<true, 256> : (const void*)k_pass64<false, 256>;
+template <bool YM>
+const void* pass_kernel_ym(bool user_d, int bs) {
+  if (bs == 1024) return user_d ? (const void*)k_pass64<true, 1024, YM> : (const void*)k_pass64<false, 1024, YM>;
+  if (bs == 512) return user_d ? (const void*)k_pass64<true, 512, YM> : (const void*)k_pass64<false, 512, YM>;
+  return user_d ? (const void*)k_pass64<true, 256, YM> : (const void*)k_pass64<false, 256, YM>;
 }
 
-const void* solve_kernel(bool user_d) {
-  return user_d ? (const void*)k_solve64<true, kSmallBlock> : (const void*)k_solve64<false, kSmallBlock>;
+const void* pass_kernel(bool user_d, int bs, bool ym) {
+  return ym ? pass_kernel_ym<true>(user_d, bs) : pass_kernel_ym<false>(user_d, bs);
+}
+
+const void* solve_kernel(bool user_d, bool ym) {
+  if (ym) return user_d ? (const void*)k_solve64<true, kSmallBlock, true> : (const void*)k_solve64<false, kSmallBlock, true>;
+  return user_d ? (const void*)k_solve64<true, kSmallBlock, false> : (const void*)k_solve64<false, kSmallBlock, false>;
 }
 
 naj_status choose_grid(naj_system* s, hipStream_t st) {
@@ -484,8 +490,8 @@ naj_status choose_grid(naj_system* s, hipStream_t st) {
     HIP_TRY(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, s->device));
     if (!coop) return fail(NAJ_EDEVICE, "device %d does not support cooperative launches", s->device);
     int occ1 = 0, occ2 = 0;
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ1, solve_kernel(false), kSmallBlock, 0));
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ2, solve_kernel(true), kSmallBlock, 0));
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ1, solve_kernel(false, s->ymode != 0), kSmallBlock, 0));
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ2, solve_kernel(true, s->ymode != 0), kSmallBlock, 0));
     int resident = std::min(occ1, occ2) * s->cus;
     resident -= resident % nxcd;
     if (resident < nxcd) return fail(NAJ_EDEVICE, "persistent solve kernel cannot be resident");
@@ -503,9 +509,10 @@ naj_status choose_grid(naj_system* s, hipStream_t st) {
     s->aux_grid = (int)std::max<int64_t>(nxcd, std::min<int64_t>(std::max(ga, nxcd), wa));
     s->max_grid = std::max(s->max_grid, s->aux_grid);
   }
-  if (nxcd > 1 && s->nslices >= nxcd) {
+  if (nxcd > 1 && s->nslices >= nxcd && env_int("NAJ_BALANCE", s->layout == 1 ? 1 : 0)) {
     // L2 domains get contiguous slice ranges of equal weight: stored entries (12 B each in
-    // float64) plus the 64 rows' vector traffic (about 4 streams of 8 B per row)
+    // float64) plus the 64 rows' vector traffic (about 4 streams of 8 B per row).  Sorted
+    // (irregular) layouts only: regular slices are equal to within a few percent.
     std::vector<int64_t> wpre(s->nslices + 1), bounds(nxcd + 1);
     for (int64_t i = 0; i <= s->nslices; ++i) wpre[i] = s->hslice[i] * 12 / kWave + i * 32;
     balanced_bounds(wpre.data(), s->nslices, nxcd, bounds.data());
@@ -774,19 +781,19 @@ naj_status run_solve(naj_system* s, SolveArgs& a, const naj_opts& o, hipStream_t
   void* kargs[] = {&a};
   if (s->mode == kModeSmall) {
     HIP_TRY(hipEventRecord(s->ev0, st));
-    HIP_TRY(hipLaunchKernel(solve_kernel(ud), dim3(1), dim3(kSmallBlock), kargs, 0, st));
+    HIP_TRY(hipLaunchKernel(solve_kernel(ud, s->ymode != 0), dim3(1), dim3(kSmallBlock), kargs, 0, st));
     HIP_TRY(hipEventRecord(s->ev1, st));
     return NAJ_OK;
   }
   if (s->mode == kModePersistent) {
     HIP_TRY(hipEventRecord(s->ev0, st));
-    HIP_TRY(hipLaunchCooperativeKernel(solve_kernel(ud), dim3(s->grid), dim3(kSmallBlock), kargs, 0, st));
+    HIP_TRY(hipLaunchCooperativeKernel(solve_kernel(ud, s->ymode != 0), dim3(s->grid), dim3(kSmallBlock), kargs, 0, st));
     HIP_TRY(hipEventRecord(s->ev1, st));
     return NAJ_OK;
   }
   // one launch per pass, enqueued in chunks; the host checks the phase word of
   // the previous chunk while the current one runs, so the device never waits
-  const void* fn = pass_kernel(ud, s->pass_bs);
+  const void* fn = pass_kernel(ud, s->pass_bs, s->ymode != 0);
   const dim3 grid(s->grid), block(s->pass_bs);
   // passes: norm of b + iterations + confirmations (at most one per confirm_gap iterations, plus one)
   const int64_t max_pass = o.precision == NAJ_MIXED
@@ -1113,8 +1120,8 @@ static naj_status create_system_impl(int64_t n, int64_t nnz, const int32_t* rowp
     goto bad;
   }
   STEP(build_layout(s, rowptr, colidx, vals, st));
-  STEP(choose_grid(s, st));
   s->ymode = env_int("NAJ_YMODE", s->layout == 1 ? 1 : 0) ? 1 : 0;
+  STEP(choose_grid(s, st));
   if (!lean) {   // workspace of the single-solve drivers
     for (int i = 0; i < 3 + s->ymode; ++i) STEP(dev_alloc(s, &s->vec[i], (size_t)n));
     STEP(dev_alloc(s, &s->part, (size_t)kPartStride * s->max_grid));

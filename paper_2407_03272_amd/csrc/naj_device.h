@@ -194,13 +194,14 @@ __device__ __forceinline__ WaveRange wave_range(const Sell& A, int nxcd) {
 
 // One slice of the fused pass: u = Q y, g = u - b, x = y - J^{-1} g, d = x - P,
 // with y = P + beta (P - R) formed at every gathered column (y = P when bz).
-template <bool USER_D>
+template <bool USER_D, bool YM>
 __device__ __forceinline__ void iter_slice(const SolveArgs& a, int64_t s, int lane, const double* __restrict__ P,
                                            const Momentum<double>& m, double* __restrict__ W, double& ps, double& pgg,
                                            double& psabs) {
   const double* __restrict__ R = m.R;
   const double beta = m.beta;
-  const bool bz = m.bz, ym = m.ym;
+  const bool bz = m.bz;
+  constexpr bool ym = YM;
   const int64_t base = a.A.slice_ptr[s];
   const int width = (int)((a.A.slice_ptr[s + 1] - base) >> 6);
   const int64_t row = a.A.row0 + s * kWave + lane;
@@ -258,7 +259,7 @@ __device__ __forceinline__ void iter_slice(const SolveArgs& a, int64_t s, int la
     const double xi = yi - dv * g;
     W[row] = xi;
     const double d = xi - Pi;
-    if (m.Yn) m.Yn[row] = xi + m.beta_next * d;
+    if (YM && m.Yn) m.Yn[row] = xi + m.beta_next * d;
     const double gd = g * d;
     ps = ps + gd;
     pgg = pgg + g * g;
@@ -304,13 +305,14 @@ __device__ __forceinline__ void resid_slice(const Sell& A, int64_t s, int lane, 
 // iter_slice on Q d = r32 with float32 values, vectors and row sums; the
 // restart inner product and the monitor are accumulated in float64 from
 // exactly converted float32 operands.  zp: the previous iterate is zero.
-template <bool USER_D>
+template <bool USER_D, bool YM>
 __device__ __forceinline__ void inner_slice(const SolveArgs& a, int64_t s, int lane, const float* __restrict__ P,
                                             const Momentum<float>& m, float* __restrict__ W, bool zp, double& ps,
                                             double& pgg, double& psabs) {
   const float* __restrict__ R = m.R;
   const float beta = m.beta;
-  const bool bz = m.bz, ym = m.ym;
+  const bool bz = m.bz;
+  constexpr bool ym = YM;
   const int64_t base = a.A.slice_ptr[s];
   const int width = (int)((a.A.slice_ptr[s + 1] - base) >> 6);
   const int64_t row = a.A.row0 + s * kWave + lane;
@@ -369,7 +371,7 @@ __device__ __forceinline__ void inner_slice(const SolveArgs& a, int64_t s, int l
     const float xi = yi - dv * g;
     W[row] = xi;
     const float d = xi - Pi;
-    if (m.Yn) m.Yn[row] = xi + m.beta_next * d;
+    if (YM && m.Yn) m.Yn[row] = xi + m.beta_next * d;
     const double g64 = (double)g, d64 = (double)d;
     const double gd = g64 * d64;
     ps = ps + gd;
@@ -475,13 +477,14 @@ __device__ __forceinline__ void long_row_sums(const int32_t* __restrict__ col, c
   }
 }
 
-template <bool USER_D>
+template <bool USER_D, bool YM>
 __device__ __forceinline__ void iter_long(const SolveArgs& a, int64_t r, int lane, const double* __restrict__ P,
                                           const Momentum<double>& m, double* __restrict__ W, double& ps, double& pgg,
                                           double& psabs) {
   const double* __restrict__ R = m.R;
   const double beta = m.beta;
-  const bool bz = m.bz, ym = m.ym;
+  const bool bz = m.bz;
+  constexpr bool ym = YM;
   double acc, asum;
   const int64_t s = a.A.lrowptr[r], e = a.A.lrowptr[r + 1];
   if (bz)
@@ -501,7 +504,7 @@ __device__ __forceinline__ void iter_long(const SolveArgs& a, int64_t r, int lan
     const double xi = yi - dv * g;
     W[r] = xi;
     const double dd = xi - Pi;
-    if (m.Yn) m.Yn[r] = xi + m.beta_next * dd;
+    if (YM && m.Yn) m.Yn[r] = xi + m.beta_next * dd;
     const double gd = g * dd;
     ps = ps + gd;
     pgg = pgg + g * g;
@@ -521,13 +524,14 @@ __device__ __forceinline__ void resid_long(const Sell& A, int64_t r, int lane, c
   }
 }
 
-template <bool USER_D>
+template <bool USER_D, bool YM>
 __device__ __forceinline__ void inner_long(const SolveArgs& a, int64_t r, int lane, const float* __restrict__ P,
                                            const Momentum<float>& m, float* __restrict__ W, bool zp, double& ps,
                                            double& pgg, double& psabs) {
   const float* __restrict__ R = m.R;
   const float beta = m.beta;
-  const bool bz = m.bz, ym = m.ym;
+  const bool bz = m.bz;
+  constexpr bool ym = YM;
   float acc, asum;
   const int64_t s = a.A.lrowptr[r], e = a.A.lrowptr[r + 1];
   if (zp)
@@ -549,7 +553,7 @@ __device__ __forceinline__ void inner_long(const SolveArgs& a, int64_t r, int la
     const float xi = yi - dv * g;
     W[r] = xi;
     const float dd = xi - Pi;
-    if (m.Yn) m.Yn[r] = xi + m.beta_next * dd;
+    if (YM && m.Yn) m.Yn[r] = xi + m.beta_next * dd;
     const double g64 = (double)g, d64 = (double)dd;
     const double gd = g64 * d64;
     ps = ps + gd;

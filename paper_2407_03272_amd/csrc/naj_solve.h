@@ -322,15 +322,17 @@ __device__ __forceinline__ void load_view(const Ctrl* c, PassView* v) {
   v->beta_next = c->beta_next;
 }
 
-// The workgroup's share of one float64 iteration pass (long rows, then slices).
-template <bool USER_D, int BS>
+// The workgroup's share of one float64 iteration pass (long rows, then slices).  YM: the
+// materialized momentum form (a compile-time choice, so the two-iterate kernel carries none
+// of the materialized form's code).
+template <bool USER_D, int BS, bool YM>
 __device__ __forceinline__ void pass_iter64(const SolveArgs& a, const double* P, const Momentum<double>& m, double* W,
                                             double& p0, double& p1, double& p2) {
   const int lane = threadIdx.x % kWave;
   const LongRange<BS> lr;
-  for (int64_t r = lr.first; r < a.A.n_long; r += lr.step) iter_long<USER_D>(a, r, lane, P, m, W, p0, p1, p2);
+  for (int64_t r = lr.first; r < a.A.n_long; r += lr.step) iter_long<USER_D, YM>(a, r, lane, P, m, W, p0, p1, p2);
   const WaveRange wr = wave_range<BS>(a.A, a.nxcd);
-  for (int64_t s = wr.first; s < wr.end; s += wr.step) iter_slice<USER_D>(a, s, lane, P, m, W, p0, p1, p2);
+  for (int64_t s = wr.first; s < wr.end; s += wr.step) iter_slice<USER_D, YM>(a, s, lane, P, m, W, p0, p1, p2);
 }
 
 // The workgroup's share of r = b - Q X (float64); ||r||^2 in p0.
@@ -345,19 +347,19 @@ __device__ __forceinline__ void pass_resid64(const Sell& A, int nxcd, const doub
 }
 
 // The workgroup's share of one pass; partial sums in p0..p2 (per thread).
-template <bool USER_D, int BS>
+template <bool USER_D, int BS, bool YM>
 __device__ __forceinline__ void run_pass(const SolveArgs& a, const PassView& v, double& p0, double& p1,
                                          double& p2) {
   const int lane = threadIdx.x % kWave;
   if (v.phase == PH_ITER) {
     Momentum<double> m;
     m.R = pick(a, v.iR);
-    m.Yn = (a.ymode && v.iYn >= 0) ? pick(a, v.iYn) : nullptr;
+    m.Yn = (YM && v.iYn >= 0) ? pick(a, v.iYn) : nullptr;
     m.beta = v.beta;
     m.beta_next = v.beta_next;
     m.bz = v.bz != 0;
-    m.ym = a.ymode != 0;
-    pass_iter64<USER_D, BS>(a, pick(a, v.iP), m, pick(a, v.iW), p0, p1, p2);
+    m.ym = YM;
+    pass_iter64<USER_D, BS, YM>(a, pick(a, v.iP), m, pick(a, v.iW), p0, p1, p2);
   } else if (v.phase == PH_CONFIRM) {
     pass_resid64<BS>(a.A, a.nxcd, pick(a, v.iW), a.b, nullptr, p0);
   } else if (v.phase == PH_INNER32) {
@@ -365,16 +367,16 @@ __device__ __forceinline__ void run_pass(const SolveArgs& a, const PassView& v, 
     float* W = pickf(a, v.iW);
     Momentum<float> m;
     m.R = pickf(a, v.iR);
-    m.Yn = (a.ymode && v.iYn >= 0) ? pickf(a, v.iYn) : nullptr;
+    m.Yn = (YM && v.iYn >= 0) ? pickf(a, v.iYn) : nullptr;
     m.beta = (float)v.beta;
     m.beta_next = (float)v.beta_next;
     m.bz = v.bz != 0;
-    m.ym = a.ymode != 0;
+    m.ym = YM;
     const bool zp = v.zp != 0;
     const LongRange<BS> lr;
-    for (int64_t r = lr.first; r < a.A.n_long; r += lr.step) inner_long<USER_D>(a, r, lane, P, m, W, zp, p0, p1, p2);
+    for (int64_t r = lr.first; r < a.A.n_long; r += lr.step) inner_long<USER_D, YM>(a, r, lane, P, m, W, zp, p0, p1, p2);
     const WaveRange wr = wave_range<BS>(a.A, a.nxcd);
-    for (int64_t s = wr.first; s < wr.end; s += wr.step) inner_slice<USER_D>(a, s, lane, P, m, W, zp, p0, p1, p2);
+    for (int64_t s = wr.first; s < wr.end; s += wr.step) inner_slice<USER_D, YM>(a, s, lane, P, m, W, zp, p0, p1, p2);
   } else if (v.phase == PH_RESID64) {
     const double* X = pick(a, v.iX);
     const float* D = v.update ? pickf(a, v.iD) : nullptr;
@@ -394,7 +396,7 @@ __device__ __forceinline__ void run_pass(const SolveArgs& a, const PassView& v, 
 // One pass per launch.  The last workgroup to finish reduces the partials and
 // updates the control block for the next launch; launches after the solve has
 // finished return at once.
-template <bool USER_D, int BS>
+template <bool USER_D, int BS, bool YM>
 __global__ void __launch_bounds__(BS) k_pass64(SolveArgs a) {
   __shared__ double sh[3][BS / kWave];
   __shared__ PassView v;
@@ -403,7 +405,7 @@ __global__ void __launch_bounds__(BS) k_pass64(SolveArgs a) {
   __syncthreads();
   if (v.phase == PH_DONE) return;
   double p0 = 0.0, p1 = 0.0, p2 = 0.0;
-  run_pass<USER_D, BS>(a, v, p0, p1, p2);
+  run_pass<USER_D, BS, YM>(a, v, p0, p1, p2);
   block_sum3<BS>(p0, p1, p2, sh);
   const int G = gridDim.x;
   if (threadIdx.x == 0) {
@@ -447,7 +449,7 @@ __global__ void __launch_bounds__(BS) k_pass64(SolveArgs a) {
 }
 
 // One persistent launch per solve (see the file comment).
-template <bool USER_D, int BS>
+template <bool USER_D, int BS, bool YM>
 __global__ void __launch_bounds__(BS) k_solve64(SolveArgs a) {
   __shared__ double sh[3][BS / kWave];
   __shared__ PassView v;
@@ -478,7 +480,7 @@ __global__ void __launch_bounds__(BS) k_solve64(SolveArgs a) {
     __syncthreads();
     if (v.phase == PH_DONE) break;
     double p0 = 0.0, p1 = 0.0, p2 = 0.0;
-    run_pass<USER_D, BS>(a, v, p0, p1, p2);
+    run_pass<USER_D, BS, YM>(a, v, p0, p1, p2);
     block_sum3<BS>(p0, p1, p2, sh);
     if (G == 1) {
       // single workgroup: every wave runs on this CU, a workgroup barrier orders the passes

@@ -379,18 +379,23 @@ class Server:
             return a.to(device=self.device, dtype=dtype).contiguous()
         return torch.as_tensor(np.ascontiguousarray(a)).to(device=self.device, dtype=dtype).contiguous()
 
+    def stage(self, rowptr, colidx, vals, b, x0=None, D=None):
+        """Device copies of a request's inputs (made on the upload stream), for admit; a request
+        that finds the server busy can be retried with them without uploading again."""
+        torch = _torch()
+        with torch.cuda.device(self.device), torch.cuda.stream(self.upload):
+            out = (self._dev(rowptr, torch.int32), self._dev(colidx, torch.int32), self._dev(vals, torch.float64),
+                   self._dev(b, torch.float64), None if x0 is None else self._dev(x0, torch.float64),
+                   None if D is None else self._dev(D, torch.float64))
+        self.upload.synchronize()
+        return out
+
     def admit(self, rowptr, colidx, vals, b, x0=None, D=None, tol: float = 0.0):
         """Returns a ticket, or None when the server is busy (no slot or budget free now)."""
         torch = _torch()
-        with torch.cuda.device(self.device), torch.cuda.stream(self.upload):
-            rp = self._dev(rowptr, torch.int32)
-            ci = self._dev(colidx, torch.int32)
-            va = self._dev(vals, torch.float64)
-            bb = self._dev(b, torch.float64)
-            x0t = None if x0 is None else self._dev(x0, torch.float64)
-            Dt = None if D is None else self._dev(D, torch.float64)
+        rp, ci, va, bb, x0t, Dt = self.stage(rowptr, colidx, vals, b, x0, D)
+        with torch.cuda.device(self.device):
             x = torch.empty_like(bb)
-        self.upload.synchronize()
         n = rp.numel() - 1
         nrhs = 1 if bb.dim() == 1 else int(bb.shape[1])
         t = _I64()
