@@ -82,6 +82,69 @@ def jacobi_diagonal(Q: sp.csr_matrix) -> np.ndarray:
     return J
 
 
+def block_jacobi_blocks(Q: sp.csr_matrix, nb: int) -> np.ndarray:
+    """Diagonal blocks of the block-diagonal J of eq. (J-blkdiag), Section 3.
+
+    The rows are partitioned into s = ceil(n / nb) blocks of nb consecutive
+    rows (Section 3's partition of Q into blocks Q^{i,j} with n_i rows; here
+    n_i = nb, the last block keeping the n - (s-1) nb rows that remain), and
+
+        J^{i,i} = Q^{i,i} + sum_{j != i} ||Q^{i,j}||_2 I_{n_i}.
+
+    The spectral norms are taken by the library SVD of each nonzero
+    off-diagonal block, and added to the shift in increasing j.  A zero
+    diagonal entry of J^{i,i} (a zero row of Q in a block coupled to no other
+    block) is replaced by 1, as for the diagonal J.  Returns an array of shape
+    (s, nb, nb); rows and columns of the last block beyond n are those of the
+    identity.
+    """
+    n = Q.shape[0]
+    s = -(-n // nb)
+    C = Q.tocoo()
+    r, c, v = C.row.astype(np.int64), C.col.astype(np.int64), C.data.astype(np.float64)
+    bi, bj = r // nb, c // nb
+    Jb = np.zeros((s, nb, nb))
+    diag = bi == bj
+    np.add.at(Jb, (bi[diag], r[diag] % nb, c[diag] % nb), v[diag])
+    off = ~diag
+    key = bi[off] * s + bj[off]
+    keys, grp = np.unique(key, return_inverse=True)
+    M = np.zeros((len(keys), nb, nb))
+    np.add.at(M, (grp, r[off] % nb, c[off] % nb), v[off])
+    norms = np.linalg.norm(M, ord=2, axis=(1, 2)) if len(keys) else np.zeros(0)
+    shift = np.zeros(s)
+    for g, k in enumerate(keys):          # keys ascend in (i, j): each shift sums its norms in increasing j
+        i = int(k // s)
+        shift[i] = shift[i] + norms[g]
+    for i in range(s):
+        ni = min(nb, n - i * nb)
+        for k in range(ni):
+            Jb[i, k, k] = Jb[i, k, k] + shift[i]
+            if Jb[i, k, k] == 0.0:
+                Jb[i, k, k] = 1.0
+        for k in range(ni, nb):
+            Jb[i, k, k] = 1.0
+    return Jb
+
+
+def block_solve(Jb: np.ndarray, g: np.ndarray) -> np.ndarray:
+    """z = J^{-1} g for the block-diagonal J: one dense solve per block (library LU)."""
+    s, nb, _ = Jb.shape
+    n = g.shape[0]
+    gp = np.zeros(s * nb)
+    gp[:n] = g
+    return np.linalg.solve(Jb, gp.reshape(s, nb, 1))[:, :, 0].reshape(-1)[:n]
+
+
+def block_matrix(Jb: np.ndarray, n: int) -> np.ndarray:
+    """The dense n x n block-diagonal J assembled from its blocks (small systems only)."""
+    s, nb, _ = Jb.shape
+    J = np.zeros((s * nb, s * nb))
+    for i in range(s):
+        J[i * nb:(i + 1) * nb, i * nb:(i + 1) * nb] = Jb[i]
+    return J[:n, :n]
+
+
 def objective(Q: sp.csr_matrix, b: np.ndarray, x: np.ndarray) -> float:
     """f(x) = 1/2 <x, Q x> - <b, x>, eq. (eq-qp)."""
     return 0.5 * float(x @ (Q @ x)) - float(b @ x)
@@ -92,21 +155,25 @@ def alpha_next(alpha: float) -> float:
     return (1.0 + math.sqrt(1.0 + 4.0 * alpha * alpha)) / 2.0
 
 
-def fused_step(rowptr, colidx, vals, p, r, beta, b, D=None):
+def fused_step(rowptr, colidx, vals, p, r, beta, b, D=None, jblock=None):
     """One pass of Algorithm 3's row update with the momentum point formed from two iterates.
 
     y = p + beta (p - r) (y = p when beta == 0; Algorithm 1, momentum step),
-    x = y + J^{-1}(b - Q y) (Section 3 update), and the reductions the restart
+    x = y + J^{-1}(b - Q y) (Section 3 update; J of eq. (J-diag), the caller's
+    D, or the block J of eq. (J-blkdiag) with blocks of ``jblock`` rows), and the reductions the restart
     test and the monitor use: s = <Q y - b, x - p>, gg = ||Q y - b||^2,
     sabs = sum |(Q y - b)_i (x - p)_i|.  Returns (x, s, gg, sabs).
     """
     Q = csr(rowptr, colidx, vals)
-    J = jacobi_diagonal(Q) if D is None else np.asarray(D, dtype=np.float64)
-    dinv = 1.0 / J
     p = np.asarray(p, dtype=np.float64)
     y = p.copy() if beta == 0.0 else p + beta * (p - np.asarray(r, dtype=np.float64))
     g = Q @ y - np.asarray(b, dtype=np.float64)
-    x = y - dinv * g
+    if jblock is not None:
+        x = y - block_solve(block_jacobi_blocks(Q, jblock), g)
+    else:
+        J = jacobi_diagonal(Q) if D is None else np.asarray(D, dtype=np.float64)
+        dinv = 1.0 / J
+        x = y - dinv * g
     d = x - p
     return x, float(g @ d), float(g @ g), float(np.abs(g * d).sum())
 
@@ -127,12 +194,14 @@ class OracleResult:
 def accelerated_jacobi(rowptr, colidx, vals, b, x0=None, *, tol: float = 1e-8, max_iter: int = 5000,
                        restart: bool = True, k0: int = 2, D: np.ndarray | None = None,
                        confirm_gap: int = 8, forced_restarts: Iterable[int] | None = None,
-                       callback: Callable | None = None) -> OracleResult:
+                       callback: Callable | None = None, jblock: int | None = None) -> OracleResult:
     """Algorithm 3 (Section 3) with diagonal J, in float64.
 
     ``restart`` is the IsRestart switch of Algorithm 3 (False gives Algorithm 1
     with S = J - Q).  ``D`` replaces J when given (Remark 1 allows any
-    invertible J with J - Q PSD).  ``forced_restarts``, when given, replaces
+    invertible J with J - Q PSD).  ``jblock`` selects the block-diagonal J of
+    eq. (J-blkdiag) with blocks of that many consecutive rows (Algorithm 3 with
+    its block update).  ``forced_restarts``, when given, replaces
     the restart test by that exact set of iterations (used to replay a run
     whose restart test was a numerical tie).  ``callback(t, info)`` sees every
     iteration's vectors (used by invariant tests).
@@ -140,8 +209,17 @@ def accelerated_jacobi(rowptr, colidx, vals, b, x0=None, *, tol: float = 1e-8, m
     Q = csr(rowptr, colidx, vals)
     n = Q.shape[0]
     b = np.asarray(b, dtype=np.float64)
-    J = jacobi_diagonal(Q) if D is None else np.asarray(D, dtype=np.float64).copy()
-    dinv = 1.0 / J
+    if jblock is not None:
+        Jb = block_jacobi_blocks(Q, jblock)
+
+        def jinv_apply(g):
+            return block_solve(Jb, g)
+    else:
+        J = jacobi_diagonal(Q) if D is None else np.asarray(D, dtype=np.float64).copy()
+        dinv = 1.0 / J
+
+        def jinv_apply(g):
+            return dinv * g
     x0 = np.zeros(n) if x0 is None else np.asarray(x0, dtype=np.float64).copy()
     forced = None if forced_restarts is None else set(int(t) for t in forced_restarts)
 
@@ -162,7 +240,7 @@ def accelerated_jacobi(rowptr, colidx, vals, b, x0=None, *, tol: float = 1e-8, m
         # Jacobi-type step of Section 3: x^t = y^t + J^{-1}(b - Q y^t)
         u = Q @ y
         g = u - b
-        x = y - dinv * g
+        x = y - jinv_apply(g)
         mon = float(np.linalg.norm(g)) / nb
         res.hist.append(mon)
         if not math.isfinite(mon):
@@ -225,9 +303,30 @@ class MixedResult:
     inner_restarts: list = field(default_factory=list)
 
 
+def block_apply_fp32(jinv32: np.ndarray, g: np.ndarray) -> np.ndarray:
+    """z = fl32(J^{-1}) g in float32 for the block-diagonal J, block by block.
+
+    ``jinv32[i, r, k]`` is entry (r, k) of fl32((J^{i,i})^{-1}); each z_r adds the
+    products of its block's columns k = 0, 1, ... in that order, in float32.
+    """
+    f32 = np.float32
+    s, nb, _ = jinv32.shape
+    n = g.shape[0]
+    gp = np.zeros(s * nb, dtype=f32)
+    gp[:n] = g
+    G = gp.reshape(s, nb)
+    z = (jinv32[:, :, 0] * G[:, 0:1]).astype(f32)
+    for k in range(1, nb):
+        z = (z + (jinv32[:, :, k] * G[:, k:k + 1]).astype(f32)).astype(f32)
+    return z.reshape(-1)[:n]
+
+
 def inner_solve_fp32(Q32: sp.csr_matrix, dinv32: np.ndarray, r32: np.ndarray, *, inner_tol: float,
                      max_iter: int, restart: bool, k0: int, stall: int = 200):
     """Algorithm 3 on Q d = r in float32 from d^0 = 0 with float64 reductions.
+
+    ``dinv32`` is the float32 diagonal of J^{-1}, or, for the block J of
+    eq. (J-blkdiag), the stack of float32 inverse blocks (``block_apply_fp32``).
 
     The product, the Jacobi-type step and the momentum step are float32
     operations (float32 accumulation in the row sums; the momentum coefficient
@@ -258,7 +357,7 @@ def inner_solve_fp32(Q32: sp.csr_matrix, dinv32: np.ndarray, r32: np.ndarray, *,
     for t in range(1, max_iter + 1):
         u = Q32 @ y
         g = (u - r32).astype(f32)
-        x = (y - dinv32 * g).astype(f32)
+        x = (y - (dinv32 * g if dinv32.ndim == 1 else block_apply_fp32(dinv32, g))).astype(f32)
         g64 = g.astype(np.float64)
         mon = math.sqrt(float(g64 @ g64)) / nr
         d = (x - x_prev).astype(f32)
@@ -287,14 +386,17 @@ def inner_solve_fp32(Q32: sp.csr_matrix, dinv32: np.ndarray, r32: np.ndarray, *,
 
 def accelerated_jacobi_mixed(rowptr, colidx, vals, b, x0=None, *, tol: float = 1e-8, max_refine: int = 50,
                              inner_tol: float = 1e-4, inner_max_iter: int = 20000, restart: bool = True,
-                             k0: int = 2, D: np.ndarray | None = None, inner_stall: int = 200) -> MixedResult:
+                             k0: int = 2, D: np.ndarray | None = None, inner_stall: int = 200,
+                             jblock: int | None = None) -> MixedResult:
     """Float32 inner Algorithm 3 inside float64 iterative refinement.
 
     Outer step k = 0, 1, ...: r_k = b - Q x_k with float64 values and
     accumulation; stop when ||r_k|| / ||b|| <= tol, or (NOT_CONVERGED) when k
     reaches ``max_refine`` or fl32(r_k) is zero; otherwise solve Q d = fl32(r_k)
     approximately with ``inner_solve_fp32`` (float32 copy of Q, J from the
-    float32 row absolute sums, or fl32(1/D) for a caller diagonal) and set
+    float32 row absolute sums, or fl32(1/D) for a caller diagonal, or for the
+    block J of eq. (J-blkdiag) with blocks of ``jblock`` rows fl32 of the
+    float64 inverse of each block) and set
     x_{k+1} = x_k + d in float64.  A non-finite inner reduction ends the solve
     with BREAKDOWN and x_k.  The refinement loop is not part of the paper; the
     paper's algorithm is the inner solver.
@@ -302,7 +404,9 @@ def accelerated_jacobi_mixed(rowptr, colidx, vals, b, x0=None, *, tol: float = 1
     Q = csr(rowptr, colidx, vals)
     Q32 = csr(rowptr, colidx, np.asarray(vals, dtype=np.float32), dtype=np.float32)
     n = Q.shape[0]
-    if D is None:
+    if jblock is not None:
+        dinv32 = np.linalg.inv(block_jacobi_blocks(Q, jblock)).astype(np.float32)
+    elif D is None:
         J32 = jacobi_diagonal(Q32)
         dinv32 = (np.float32(1.0) / J32).astype(np.float32)
     else:
@@ -416,7 +520,8 @@ def dense_limit_spsd(rowptr, colidx, vals, b, x0, J=None) -> np.ndarray:
     Each step is J-affine and N^T Q = 0, N^T b = 0 for a null-space basis N, so
     N^T J x^t = N^T J x^0 for every t (follows from the update of Section 3).
     The limit is therefore x_p - N (N^T J N)^{-1} N^T J (x_p - x^0), with
-    x_p = Q^+ b the minimum-norm solution.
+    x_p = Q^+ b the minimum-norm solution.  ``J`` is the diagonal (a vector) or
+    a dense symmetric J (the block-diagonal J of eq. (J-blkdiag)).
     """
     Qs = csr(rowptr, colidx, vals)
     Q = Qs.toarray()
@@ -428,6 +533,6 @@ def dense_limit_spsd(rowptr, colidx, vals, b, x0, J=None) -> np.ndarray:
     xp = np.linalg.pinv(Q, rcond=1e-12, hermitian=True) @ b
     if N.shape[1] == 0:
         return xp
-    JN = J[:, None] * N
+    JN = J[:, None] * N if np.ndim(J) == 1 else J @ N
     c = np.linalg.solve(N.T @ JN, JN.T @ (xp - x0))
     return xp - N @ c
