@@ -111,6 +111,33 @@ const char *naj_version(void);
 naj_status naj_create_system(int64_t n, int64_t nnz, const int32_t *rowptr, const int32_t *colidx,
                              const double *vals, const double *D, void *stream, naj_system **out);
 
+/*
+ * Create a system whose J is the block-diagonal matrix of eq. (J-blkdiag)
+ * (Section 3): the rows are cut into blocks of `block` consecutive rows (the
+ * last block keeps the rows that remain) and
+ *     J^{i,i} = Q^{i,i} + sum_{j != i} ||Q^{i,j}||_2 I,
+ * with a zero diagonal entry replaced by 1.  The setup computes every block
+ * norm and the inverse of every block on the device; each iteration then
+ * applies x = y - J^{-1}(Q y - b) block by block.  Same arguments and
+ * ownership as naj_create_system, without D.
+ *   block           : 1, 2, 4 or 8 (1 gives eq. (J-diag) computed block-wise)
+ * The system always uses the sliced layout in caller row order and the
+ * two-iterate momentum form.  It serves naj_solve (float64 and mixed; the
+ * float32 inner solve applies fl32 of the float64 inverse blocks), naj_step
+ * and naj_residual; batches and servers reject it.
+ * Errors: as naj_create_system; NAJ_EINVAL also for another block size or a
+ * block that is not positive definite (Q not positive semidefinite).
+ */
+naj_status naj_create_system_blockj(int64_t n, int64_t nnz, const int32_t *rowptr, const int32_t *colidx,
+                                    const double *vals, int32_t block, void *stream, naj_system **out);
+
+/*
+ * The inverse blocks of a block-J system: device float64 out[n * block],
+ * out[r * block + k] = entry (r - i*block, k) of (J^{i,i})^{-1} for the block
+ * i holding row r.  NAJ_EINVAL for a system with a diagonal J.
+ */
+naj_status naj_block_inverse(naj_system *sys, double *out, void *stream);
+
 /* Release a system and all device memory it owns.  NULL is ignored. */
 void naj_destroy_system(naj_system *sys);
 
@@ -166,7 +193,8 @@ naj_status naj_step(naj_system *sys, const double *p, const double *r, double be
 naj_status naj_residual(naj_system *sys, const double *x, const double *b, double *out, double *rr,
                         void *stream);
 
-/* naj_diagonal: the diagonal J in use (eq. (J-diag) or the caller's D), device float64[n] out. */
+/* naj_diagonal: the diagonal J in use (eq. (J-diag) or the caller's D), device float64[n] out.
+ * NAJ_EINVAL for a block-J system (see naj_block_inverse). */
 naj_status naj_diagonal(naj_system *sys, double *out, void *stream);
 
 /*

@@ -85,6 +85,151 @@ __global__ void k_check_D(const double* D, int64_t n, double* dinv, int* flag) {
   }
 }
 
+// ---------------------------------------------------------------- block-diagonal J, eq. (J-blkdiag)
+
+// Largest eigenvalue of a symmetric NB x NB matrix (overwritten) by the cyclic Jacobi method:
+// sweeps of plane rotations over all index pairs, each rotation chosen to zero one
+// off-diagonal pair, until the off-diagonal part is below 1e-16 of the diagonal (Golub and
+// Van Loan, Matrix Computations, Section 8.5).
+template <int NB>
+__device__ double sym_max_eig(double (&A)[NB][NB]) {
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    double off = 0.0, dg = 0.0;
+    for (int p = 0; p < NB; ++p) {
+      dg = dg + A[p][p] * A[p][p];
+      for (int q = p + 1; q < NB; ++q) off = off + A[p][q] * A[p][q];
+    }
+    if (off <= 1e-32 * dg) break;
+    for (int p = 0; p < NB - 1; ++p)
+      for (int q = p + 1; q < NB; ++q) {
+        const double apq = A[p][q];
+        if (apq == 0.0) continue;
+        const double tau = (A[q][q] - A[p][p]) / (2.0 * apq);
+        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+        const double c = 1.0 / sqrt(1.0 + t * t);
+        const double sn = t * c;
+        for (int k = 0; k < NB; ++k) {   // columns p, q of A G
+          const double akp = A[k][p], akq = A[k][q];
+          A[k][p] = c * akp - sn * akq;
+          A[k][q] = sn * akp + c * akq;
+        }
+        for (int k = 0; k < NB; ++k) {   // rows p, q of G^T (A G)
+          const double apk = A[p][k], aqk = A[q][k];
+          A[p][k] = c * apk - sn * aqk;
+          A[q][k] = sn * apk + c * aqk;
+        }
+      }
+  }
+  double m = A[0][0];
+  for (int p = 1; p < NB; ++p) m = fmax(m, A[p][p]);
+  return m;
+}
+
+// One thread per block of NB consecutive rows (block i holds rows NB i .. NB i + NB - 1 below n):
+// J^{i,i} = Q^{i,i} + sum_{j != i} ||Q^{i,j}||_2 I (eq. (J-blkdiag)), a zero diagonal entry
+// replaced by 1 (as for the diagonal J), identity rows past n; then its inverse by Cholesky,
+// stored in the layout block_apply reads, in float64 and float32.  ||Q^{i,j}||_2 is the square
+// root of the largest eigenvalue of Q^{i,j}^T Q^{i,j} (a sum of outer products of the block's
+// rows restricted to block j), and the coupled blocks j are visited in increasing order.
+// Flag 64: a block is not positive definite (so Q is not positive semidefinite).
+template <int NB>
+__global__ void k_block_jinv(const int32_t* rowptr, const int32_t* colidx, const double* vals, int64_t n,
+                             int64_t nblocks, double* jinv, float* jinv32, int* flag) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= nblocks) return;
+  const int64_t r0 = i * NB;
+  const int ni = (int)(n - r0 < NB ? (n - r0 > 0 ? n - r0 : 0) : NB);
+  double J[NB][NB];
+  for (int p = 0; p < NB; ++p)
+    for (int q = 0; q < NB; ++q) J[p][q] = 0.0;
+  for (int r = 0; r < ni; ++r)
+    for (int e = rowptr[r0 + r]; e < rowptr[r0 + r + 1]; ++e) {
+      const int64_t c = colidx[e];
+      if (c / NB == i) J[r][c - r0] = J[r][c - r0] + vals[e];
+    }
+  double shift = 0.0;
+  int64_t jprev = -1;
+  for (;;) {
+    int64_t jn = INT64_MAX;
+    for (int r = 0; r < ni; ++r)
+      for (int e = rowptr[r0 + r]; e < rowptr[r0 + r + 1]; ++e) {
+        const int64_t j = colidx[e] / NB;
+        if (j != i && j > jprev && j < jn) jn = j;
+      }
+    if (jn == INT64_MAX) break;
+    double A[NB][NB];
+    for (int p = 0; p < NB; ++p)
+      for (int q = 0; q < NB; ++q) A[p][q] = 0.0;
+    for (int r = 0; r < ni; ++r) {
+      double m[NB];
+      for (int q = 0; q < NB; ++q) m[q] = 0.0;
+      for (int e = rowptr[r0 + r]; e < rowptr[r0 + r + 1]; ++e) {
+        const int64_t c = colidx[e];
+        if (c / NB == jn) m[c - jn * NB] = m[c - jn * NB] + vals[e];
+      }
+      for (int p = 0; p < NB; ++p)
+        for (int q = 0; q < NB; ++q) A[p][q] = A[p][q] + m[p] * m[q];
+    }
+    shift = shift + sqrt(sym_max_eig<NB>(A));
+    jprev = jn;
+  }
+  for (int k = 0; k < NB; ++k) {
+    if (k < ni) {
+      J[k][k] = J[k][k] + shift;
+      if (J[k][k] == 0.0) J[k][k] = 1.0;
+    } else {
+      for (int q = 0; q < NB; ++q) J[k][q] = J[q][k] = 0.0;
+      J[k][k] = 1.0;
+    }
+  }
+  bool pd = true;   // Cholesky J = L L^T, L in the lower triangle
+  for (int j = 0; j < NB; ++j) {
+    double d = J[j][j];
+    for (int k = 0; k < j; ++k) d = d - J[j][k] * J[j][k];
+    if (!(d > 0.0)) {
+      pd = false;
+      d = 1.0;
+    }
+    const double l = sqrt(d);
+    J[j][j] = l;
+    for (int r = j + 1; r < NB; ++r) {
+      double v = J[r][j];
+      for (int k = 0; k < j; ++k) v = v - J[r][k] * J[j][k];
+      J[r][j] = v / l;
+    }
+  }
+  if (!pd) atomicOr(flag, 64);
+  const int64_t sl = r0 / kWave;
+  const int lane0 = (int)(r0 % kWave);
+  for (int k = 0; k < NB; ++k) {   // column k of the inverse: L y = e_k, then L^T z = y
+    double z[NB];
+    for (int r = 0; r < NB; ++r) {
+      double v = r == k ? 1.0 : 0.0;
+      for (int q = 0; q < r; ++q) v = v - J[r][q] * z[q];
+      z[r] = v / J[r][r];
+    }
+    for (int r = NB - 1; r >= 0; --r) {
+      double v = z[r];
+      for (int q = r + 1; q < NB; ++q) v = v - J[q][r] * z[q];
+      z[r] = v / J[r][r];
+    }
+    for (int r = 0; r < NB; ++r) {
+      const size_t at = ((size_t)sl * NB + k) * kWave + lane0 + r;
+      jinv[at] = z[r];
+      jinv32[at] = (float)z[r];
+    }
+  }
+}
+
+// out[row * nb + k] = entry k of row `row` of the block inverse (caller layout).
+__global__ void k_block_jinv_out(const double* jinv, int64_t n, int nb, double* out) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= n * nb) return;
+  const int64_t row = t / nb;
+  const int k = (int)(t % nb);
+  out[t] = jinv[((size_t)(row / kWave) * nb + k) * kWave + row % kWave];
+}
+
 // Width of each 64-row slice (rows row0 + 64 s + lane) = its longest row.
 __global__ void k_slice_width(const int32_t* rowptr, int64_t row0, int64_t n, int64_t nslices, int32_t* width) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -197,7 +342,7 @@ __global__ void k_row_abs_sum(Sell A, const double* dinv, double* out) {
 constexpr int kAux = 256;   // block size of the stand-alone one-pass kernels
 
 // One fused pass (stand-alone form of the solve kernel's iteration pass).
-template <bool USER_D>
+template <int JM>
 __global__ void __launch_bounds__(kAux) k_step64(SolveArgs a, const double* P, const double* R, double beta,
                                                  int bz, double* W) {
   __shared__ double sh[3][kAux / kWave];
@@ -209,7 +354,7 @@ __global__ void __launch_bounds__(kAux) k_step64(SolveArgs a, const double* P, c
   m.beta_next = 0.0;
   m.bz = bz != 0;
   m.ym = false;
-  pass_iter64<USER_D, kAux, false>(a, P, m, W, p0, p1, p2);
+  pass_iter64<JM, kAux, false>(a, P, m, W, p0, p1, p2);
   block_sum3<kAux>(p0, p1, p2, sh);
   if (threadIdx.x == 0) {
     double* slot = a.part + (size_t)blockIdx.x * kPartStride;
@@ -348,6 +493,9 @@ struct naj_system {
   double* val = nullptr;
   float* val32 = nullptr;
   double* dinv = nullptr;          // caller's D as 1/D (solver row order), or null
+  int jblock = 0;                  // > 0: block-diagonal J with blocks of jblock rows (regular layout)
+  double* jinv = nullptr;          // its inverse blocks, [nslices * jblock * 64] (see block_apply)
+  float* jinv32 = nullptr;
   // row order: with the irregular layout rows are renumbered by decreasing length
   int32_t* perm = nullptr;         // solver row i is caller row perm[i]; null = identity
   double* bperm = nullptr;         // b in solver row order (irregular layout only)
@@ -418,7 +566,7 @@ naj_status dev_alloc(naj_system* s, T** p, size_t count) {
 
 void free_system(naj_system* s) {
   if (!s) return;
-  for (void* p : {(void*)s->slice_ptr, (void*)s->col, (void*)s->val, (void*)s->val32, (void*)s->dinv, (void*)s->perm,
+  for (void* p : {(void*)s->slice_ptr, (void*)s->col, (void*)s->val, (void*)s->val32, (void*)s->dinv, (void*)s->jinv, (void*)s->jinv32, (void*)s->perm,
                   (void*)s->dom_bounds, (void*)s->bperm, (void*)s->lrowptr, (void*)s->lcol, (void*)s->lval,
                   (void*)s->lval32, (void*)s->part, (void*)s->ctrl, (void*)s->bar, (void*)s->counters, (void*)s->hist,
                   (void*)s->trace, (void*)s->scal})
@@ -443,20 +591,30 @@ int blocks_for(int64_t work, int per_block) {
 constexpr int kModePass = 0, kModeSmall = 1, kModePersistent = 2;
 constexpr int kSmallBlock = 1024;
 
+// J of a system: its stored block inverse, the caller's D, or the row sums.
+int jm_of(const naj_system* s) { return s->jblock > 0 ? kJBlock : (s->dinv ? kJUser : kJRowSum); }
+
 template <bool YM>
-const void* pass_kernel_ym(bool user_d, int bs) {
-  if (bs == 1024) return user_d ? (const void*)k_pass64<true, 1024, YM> : (const void*)k_pass64<false, 1024, YM>;
-  if (bs == 512) return user_d ? (const void*)k_pass64<true, 512, YM> : (const void*)k_pass64<false, 512, YM>;
-  return user_d ? (const void*)k_pass64<true, 256, YM> : (const void*)k_pass64<false, 256, YM>;
+const void* pass_kernel_ym(int jm, int bs) {
+  if (bs == 1024) return jm ? (const void*)k_pass64<kJUser, 1024, YM> : (const void*)k_pass64<kJRowSum, 1024, YM>;
+  if (bs == 512) return jm ? (const void*)k_pass64<kJUser, 512, YM> : (const void*)k_pass64<kJRowSum, 512, YM>;
+  return jm ? (const void*)k_pass64<kJUser, 256, YM> : (const void*)k_pass64<kJRowSum, 256, YM>;
 }
 
-const void* pass_kernel(bool user_d, int bs, bool ym) {
-  return ym ? pass_kernel_ym<true>(user_d, bs) : pass_kernel_ym<false>(user_d, bs);
+// A block-J system always uses the regular layout in the two-iterate form.
+const void* pass_kernel(int jm, int bs, bool ym) {
+  if (jm == kJBlock) {
+    if (bs == 1024) return (const void*)k_pass64<kJBlock, 1024, false>;
+    if (bs == 512) return (const void*)k_pass64<kJBlock, 512, false>;
+    return (const void*)k_pass64<kJBlock, 256, false>;
+  }
+  return ym ? pass_kernel_ym<true>(jm, bs) : pass_kernel_ym<false>(jm, bs);
 }
 
-const void* solve_kernel(bool user_d, bool ym) {
-  if (ym) return user_d ? (const void*)k_solve64<true, kSmallBlock, true> : (const void*)k_solve64<false, kSmallBlock, true>;
-  return user_d ? (const void*)k_solve64<true, kSmallBlock, false> : (const void*)k_solve64<false, kSmallBlock, false>;
+const void* solve_kernel(int jm, bool ym) {
+  if (jm == kJBlock) return (const void*)k_solve64<kJBlock, kSmallBlock, false>;
+  if (ym) return jm ? (const void*)k_solve64<kJUser, kSmallBlock, true> : (const void*)k_solve64<kJRowSum, kSmallBlock, true>;
+  return jm ? (const void*)k_solve64<kJUser, kSmallBlock, false> : (const void*)k_solve64<kJRowSum, kSmallBlock, false>;
 }
 
 naj_status choose_grid(naj_system* s, hipStream_t st) {
@@ -489,10 +647,9 @@ naj_status choose_grid(naj_system* s, hipStream_t st) {
     int coop = 0;
     HIP_TRY(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, s->device));
     if (!coop) return fail(NAJ_EDEVICE, "device %d does not support cooperative launches", s->device);
-    int occ1 = 0, occ2 = 0;
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ1, solve_kernel(false, s->ymode != 0), kSmallBlock, 0));
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ2, solve_kernel(true, s->ymode != 0), kSmallBlock, 0));
-    int resident = std::min(occ1, occ2) * s->cus;
+    int occ = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, solve_kernel(jm_of(s), s->ymode != 0), kSmallBlock, 0));
+    int resident = occ * s->cus;
     resident -= resident % nxcd;
     if (resident < nxcd) return fail(NAJ_EDEVICE, "persistent solve kernel cannot be resident");
     const int wpb1 = kSmallBlock / kWave;
@@ -586,6 +743,9 @@ SolveArgs make_args(naj_system* s, const double* b, const naj_opts& o) {
   SolveArgs a;
   a.A = sell_of(s);
   a.dinv = s->dinv;
+  a.jinv = s->jinv;
+  a.jinv32 = s->jinv32;
+  a.jblock = s->jblock;
   a.b = b;
   a.buf0 = s->vec[0];
   a.buf1 = s->vec[1];
@@ -659,6 +819,7 @@ naj_status build_layout(naj_system* s, const int32_t* rowptr, const int32_t* col
   int layout = plain_stored > (int64_t)(1.3 * (double)std::max<int64_t>(s->nnz, n)) ? 1 : 0;
   const int forced = env_int("NAJ_LAYOUT", -1);
   if (forced == 0 || forced == 1) layout = forced;
+  if (s->jblock) layout = 0;   // a block J's rows must stay consecutive
   s->layout = layout;
 
   const int32_t* src_rp = rowptr;
@@ -777,7 +938,7 @@ naj_status build_layout(naj_system* s, const int32_t* rowptr, const int32_t* col
 
 // Runs the solve kernels on `st` for the prepared control block; ev0/ev1 bracket them.
 naj_status run_solve(naj_system* s, SolveArgs& a, const naj_opts& o, hipStream_t st) {
-  const bool ud = s->dinv != nullptr;
+  const int ud = jm_of(s);
   void* kargs[] = {&a};
   if (s->mode == kModeSmall) {
     HIP_TRY(hipEventRecord(s->ev0, st));
@@ -1060,7 +1221,7 @@ const char* naj_version(void) { return "naj 0.1 gfx950"; }
 // matrix only (its right-hand sides are solved by a batch or a server).
 static naj_status create_system_impl(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* colidx,
                                      const double* vals, const double* D, void* stream, Pool* pool, bool lean,
-                                     naj_system** out) {
+                                     naj_system** out, int jblock = 0) {
   g_err.clear();
   (void)hipGetLastError();   // drop a stale error left by unrelated earlier runtime calls
   if (!out) return fail(NAJ_EINVAL, "out is NULL");
@@ -1069,9 +1230,13 @@ static naj_status create_system_impl(int64_t n, int64_t nnz, const int32_t* rowp
   if (nnz < 0 || nnz >= (1LL << 31)) return fail(NAJ_EINVAL, "nnz must be in [0, 2^31) (got %lld)", (long long)nnz);
   if (!rowptr || (nnz > 0 && (!colidx || !vals))) return fail(NAJ_EINVAL, "null CSR pointer");
   hipStream_t st = (hipStream_t)stream;
+  if (jblock != 0 && jblock != 1 && jblock != 2 && jblock != 4 && jblock != 8)
+    return fail(NAJ_EINVAL, "block must be 1, 2, 4 or 8 (got %d)", jblock);
+  if (jblock && D) return fail(NAJ_EINVAL, "a block J and a caller diagonal D exclude each other");
   naj_system* s = new naj_system();
   s->pool = pool;
   s->lean = lean;
+  s->jblock = jblock;
   naj_status rc = NAJ_OK;
   int* flag = nullptr;
   int hflag = 0;
@@ -1121,6 +1286,24 @@ static naj_status create_system_impl(int64_t n, int64_t nnz, const int32_t* rowp
   }
   STEP(build_layout(s, rowptr, colidx, vals, st));
   s->ymode = env_int("NAJ_YMODE", s->layout == 1 ? 1 : 0) ? 1 : 0;
+  if (jblock) {   // eq. (J-blkdiag): inverse blocks from the caller's CSR
+    s->ymode = 0;
+    const int64_t nblk = s->nslices * kWave / jblock;
+    STEP(dev_alloc(s, &s->jinv, (size_t)(s->nslices * kWave * jblock)));
+    STEP(dev_alloc(s, &s->jinv32, (size_t)(s->nslices * kWave * jblock)));
+    const dim3 g(blocks_for(nblk, 64)), b(64);
+    if (jblock == 1) hipLaunchKernelGGL(k_block_jinv<1>, g, b, 0, st, rowptr, colidx, vals, n, nblk, s->jinv, s->jinv32, flag);
+    if (jblock == 2) hipLaunchKernelGGL(k_block_jinv<2>, g, b, 0, st, rowptr, colidx, vals, n, nblk, s->jinv, s->jinv32, flag);
+    if (jblock == 4) hipLaunchKernelGGL(k_block_jinv<4>, g, b, 0, st, rowptr, colidx, vals, n, nblk, s->jinv, s->jinv32, flag);
+    if (jblock == 8) hipLaunchKernelGGL(k_block_jinv<8>, g, b, 0, st, rowptr, colidx, vals, n, nblk, s->jinv, s->jinv32, flag);
+    HSTEP(hipGetLastError());
+    HSTEP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    HSTEP(hipStreamSynchronize(st));
+    if (hflag) {
+      rc = fail(NAJ_EINVAL, "a diagonal block of the block J is not positive definite (Q is not PSD)");
+      goto bad;
+    }
+  }
   STEP(choose_grid(s, st));
   if (!lean) {   // workspace of the single-solve drivers
     for (int i = 0; i < 3 + s->ymode; ++i) STEP(dev_alloc(s, &s->vec[i], (size_t)n));
@@ -1151,6 +1334,27 @@ bad:
 naj_status naj_create_system(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* colidx, const double* vals,
                              const double* D, void* stream, naj_system** out) {
   return create_system_impl(n, nnz, rowptr, colidx, vals, D, stream, nullptr, false, out);
+}
+
+naj_status naj_create_system_blockj(int64_t n, int64_t nnz, const int32_t* rowptr, const int32_t* colidx,
+                                    const double* vals, int32_t block, void* stream, naj_system** out) {
+  if (block < 1) {
+    g_err.clear();
+    return fail(NAJ_EINVAL, "block must be 1, 2, 4 or 8 (got %d)", block);
+  }
+  return create_system_impl(n, nnz, rowptr, colidx, vals, nullptr, stream, nullptr, false, out, block);
+}
+
+naj_status naj_block_inverse(naj_system* s, double* out, void* stream) {
+  g_err.clear();
+  (void)hipGetLastError();
+  if (!s || !out) return fail(NAJ_EINVAL, "null argument");
+  if (s->jblock == 0) return fail(NAJ_EINVAL, "the system uses a diagonal J (no block inverse)");
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t cnt = s->n * s->jblock;
+  hipLaunchKernelGGL(k_block_jinv_out, dim3(blocks_for(cnt, kAux)), dim3(kAux), 0, st, s->jinv, s->n, s->jblock, out);
+  HIP_TRY(hipGetLastError());
+  return NAJ_OK;
 }
 
 void naj_destroy_system(naj_system* s) {
@@ -1290,10 +1494,12 @@ naj_status naj_step(naj_system* s, const double* p, const double* r, double beta
     W = s->vec[2];
     a.b = s->bperm;
   }
-  if (s->dinv)
-    hipLaunchKernelGGL(k_step64<true>, dim3(G), dim3(kAux), 0, st, a, P, R, beta, bz, W);
+  if (s->jblock > 0)
+    hipLaunchKernelGGL(k_step64<kJBlock>, dim3(G), dim3(kAux), 0, st, a, P, R, beta, bz, W);
+  else if (s->dinv)
+    hipLaunchKernelGGL(k_step64<kJUser>, dim3(G), dim3(kAux), 0, st, a, P, R, beta, bz, W);
   else
-    hipLaunchKernelGGL(k_step64<false>, dim3(G), dim3(kAux), 0, st, a, P, R, beta, bz, W);
+    hipLaunchKernelGGL(k_step64<kJRowSum>, dim3(G), dim3(kAux), 0, st, a, P, R, beta, bz, W);
   HIP_TRY(hipGetLastError());
   if (s->perm) {
     hipLaunchKernelGGL(k_scatter, dim3(blocks_for(s->n, kAux * 4)), dim3(kAux), 0, st, W, s->perm, x, s->n);
@@ -1328,6 +1534,7 @@ naj_status naj_residual(naj_system* s, const double* x, const double* b, double*
 naj_status naj_diagonal(naj_system* s, double* out, void* stream) {
   g_err.clear();
   if (!s || !out) return fail(NAJ_EINVAL, "null argument");
+  if (s->jblock) return fail(NAJ_EINVAL, "the system uses a block J (read it with naj_block_inverse)");
   hipStream_t st = (hipStream_t)stream;
   double* dst = s->perm ? s->vec[0] : out;
   hipLaunchKernelGGL(k_row_abs_sum, dim3(blocks_for(std::max<int64_t>(s->n, s->nslices * kWave), kAux)), dim3(kAux), 0,
@@ -1362,6 +1569,7 @@ naj_status naj_batch_create(int32_t nsys, naj_system* const* systems, const int3
     if (!systems[i]) return fail(NAJ_EINVAL, "system %d is NULL", i);
     if (nrhs[i] < 1 || nrhs[i] > kMaxRhs) return fail(NAJ_EINVAL, "nrhs[%d] = %d outside [1, %d]", i, nrhs[i], kMaxRhs);
     if (systems[i]->device != dev) return fail(NAJ_EINVAL, "system %d lives on another device", i);
+    if (systems[i]->jblock) return fail(NAJ_EINVAL, "system %d uses a block J (single solves only)", i);
   }
   naj_batch* bt = new naj_batch();
   bt->device = dev;

@@ -117,9 +117,20 @@ struct Sell {
   const float* lval32;
 };
 
+// Which J a pass applies (template parameter JM of the pass functions):
+//  0  J of eq. (J-diag), recomputed from the row's values as its absolute sum;
+//  1  the caller's diagonal D (stored as 1/D);
+//  2  the block-diagonal J of eq. (J-blkdiag) with blocks of `jblock` consecutive rows
+//     (regular layout only), applied through its stored inverse blocks.
+constexpr int kJRowSum = 0, kJUser = 1, kJBlock = 2;
+constexpr int kMaxJBlock = 8;
+
 struct SolveArgs {
   Sell A;
   const double* dinv;         // non-null: caller's diagonal (as 1/D); null: J from the row
+  const double* jinv;         // block J: inverse blocks, row r of a block holding row r of its inverse
+  const float* jinv32;        // the same in float32 (inner solves)
+  int jblock;                 // block J: rows per block (1, 2, 4 or 8; divides 64)
   const double* b;
   double* buf0;
   double* buf1;
@@ -187,6 +198,30 @@ __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane
 
 using WaveRange = SliceRange;
 
+// z = J^{-1} g on the rows of one slice for the block-diagonal J.  A block's nb rows are nb
+// consecutive lanes (nb divides 64 and slices start at multiples of 64), so the lane of row r
+// reads the block's g values from its neighbours and adds J^{-1}_{r,k} g_k for k = 0, 1, ...
+// in that order.  Entry k of the lane's row of the inverse is at jinv[(s * nb + k) * 64 + lane]
+// (one coalesced 64-lane load per k).  Every lane of the wavefront must call this (shuffles);
+// lanes past the last row pass g = 0.
+template <typename T>
+__device__ __forceinline__ T block_apply(const T* __restrict__ jinv, int64_t s, int lane, int nb, T g) {
+  const T* __restrict__ jp = jinv + (size_t)s * nb * kWave + lane;
+  T jk[kMaxJBlock];
+#pragma unroll
+  for (int k = 0; k < kMaxJBlock; ++k)
+    if (k < nb) jk[k] = jp[k * kWave];
+  const int first = lane & ~(nb - 1);
+  T z = T(0);
+#pragma unroll
+  for (int k = 0; k < kMaxJBlock; ++k)
+    if (k < nb) {
+      const T gk = __shfl(g, first + k, kWave);
+      z = (k == 0) ? jk[k] * gk : z + jk[k] * gk;
+    }
+  return z;
+}
+
 template <int BS>
 __device__ __forceinline__ WaveRange wave_range(const Sell& A, int nxcd) {
   return slice_range(A.nslices, nxcd, (int)gridDim.x, (int)blockIdx.x, wave_id(), BS / kWave, A.dom_bounds);
@@ -194,7 +229,7 @@ __device__ __forceinline__ WaveRange wave_range(const Sell& A, int nxcd) {
 
 // One slice of the fused pass: u = Q y, g = u - b, x = y - J^{-1} g, d = x - P,
 // with y = P + beta (P - R) formed at every gathered column (y = P when bz).
-template <bool USER_D, bool YM>
+template <int JM, bool YM>
 __device__ __forceinline__ void iter_slice(const SolveArgs& a, int64_t s, int lane, const double* __restrict__ P,
                                            const Momentum<double>& m, double* __restrict__ W, double& ps, double& pgg,
                                            double& psabs) {
@@ -211,7 +246,7 @@ __device__ __forceinline__ void iter_slice(const SolveArgs& a, int64_t s, int la
   const double Pi = P[rr];
   const double Ri = bz ? 0.0 : R[rr];
   const double bi = a.b[rr];
-  const double di = USER_D ? a.dinv[rr] : 0.0;
+  const double di = (JM == 1) ? a.dinv[rr] : 0.0;
   const int32_t* __restrict__ cp = a.A.col + base + lane;
   const double* __restrict__ vp = a.A.val + base + lane;
   double acc = 0.0, asum = 0.0;
@@ -252,11 +287,13 @@ __device__ __forceinline__ void iter_slice(const SolveArgs& a, int64_t s, int la
         asum = asum + fabs(v[j]);
       }
   }
+  double z = 0.0;
+  if constexpr (JM == kJBlock) z = block_apply(a.jinv, s, lane, a.jblock, live ? acc - bi : 0.0);
   if (live) {
     const double yi = bz ? Pi : (ym ? Ri : Pi + beta * (Pi - Ri));
     const double g = acc - bi;
-    const double dv = USER_D ? di : 1.0 / (asum == 0.0 ? 1.0 : asum);
-    const double xi = yi - dv * g;
+    const double dv = (JM == 1) ? di : 1.0 / (asum == 0.0 ? 1.0 : asum);
+    const double xi = (JM == kJBlock) ? yi - z : yi - dv * g;
     W[row] = xi;
     const double d = xi - Pi;
     if (YM && m.Yn) m.Yn[row] = xi + m.beta_next * d;
@@ -305,7 +342,7 @@ __device__ __forceinline__ void resid_slice(const Sell& A, int64_t s, int lane, 
 // iter_slice on Q d = r32 with float32 values, vectors and row sums; the
 // restart inner product and the monitor are accumulated in float64 from
 // exactly converted float32 operands.  zp: the previous iterate is zero.
-template <bool USER_D, bool YM>
+template <int JM, bool YM>
 __device__ __forceinline__ void inner_slice(const SolveArgs& a, int64_t s, int lane, const float* __restrict__ P,
                                             const Momentum<float>& m, float* __restrict__ W, bool zp, double& ps,
                                             double& pgg, double& psabs) {
@@ -321,7 +358,7 @@ __device__ __forceinline__ void inner_slice(const SolveArgs& a, int64_t s, int l
   const float Pi = zp ? 0.0f : P[rr];
   const float Ri = (zp || bz) ? 0.0f : R[rr];
   const float bi = a.r32[rr];
-  const double di = USER_D ? a.dinv[rr] : 0.0;
+  const double di = (JM == 1) ? a.dinv[rr] : 0.0;
   const int32_t* __restrict__ cp = a.A.col + base + lane;
   const float* __restrict__ vp = a.A.val32 + base + lane;
   float acc = 0.0f, asum = 0.0f;
@@ -364,11 +401,13 @@ __device__ __forceinline__ void inner_slice(const SolveArgs& a, int64_t s, int l
         asum = asum + fabsf(v[j]);
       }
   }
+  float z = 0.0f;
+  if constexpr (JM == kJBlock) z = block_apply(a.jinv32, s, lane, a.jblock, live ? acc - bi : 0.0f);
   if (live) {
     const float yi = (zp || bz) ? Pi : (ym ? Ri : Pi + beta * (Pi - Ri));
     const float g = acc - bi;
-    const float dv = USER_D ? (float)di : 1.0f / (asum == 0.0f ? 1.0f : asum);
-    const float xi = yi - dv * g;
+    const float dv = (JM == 1) ? (float)di : 1.0f / (asum == 0.0f ? 1.0f : asum);
+    const float xi = (JM == kJBlock) ? yi - z : yi - dv * g;
     W[row] = xi;
     const float d = xi - Pi;
     if (YM && m.Yn) m.Yn[row] = xi + m.beta_next * d;
@@ -477,7 +516,7 @@ __device__ __forceinline__ void long_row_sums(const int32_t* __restrict__ col, c
   }
 }
 
-template <bool USER_D, bool YM>
+template <int JM, bool YM>
 __device__ __forceinline__ void iter_long(const SolveArgs& a, int64_t r, int lane, const double* __restrict__ P,
                                           const Momentum<double>& m, double* __restrict__ W, double& ps, double& pgg,
                                           double& psabs) {
@@ -500,7 +539,7 @@ __device__ __forceinline__ void iter_long(const SolveArgs& a, int64_t r, int lan
     const double Pi = P[r];
     const double yi = bz ? Pi : (ym ? R[r] : Pi + beta * (Pi - R[r]));
     const double g = acc - a.b[r];
-    const double dv = USER_D ? a.dinv[r] : 1.0 / (asum == 0.0 ? 1.0 : asum);
+    const double dv = (JM == 1) ? a.dinv[r] : 1.0 / (asum == 0.0 ? 1.0 : asum);
     const double xi = yi - dv * g;
     W[r] = xi;
     const double dd = xi - Pi;
@@ -524,7 +563,7 @@ __device__ __forceinline__ void resid_long(const Sell& A, int64_t r, int lane, c
   }
 }
 
-template <bool USER_D, bool YM>
+template <int JM, bool YM>
 __device__ __forceinline__ void inner_long(const SolveArgs& a, int64_t r, int lane, const float* __restrict__ P,
                                            const Momentum<float>& m, float* __restrict__ W, bool zp, double& ps,
                                            double& pgg, double& psabs) {
@@ -549,7 +588,7 @@ __device__ __forceinline__ void inner_long(const SolveArgs& a, int64_t r, int la
     const float Pi = zp ? 0.0f : P[r];
     const float yi = (zp || bz) ? Pi : (ym ? R[r] : Pi + beta * (Pi - R[r]));
     const float g = acc - a.r32[r];
-    const float dv = USER_D ? (float)a.dinv[r] : 1.0f / (asum == 0.0f ? 1.0f : asum);
+    const float dv = (JM == 1) ? (float)a.dinv[r] : 1.0f / (asum == 0.0f ? 1.0f : asum);
     const float xi = yi - dv * g;
     W[r] = xi;
     const float dd = xi - Pi;

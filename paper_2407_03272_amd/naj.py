@@ -59,6 +59,8 @@ _SIGS = {
     "naj_last_error": (ctypes.c_char_p, []),
     "naj_version": (ctypes.c_char_p, []),
     "naj_create_system": (ctypes.c_int, [_I64, _I64, _P, _P, _P, _P, _P, ctypes.POINTER(_P)]),
+    "naj_create_system_blockj": (ctypes.c_int, [_I64, _I64, _P, _P, _P, _I32, _P, ctypes.POINTER(_P)]),
+    "naj_block_inverse": (ctypes.c_int, [_P, _P, _P]),
     "naj_destroy_system": (None, [_P]),
     "naj_system_info": (ctypes.c_int, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I64),
                                        ctypes.POINTER(_I32), ctypes.POINTER(_I64)]),
@@ -159,11 +161,12 @@ class System:
     """A system Q x = b resident on the GPU (naj_create_system).
 
     rowptr, colidx: int32 CSR arrays; vals: float64; D: optional float64
-    diagonal replacing J.  Accepts numpy arrays or torch tensors; host arrays
-    are copied to ``device``.
+    diagonal replacing J; jblock: block size of the block-diagonal J of
+    eq. (J-blkdiag) (naj_create_system_blockj) instead of the diagonal J.
+    Accepts numpy arrays or torch tensors; host arrays are copied to ``device``.
     """
 
-    def __init__(self, rowptr, colidx, vals, D=None, device="cuda:0", stream=None):
+    def __init__(self, rowptr, colidx, vals, D=None, device="cuda:0", stream=None, jblock=None):
         torch = _torch()
         lib = load()
         self.device = torch.device(device)
@@ -174,9 +177,16 @@ class System:
         self.n = int(self._rowptr.numel() - 1)
         self.nnz = int(self._colidx.numel())
         h = ctypes.c_void_p()
+        self.jblock = jblock
         with torch.cuda.device(self.device):
-            st = lib.naj_create_system(self.n, self.nnz, _ptr(self._rowptr), _ptr(self._colidx), _ptr(self._vals),
-                                       _ptr(self._D), _stream_ptr(stream), ctypes.byref(h))
+            if jblock is not None:
+                if D is not None:
+                    raise ValueError("a block J and a caller diagonal D exclude each other")
+                st = lib.naj_create_system_blockj(self.n, self.nnz, _ptr(self._rowptr), _ptr(self._colidx),
+                                                  _ptr(self._vals), int(jblock), _stream_ptr(stream), ctypes.byref(h))
+            else:
+                st = lib.naj_create_system(self.n, self.nnz, _ptr(self._rowptr), _ptr(self._colidx), _ptr(self._vals),
+                                           _ptr(self._D), _stream_ptr(stream), ctypes.byref(h))
         _check(st)
         self._h = h
         # inputs are copied by the library; drop our references
@@ -267,6 +277,16 @@ class System:
         with torch.cuda.device(self.device):
             _check(load().naj_diagonal(self._h, _ptr(out), _stream_ptr(stream)))
         return out
+
+
+    def block_inverse(self, stream=None):
+        """The inverse blocks of a block-J system as an (n, jblock) float64 tensor: row r holds row
+        r - i*jblock of (J^{i,i})^{-1} for the block i that contains r."""
+        torch = _torch()
+        out = torch.empty(self.n * int(self.jblock or 1), dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            _check(load().naj_block_inverse(self._h, _ptr(out), _stream_ptr(stream)))
+        return out.view(self.n, -1)
 
 
 class Batch:
