@@ -54,10 +54,11 @@ def measured_traffic(workload: str):
     return rec["traffic_bytes_per_pass"]
 
 
-def bytes_per_iteration(n: int, nnz: int, s_v: int = 8, s_x: int = 8, k: int = 1) -> int:
+def bytes_per_iteration(n: int, nnz: int, s_v: int = 8, s_x: int = 8, k: int = 1, jb: int = 0) -> int:
     """Algorithmic bytes of one fused pass: CSR values + int32 columns, int32 row pointers, and four vector
-    streams (read x^{t-1}, read y^t / x^{t-2}, read b, write x^t)."""
-    return (s_v + 4) * nnz + 4 * (n + 1) + 4 * k * s_x * n
+    streams (read x^{t-1}, read y^t / x^{t-2}, read b, write x^t); with a block J of jb-row blocks, each row
+    also reads its row of the block's inverse (jb values)."""
+    return (s_v + 4) * nnz + 4 * (n + 1) + 4 * k * s_x * n + jb * s_x * n
 
 
 def bytes_per_residual(n: int, nnz: int) -> int:
@@ -71,13 +72,13 @@ def bytes_per_refinement_residual(n: int, nnz: int) -> int:
     return 12 * nnz + 4 * (n + 1) + 8 * n + 4 * n + 8 * n + 8 * n + 4 * n
 
 
-def solve_bytes(n: int, nnz: int, info, mixed: bool) -> int:
+def solve_bytes(n: int, nnz: int, info, mixed: bool, jb: int = 0) -> int:
     """Algorithmic bytes of a whole solve from its pass counts (norm of b = 8n bytes)."""
     if not mixed:
         it = info.iterations
         conf = info.passes - it - 1
-        return 8 * n + it * bytes_per_iteration(n, nnz) + conf * bytes_per_residual(n, nnz)
-    return (8 * n + info.iterations * bytes_per_iteration(n, nnz, s_v=4, s_x=4)
+        return 8 * n + it * bytes_per_iteration(n, nnz, jb=jb) + conf * bytes_per_residual(n, nnz)
+    return (8 * n + info.iterations * bytes_per_iteration(n, nnz, s_v=4, s_x=4, jb=jb)
             + info.confirmations * bytes_per_refinement_residual(n, nnz))
 
 
@@ -94,7 +95,7 @@ def make_workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(sysobj, iterations_needed: int, sample_iters: int) -> dict:
+def cpu_baseline(sysobj, iterations_needed: int, sample_iters: int, jblock=None) -> dict:
     """Time the CPU oracle (as it is) on a bounded sample of the same solve and scale to solves/s."""
     from threadpoolctl import threadpool_limits
 
@@ -102,7 +103,7 @@ def cpu_baseline(sysobj, iterations_needed: int, sample_iters: int) -> dict:
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
         r = O.accelerated_jacobi(sysobj.rowptr, sysobj.colidx, sysobj.vals, sysobj.b, tol=1e-8,
-                                 max_iter=sample_iters)
+                                 max_iter=sample_iters, jblock=jblock)
         dt = time.perf_counter() - t0
     per_iter = dt / max(1, len(r.hist))
     solve_s = per_iter * iterations_needed
@@ -408,6 +409,8 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip the second-precision comparison solves")
     ap.add_argument("--nsys", type=int, default=512, help="systems in the fe_batch workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--jblock", type=int, default=0,
+                    help="single-solve workloads: block-diagonal J of eq. (J-blkdiag) with blocks of this many rows")
     ap.add_argument("--serve-requests", type=int, default=2200, help="requests in the serve workload trace")
     ap.add_argument("--serve-budget-mb", type=int, default=8192, help="serve workload memory budget")
     ap.add_argument("--serve-small-budget-mb", type=int, default=512, help="second serve run with this budget (0: none)")
@@ -450,7 +453,8 @@ def main():
         _, info = sysm.solve(b, hist_cap=0, tol=1e-30, max_iter=50)
         print(json.dumps({"pmc_sample": True, "copy_bytes_each_way": src.numel() * 8, "passes": info.passes}))
         return
-    sysm = naj.System(sysobj.rowptr, sysobj.colidx, sysobj.vals, device="cuda:0")
+    jb = args.jblock
+    sysm = naj.System(sysobj.rowptr, sysobj.colidx, sysobj.vals, device="cuda:0", jblock=jb or None)
     b = torch.as_tensor(sysobj.b).to(dev)
     x = torch.empty(n, dtype=torch.float64, device=dev)
     mixed = args.precision == "mixed"
@@ -478,18 +482,20 @@ def main():
     total, lat, kms, infos = timed(mixed, args.steps, args.warmup)
     progress(f"timed {args.steps} solves: {total / args.steps * 1e3:.2f} ms each")
     info = infos[-1]
-    alg_bytes = solve_bytes(n, nnz, info, mixed)
+    alg_bytes = solve_bytes(n, nnz, info, mixed, jb)
     kernel_s = float(np.mean(kms)) / 1e3
     achieved = alg_bytes / kernel_s / 1e9
     solves_s = args.steps / total
     if mixed:
-        per_launch = bytes_per_iteration(n, nnz, s_v=4, s_x=4)
+        per_launch = bytes_per_iteration(n, nnz, s_v=4, s_x=4, jb=jb)
         wl = (f"{sysobj.name}: n={n}, nnz={nnz}; float32 inner accelerated Jacobi with float64 reductions inside "
               f"float64 iterative refinement, x0=0, restart on, K0=2, inner tol 1e-4, final relres <= 1e-8, single solve")
     else:
-        per_launch = bytes_per_iteration(n, nnz)
+        per_launch = bytes_per_iteration(n, nnz, jb=jb)
         wl = (f"{sysobj.name}: n={n}, nnz={nnz}, float64, x0=0, restart on, K0=2, tol 1e-8, single solve "
               f"(plain FP64 one system at a time)")
+    if jb:
+        wl += f"; block-diagonal J of eq. (J-blkdiag), blocks of {jb} rows"
     line = {
         "metric": "solves/s + HBM GB/s at relres 1e-8 vs plain FP64; p50/p99 solve latency",
         "value": solves_s,
@@ -506,14 +512,14 @@ def main():
         "config": {"workload": wl, "n": n, "nnz": nnz, "precision": args.precision, "tol": 1e-8,
                    "iterations": info.iterations, "restarts": info.restarts, "confirmations": info.confirmations,
                    "passes": info.passes, "grid": info.grid, "relres": info.relres,
-                   "layout": sysm.info()["layout"]},
+                   "layout": sysm.info()["layout"], "jblock": jb},
         "p50_ms": float(np.percentile(lat, 50) * 1e3),
         "p99_ms": float(np.percentile(lat, 99) * 1e3),
         "kernel_ms": float(np.mean(kms)),
         "gbps_solve": achieved,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None if mixed else measured_traffic(args.workload),
+                     "traffic": None if (mixed or jb) else measured_traffic(args.workload),
                      "kernel": "k_pass64 (fused iteration pass, one launch per pass)",
                      "launches_per_solve": info.passes,
                      "algorithmic_bytes_per_launch": per_launch,
@@ -527,12 +533,12 @@ def main():
                            "p50_ms": float(np.percentile(clat, 50) * 1e3),
                            "p99_ms": float(np.percentile(clat, 99) * 1e3),
                            "iterations": ci.iterations, "confirmations": ci.confirmations, "relres": ci.relres,
-                           "gbps_solve": solve_bytes(n, nnz, ci, not mixed) / (float(np.mean(ckms)) / 1e3) / 1e9}
+                           "gbps_solve": solve_bytes(n, nnz, ci, not mixed, jb) / (float(np.mean(ckms)) / 1e3) / 1e9}
     it = info.iterations
     if not args.no_cpu_baseline:
         progress("cpu baseline")
         its_fp64 = info.iterations if not mixed else line.get("compare", {}).get("iterations", info.iterations)
-        line["cpu_baseline"] = cpu_baseline(sysobj, its_fp64, args.cpu_sample_iters)
+        line["cpu_baseline"] = cpu_baseline(sysobj, its_fp64, args.cpu_sample_iters, jb or None)
     sysm.close()
     print(json.dumps(line), flush=True)
 

@@ -1045,40 +1045,44 @@ inline const void* batch_pass_kernel(bool mixed, int kpmax) {
   return (const void*)k_batch_pass<true, 8>;
 }
 
-// After a pass: for every system with an unfinished instance (one workgroup each), the
-// items' partial sums in item order (thread i adds items i, i + 256, ..., then the
-// workgroup adds the threads in a fixed order), the scalar decision, and the view of
-// the next pass.
-constexpr int kDecideBlock = 256;
+// After a pass: for every system with an unfinished instance (one workgroup each, one
+// wavefront per right-hand side, so the instances of a system decide concurrently), the
+// items' partial sums of the instance in item order (lane l adds items l, l + 64, ...,
+// then a fixed butterfly over the lanes), the scalar decision, and the view of the next
+// pass.  The order depends only on the system's item count.
+constexpr int kDecideBlock = kWave * kMaxRhs;
 
 __global__ void __launch_bounds__(kDecideBlock) k_batch_decide(BatchArgs ba) {
-  __shared__ double sh[3][kDecideBlock / kWave];
   const int nsact = uni(*gptr(ba.nsact));
   if ((int)blockIdx.x >= nsact) return;
   const int sys = uni(gptr(ba.sact)[blockIdx.x]);
   const BatchSys S = uniform_sys(ba.sys[sys]);
-  const SolveArgs a = batch_ctrl_args(ba, S);
-  for (int j = 0; j < S.nrhs; ++j) {
-    if (uni(gptr(S.vt)[j].phase) == PH_DONE) continue;
+  const int j = wave_id();
+  const int lane = (int)threadIdx.x % kWave;
+  if (j < S.nrhs && uni(gptr(S.vt)[j].phase) != PH_DONE) {
+    const SolveArgs a = batch_ctrl_args(ba, S);
     const NAJ_GLOBAL double* part = gptr(S.part) + (size_t)j * S.ntiles * kPartStride;
     double r0 = 0.0, r1 = 0.0, r2 = 0.0;
-    for (int i = threadIdx.x; i < S.ntiles; i += kDecideBlock) {
+#pragma unroll 4
+    for (int i = lane; i < S.ntiles; i += kWave) {
       r0 = r0 + part[(size_t)i * kPartStride + 0];
       r1 = r1 + part[(size_t)i * kPartStride + 1];
       r2 = r2 + part[(size_t)i * kPartStride + 2];
     }
-    block_sum3<kDecideBlock>(r0, r1, r2, sh);
-    if (threadIdx.x == 0) {
+    r0 = wave_sum(r0);
+    r1 = wave_sum(r1);
+    r2 = wave_sum(r2);
+    if (lane == 0) {
       Ctrl* c = S.ctrl + j;
       control_update(a, c, r0, r1, r2);
       load_view(c, S.vt + j);
       if (c->phase == PH_DONE) __hip_atomic_fetch_add(ba.done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    __syncthreads();
   }
+  __syncthreads();   // the views written above are visible to the workgroup
   if (ba.slot_done && threadIdx.x == 0) {
     bool all = true;
-    for (int j = 0; j < S.nrhs; ++j) all = all && S.vt[j].phase == PH_DONE;
+    for (int q = 0; q < S.nrhs; ++q) all = all && S.vt[q].phase == PH_DONE;
     if (all) ba.slot_done[sys] = S.gen;
   }
 }
