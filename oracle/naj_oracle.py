@@ -28,13 +28,20 @@ Readings where the paper leaves a choice open (all shared with the GPU path
 by specification, not by code):
 
 * x^0 defaults to 0; K_0 defaults to 2 (the paper only requires K_0 >= 2).
-* Stopping: the paper stops on a relative objective gap with f* known
-  (Section 4); here the stop is on the relative residual
-  ||b - Q x^t|| / ||b|| <= tol.  The residual at y^t, ||Q y^t - b||, comes
-  free with the step and is the monitor; when it is <= tol the residual at
-  x^t is computed (one extra product) and the run stops if that is <= tol.
-  After a failed confirmation the next one waits ``confirm_gap`` iterations.
-  At t = 1, y^1 = x^0, so a monitor <= tol returns x^0 with 0 iterations.
+* Stopping: by default on the relative residual ||b - Q x^t|| / ||b|| <= tol.
+  The residual at y^t, ||Q y^t - b||, comes free with the step and is the
+  monitor; when it is <= tol the residual at x^t is computed (one extra
+  product) and the run stops if that is <= tol.  After a failed
+  confirmation the next one waits ``confirm_gap`` iterations.  At t = 1,
+  y^1 = x^0, so a monitor <= tol returns x^0 with 0 iterations.
+  With ``stop="objective"`` the criterion is the paper's own (Section 4):
+  |f(x^t) - f*| / (1 + |f*|) <= tol with f* given.  The monitor is then the
+  same gap at y^t, f(y^t) = sum_i y_i (u_i / 2 - b_i) with u = Q y^t (free
+  with the step), and the confirmation evaluates f(x^t) with one extra
+  product.  Since x^t minimizes f + ||. - y^t||_S^2 / 2 (Lemma 1),
+  f(x^t) <= f(y^t): a monitor <= tol implies the criterion at x^t in exact
+  arithmetic, and the stop can come a few iterations after the first x^t
+  that meets it.
 * A restart iteration counts as an iteration (its product was spent).
 * The table of update rules in Section 4 writes Q x^t in the accelerated
   Jacobi row; Algorithm 3 writes Q y^t, which is what is done here.
@@ -189,19 +196,24 @@ class OracleResult:
     sabs_log: list = field(default_factory=list)      # sum_i |g_i d_i| (scale of s_t, for near-tie checks)
     confirms: list = field(default_factory=list)      # (t, ||b - Q x^t|| / ||b||)
     relres: float = float("nan")                      # residual of the returned x (when computed)
+    objgap: float = float("nan")                      # objective stop: |f(x) - f*| / (1 + |f*|) of the returned x
 
 
 def accelerated_jacobi(rowptr, colidx, vals, b, x0=None, *, tol: float = 1e-8, max_iter: int = 5000,
                        restart: bool = True, k0: int = 2, D: np.ndarray | None = None,
                        confirm_gap: int = 8, forced_restarts: Iterable[int] | None = None,
-                       callback: Callable | None = None, jblock: int | None = None) -> OracleResult:
+                       callback: Callable | None = None, jblock: int | None = None,
+                       stop: str = "relres", fstar: float | None = None) -> OracleResult:
     """Algorithm 3 (Section 3) with diagonal J, in float64.
 
     ``restart`` is the IsRestart switch of Algorithm 3 (False gives Algorithm 1
     with S = J - Q).  ``D`` replaces J when given (Remark 1 allows any
     invertible J with J - Q PSD).  ``jblock`` selects the block-diagonal J of
     eq. (J-blkdiag) with blocks of that many consecutive rows (Algorithm 3 with
-    its block update).  ``forced_restarts``, when given, replaces
+    its block update).  ``stop="objective"`` with ``fstar`` stops on the
+    relative objective gap of Section 4 (see the module notes); the result's
+    ``relres`` is then still the relative residual of the returned x and
+    ``objgap`` its gap.  ``forced_restarts``, when given, replaces
     the restart test by that exact set of iterations (used to replay a run
     whose restart test was a numerical tie).  ``callback(t, info)`` sees every
     iteration's vectors (used by invariant tests).
@@ -228,7 +240,33 @@ def accelerated_jacobi(rowptr, colidx, vals, b, x0=None, *, tol: float = 1e-8, m
     if nb == 0.0:
         res.x = np.zeros(n)
         res.relres = 0.0
+        res.objgap = 0.0 if stop == "objective" else float("nan")
         return res
+    if stop == "objective":
+        if fstar is None:
+            raise ValueError("the objective stop needs f*")
+        fscale = 1.0 + abs(float(fstar))
+
+        def monitor(y, u, g):
+            # f(y) = <y, Q y>/2 - <b, y> = sum_i y_i (u_i/2 - b_i), eq. (eq-qp)
+            return abs(float(y @ (0.5 * u - b)) - fstar) / fscale
+
+        def check(x):
+            return abs(float(x @ (0.5 * (Q @ x) - b)) - fstar) / fscale
+    elif stop == "relres":
+        def monitor(y, u, g):
+            return float(np.linalg.norm(g)) / nb
+
+        def check(x):
+            return float(np.linalg.norm(b - Q @ x)) / nb
+    else:
+        raise ValueError(f"unknown stop {stop!r}")
+
+    def finish(x):
+        res.x = x
+        if stop == "objective":
+            res.objgap = check(x)
+            res.relres = float(np.linalg.norm(b - Q @ x)) / nb
 
     # Algorithm 3 input: x^0 = y^1, alpha_1 = 1, l = 0, K_0, K_re = 0
     x_prev = x0.copy()
@@ -241,20 +279,22 @@ def accelerated_jacobi(rowptr, colidx, vals, b, x0=None, *, tol: float = 1e-8, m
         u = Q @ y
         g = u - b
         x = y - jinv_apply(g)
-        mon = float(np.linalg.norm(g)) / nb
+        mon = monitor(y, u, g)
         res.hist.append(mon)
         if not math.isfinite(mon):
             res.x, res.iterations, res.status = x_prev, t, STATUS_BREAKDOWN
             return res
         if t == 1 and mon <= tol:
             res.x, res.iterations, res.relres = x0, 0, mon
+            finish(x0)
             return res
         if mon <= tol and t >= last_confirm + confirm_gap:
-            rho = float(np.linalg.norm(b - Q @ x)) / nb
+            rho = check(x)
             last_confirm = t
             res.confirms.append((t, rho))
             if rho <= tol:
                 res.x, res.iterations, res.relres = x, t, rho
+                finish(x)
                 if callback is not None:
                     callback(t, dict(x=x, y=y, x_prev=x_prev, alpha=alpha, restarted=False, final=True))
                 return res
@@ -289,6 +329,7 @@ def accelerated_jacobi(rowptr, colidx, vals, b, x0=None, *, tol: float = 1e-8, m
         alpha = a_next
     res.x, res.iterations, res.status = x_prev, max_iter, STATUS_NOT_CONVERGED
     res.relres = float(np.linalg.norm(b - Q @ x_prev)) / nb
+    finish(x_prev)
     return res
 
 
@@ -450,7 +491,7 @@ def accelerated_jacobi_mixed(rowptr, colidx, vals, b, x0=None, *, tol: float = 1
 # ----------------------------------------------------------------------------
 
 def sdd_scalar_run(n: int, *, tol: float = 1e-8, max_iter: int = 5000, restart: bool = True, k0: int = 2,
-                   confirm_gap: int = 8, digits: int = 60):
+                   confirm_gap: int = 8, digits: int = 60, stop: str = "relres"):
     """Algorithm 3 on the Section 4.1 system in high-precision scalar arithmetic.
 
     Q = (n+1) I - 1 1^T, b = 1, x^0 = 0.  Q 1 = 1, so every iterate is a
@@ -458,9 +499,13 @@ def sdd_scalar_run(n: int, *, tol: float = 1e-8, max_iter: int = 5000, restart: 
     J = (2n - 1) I from eq. (J-diag):  Q y^t - b = (eta_t - 1) 1,
     xi_t = eta_t - (eta_t - 1)/(2n - 1), the restart inner product is
     n (eta_t - 1)(xi_t - xi_{t-1}), ||Q y^t - b||/||b|| = |eta_t - 1| and
-    ||b - Q x^t||/||b|| = |1 - xi_t|.  Same control flow and readings as
-    ``accelerated_jacobi``; arithmetic in ``digits``-digit decimals.
-    Returns dict(iterations, status, restarts, xi (list), hist (list)).
+    ||b - Q x^t||/||b|| = |1 - xi_t|.  With ``stop="objective"``: x* = 1,
+    f* = -n/2 and f(eta 1) - f* = n (eta - 1)^2 / 2, so the monitor and the
+    confirmation are n (eta_t - 1)^2 / (2 + n) and n (xi_t - 1)^2 / (2 + n).
+    Same control flow and readings as ``accelerated_jacobi``; arithmetic in
+    ``digits``-digit decimals.
+    Returns dict(iterations, status, restarts, xi (list), hist (list), xhat (list)); xi holds the
+    accepted x^t of every iteration (x^{t-1} after a restart), xhat the computed Jacobi-type step.
     """
     getcontext().prec = digits
     one = Decimal(1)
@@ -471,19 +516,26 @@ def sdd_scalar_run(n: int, *, tol: float = 1e-8, max_iter: int = 5000, restart: 
     alpha = one
     K_re, K = 0, k0
     last_confirm = -(1 << 62)
-    restarts, xis, hist = [], [], []
+    restarts, xis, hist, xhat = [], [], [], []
+    obj = stop == "objective"
+    fs = Decimal(n) / (Decimal(2) + Decimal(n))
+
+    def gap(v):
+        return fs * (v - one) * (v - one) if obj else abs(v - one)
+
     for t in range(1, max_iter + 1):
         g = eta - one
         xi = eta - g / J
-        mon = abs(g)
+        xhat.append(xi)
+        mon = gap(eta)
         hist.append(mon)
         if t == 1 and mon <= tol_d:
-            return dict(iterations=0, status=STATUS_OK, restarts=restarts, xi=[Decimal(0)], hist=hist)
+            return dict(iterations=0, status=STATUS_OK, restarts=restarts, xi=[Decimal(0)], hist=hist, xhat=xhat)
         if mon <= tol_d and t >= last_confirm + confirm_gap:
             last_confirm = t
-            if abs(one - xi) <= tol_d:
+            if gap(xi) <= tol_d:
                 xis.append(xi)
-                return dict(iterations=t, status=STATUS_OK, restarts=restarts, xi=xis, hist=hist)
+                return dict(iterations=t, status=STATUS_OK, restarts=restarts, xi=xis, hist=hist, xhat=xhat)
         d = xi - xi_prev
         s = Decimal(n) * g * d
         if restart and t > K_re + K and s >= 0:
@@ -499,7 +551,7 @@ def sdd_scalar_run(n: int, *, tol: float = 1e-8, max_iter: int = 5000, restart: 
             xi_prev = xi
             xis.append(xi)
         alpha = a_next
-    return dict(iterations=max_iter, status=STATUS_NOT_CONVERGED, restarts=restarts, xi=xis, hist=hist)
+    return dict(iterations=max_iter, status=STATUS_NOT_CONVERGED, restarts=restarts, xi=xis, hist=hist, xhat=xhat)
 
 
 # ----------------------------------------------------------------------------
