@@ -92,10 +92,12 @@ def make_workload(name: str):
         return W.poisson2d_64()
     if name == "chunglu_4m":
         return W.chung_lu_laplacian()
+    if name.startswith("sdd_"):       # the Section 4.1 system (n+1) I - 1 1^T, b = 1 (dense rows)
+        return W.sdd_system(int(name[4:]))
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(sysobj, iterations_needed: int, sample_iters: int, jblock=None) -> dict:
+def cpu_baseline(sysobj, iterations_needed: int, sample_iters: int, jblock=None, stop_kw=None) -> dict:
     """Time the CPU oracle (as it is) on a bounded sample of the same solve and scale to solves/s."""
     from threadpoolctl import threadpool_limits
 
@@ -103,7 +105,7 @@ def cpu_baseline(sysobj, iterations_needed: int, sample_iters: int, jblock=None)
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
         r = O.accelerated_jacobi(sysobj.rowptr, sysobj.colidx, sysobj.vals, sysobj.b, tol=1e-8,
-                                 max_iter=sample_iters, jblock=jblock)
+                                 max_iter=sample_iters, jblock=jblock, **(stop_kw or {}))
         dt = time.perf_counter() - t0
     per_iter = dt / max(1, len(r.hist))
     solve_s = per_iter * iterations_needed
@@ -409,6 +411,9 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip the second-precision comparison solves")
     ap.add_argument("--nsys", type=int, default=512, help="systems in the fe_batch workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--stop", choices=["relres", "objective"], default="relres",
+                    help="single float64 solves: stop on the relative residual (tol 1e-8) or on the paper's "
+                         "relative objective gap (tol 1e-10, f* = -<b, x*>/2 from the generator's x*)")
     ap.add_argument("--jblock", type=int, default=0,
                     help="single-solve workloads: block-diagonal J of eq. (J-blkdiag) with blocks of this many rows")
     ap.add_argument("--serve-requests", type=int, default=2200, help="requests in the serve workload trace")
@@ -454,13 +459,24 @@ def main():
         print(json.dumps({"pmc_sample": True, "copy_bytes_each_way": src.numel() * 8, "passes": info.passes}))
         return
     jb = args.jblock
+    obj = args.stop == "objective"
+    if obj:
+        if args.precision != "fp64":
+            raise SystemExit("the objective-gap stop is a float64 option")
+        args.no_compare = True
+        fstar = -0.5 * float(np.dot(sysobj.b, sysobj.xstar))
+        stop_kw = dict(stop=naj.NAJ_STOP_OBJECTIVE, fstar=fstar)
+        tol = 1e-10
+    else:
+        stop_kw, tol = {}, 1e-8
     sysm = naj.System(sysobj.rowptr, sysobj.colidx, sysobj.vals, device="cuda:0", jblock=jb or None)
     b = torch.as_tensor(sysobj.b).to(dev)
     x = torch.empty(n, dtype=torch.float64, device=dev)
     mixed = args.precision == "mixed"
 
     def timed(mixed_: bool, steps: int, warmup: int):
-        opts = dict(tol=1e-8, max_iter=20000, precision=naj.NAJ_MIXED if mixed_ else naj.NAJ_FP64)
+        opts = dict(tol=tol, max_iter=20000, precision=naj.NAJ_MIXED if mixed_ else naj.NAJ_FP64,
+                    **(stop_kw if not mixed_ else {}))
         for _ in range(warmup):
             sysm.solve(b, out=x, hist_cap=0, **opts)
         torch.cuda.synchronize()
@@ -496,6 +512,8 @@ def main():
               f"(plain FP64 one system at a time)")
     if jb:
         wl += f"; block-diagonal J of eq. (J-blkdiag), blocks of {jb} rows"
+    if obj:
+        wl = wl.replace("tol 1e-8", "stop on the relative objective gap <= 1e-10 (f* = -<b, x*>/2)")
     line = {
         "metric": "solves/s + HBM GB/s at relres 1e-8 vs plain FP64; p50/p99 solve latency",
         "value": solves_s,
@@ -509,10 +527,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64" if mixed else "f64",
         "data": "synthetic",
-        "config": {"workload": wl, "n": n, "nnz": nnz, "precision": args.precision, "tol": 1e-8,
+        "config": {"workload": wl, "n": n, "nnz": nnz, "precision": args.precision, "tol": tol,
                    "iterations": info.iterations, "restarts": info.restarts, "confirmations": info.confirmations,
                    "passes": info.passes, "grid": info.grid, "relres": info.relres,
-                   "layout": sysm.info()["layout"], "jblock": jb},
+                   "layout": sysm.info()["layout"], "jblock": jb, "stop": args.stop,
+                   "objgap": info.objgap if obj else None},
         "p50_ms": float(np.percentile(lat, 50) * 1e3),
         "p99_ms": float(np.percentile(lat, 99) * 1e3),
         "kernel_ms": float(np.mean(kms)),
@@ -538,7 +557,8 @@ def main():
     if not args.no_cpu_baseline:
         progress("cpu baseline")
         its_fp64 = info.iterations if not mixed else line.get("compare", {}).get("iterations", info.iterations)
-        line["cpu_baseline"] = cpu_baseline(sysobj, its_fp64, args.cpu_sample_iters, jb or None)
+        line["cpu_baseline"] = cpu_baseline(sysobj, its_fp64, args.cpu_sample_iters, jb or None,
+                                            dict(stop="objective", fstar=stop_kw["fstar"]) if obj else None)
     sysm.close()
     print(json.dumps(line), flush=True)
 

@@ -51,6 +51,7 @@ typedef enum naj_status {
 } naj_status;
 
 enum { NAJ_FP64 = 0, NAJ_MIXED = 1 };
+enum { NAJ_STOP_RELRES = 0, NAJ_STOP_OBJECTIVE = 1 };
 
 /* Solver options.  Fill with naj_opts_default() and override fields. */
 typedef struct naj_opts {
@@ -65,6 +66,14 @@ typedef struct naj_opts {
     int32_t inner_stall;    /* mixed: once an inner monitor has fallen to <= 1/2, the inner solve also */
                             /* stops when the monitor has not fallen below 0.9 x its best value for    */
                             /* this many iterations (the float32 rounding floor); >= 1; default 200    */
+    int32_t stop;           /* NAJ_STOP_RELRES (default), or NAJ_STOP_OBJECTIVE: the paper's criterion */
+                            /* of Section 4, |f(x^t) - f*| / (1 + |f*|) <= tol with f(x) = <x,Qx>/2 -   */
+                            /* <b,x> (eq. (eq-qp)) and f* = fstar; float64 single solves only.  The    */
+                            /* gap at y^t (free with each pass) is the monitor and f(x^t) is confirmed */
+                            /* with one extra product; f(x^t) <= f(y^t), so a monitor <= tol implies   */
+                            /* the criterion at x^t                                                    */
+    int32_t pad_;           /* reserved, 0                                                             */
+    double  fstar;          /* f* for NAJ_STOP_OBJECTIVE; default 0                                    */
 } naj_opts;
 
 /* Per-right-hand-side result of a solve (host struct). */
@@ -74,11 +83,13 @@ typedef struct naj_result {
     int32_t restarts;       /* number of restarts (FP64) / inner restarts summed (mixed)               */
     int32_t confirmations;  /* residual confirmations (FP64) / float64 residual passes (mixed)        */
     double  relres;         /* ||b - Q x||_2 / ||b||_2 of the returned x as computed on the device     */
+                            /* (also with the objective stop)                                          */
     int32_t hist_len;       /* entries written to hist                                                 */
     int32_t nrestart_log;   /* entries written to the restart log                                      */
     double  kernel_ms;      /* device time of the solve kernel(s), from HIP events on `stream`         */
     int32_t passes;         /* matrix passes of the solve kernel(s): iterations + confirmations (+ refinement residuals) */
     int32_t grid;           /* workgroups of the persistent solve kernel                               */
+    double  objgap;         /* NAJ_STOP_OBJECTIVE: |f(x) - f*| / (1 + |f*|) of the returned x, else NaN  */
 } naj_result;
 
 typedef struct naj_system naj_system;

@@ -365,10 +365,10 @@ __global__ void __launch_bounds__(kAux) k_step64(SolveArgs a, const double* P, c
 }
 
 __global__ void __launch_bounds__(kAux) k_resid64(Sell A, int nxcd, const double* X, const double* b, double* out,
-                                                  double* part) {
+                                                  double* part, int obj) {
   __shared__ double sh[3][kAux / kWave];
   double p0 = 0.0, p1 = 0.0, p2 = 0.0;
-  pass_resid64<kAux>(A, nxcd, X, b, out, p0);
+  pass_resid64<kAux>(A, nxcd, X, b, out, p0, obj != 0);
   block_sum3<kAux>(p0, p1, p2, sh);
   if (threadIdx.x == 0) {
     double* slot = part + (size_t)blockIdx.x * kPartStride;
@@ -639,7 +639,8 @@ naj_status choose_grid(naj_system* s, hipStream_t st) {
   s->max_grid = (int)std::max<int64_t>(nxcd, std::min<int64_t>(g, want));
   const int small_slices = env_int("NAJ_SMALL_SLICES", 256);
   const int force = env_int("NAJ_MODE", -1);
-  s->mode = s->nslices + s->n_long / 4 <= small_slices ? kModeSmall : kModePass;
+  // one workgroup only for small systems (few slices and little stored work)
+  s->mode = (s->nslices + s->n_long / 4 <= small_slices && s->nnz <= (1 << 21)) ? kModeSmall : kModePass;
   if (force >= 0 && force <= 2) s->mode = force;
   s->grid = s->max_grid;
   if (s->mode == kModeSmall) s->grid = 1;
@@ -736,6 +737,11 @@ naj_status check_opts(const naj_opts& o) {
     if (o.max_refine < 1) return fail(NAJ_EINVAL, "max_refine must be >= 1");
   }
   if (o.inner_stall < 1) return fail(NAJ_EINVAL, "inner_stall must be >= 1 (got %d)", o.inner_stall);
+  if (o.stop != NAJ_STOP_RELRES && o.stop != NAJ_STOP_OBJECTIVE) return fail(NAJ_EINVAL, "unknown stop %d", o.stop);
+  if (o.stop == NAJ_STOP_OBJECTIVE) {
+    if (o.precision != NAJ_FP64) return fail(NAJ_EINVAL, "the objective-gap stop is a float64 option");
+    if (!(std::fabs(o.fstar) < HUGE_VAL)) return fail(NAJ_EINVAL, "fstar must be finite");
+  }
   return NAJ_OK;
 }
 
@@ -752,6 +758,7 @@ SolveArgs make_args(naj_system* s, const double* b, const naj_opts& o) {
   a.buf2 = s->vec[2];
   a.buf3 = s->vec[3];
   a.ymode = s->ymode;
+  a.ypar = 0;
   a.part = s->part;
   a.ctrl = s->ctrl;
   a.bar = s->bar;
@@ -769,6 +776,9 @@ SolveArgs make_args(naj_system* s, const double* b, const naj_opts& o) {
   a.max_refine = o.max_refine;
   a.inner_stall = o.inner_stall;
   a.inner_tol = o.inner_tol;
+  a.stop_obj = o.stop == NAJ_STOP_OBJECTIVE ? 1 : 0;
+  a.fstar = o.fstar;
+  a.fscale = 1.0 + std::fabs(o.fstar);
   a.f0 = s->fvec[0];
   a.f1 = s->fvec[1];
   a.f2 = s->fvec[2];
@@ -779,10 +789,11 @@ SolveArgs make_args(naj_system* s, const double* b, const naj_opts& o) {
   return a;
 }
 
+// ||b - Q x||^2 into *rr (with obj: f(x) = <x, Q x>/2 - <b, x> instead), fixed-order sums.
 naj_status residual_norm2(naj_system* s, const double* x, const double* b, double* out, double* rr,
-                          hipStream_t st) {
+                          hipStream_t st, bool obj = false) {
   const int G = s->aux_grid;
-  hipLaunchKernelGGL(k_resid64, dim3(G), dim3(kAux), 0, st, sell_of(s), s->nxcd, x, b, out, s->part);
+  hipLaunchKernelGGL(k_resid64, dim3(G), dim3(kAux), 0, st, sell_of(s), s->nxcd, x, b, out, s->part, obj ? 1 : 0);
   HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(k_reduce_fixed, dim3(1), dim3(kWave), 0, st, s->part, G, s->scal);
   HIP_TRY(hipGetLastError());
@@ -817,6 +828,9 @@ naj_status build_layout(naj_system* s, const int32_t* rowptr, const int32_t* col
     maxlen = std::max(maxlen, w);
   }
   int layout = plain_stored > (int64_t)(1.3 * (double)std::max<int64_t>(s->nnz, n)) ? 1 : 0;
+  // Long rows on average (a dense-row system such as the Section 4.1 matrix): one wavefront per row
+  // streams them with all 64 lanes instead of one lane per row over few slices.
+  if (s->nnz >= (1 << 20) && s->nnz > (int64_t)kLongRow * n) layout = 1;
   const int forced = env_int("NAJ_LAYOUT", -1);
   if (forced == 0 || forced == 1) layout = forced;
   if (s->jblock) layout = 0;   // a block J's rows must stay consecutive
@@ -1099,7 +1113,8 @@ naj_status batch_build(naj_batch* bt, hipStream_t st) {
     S.lk = 0;
     while ((1 << S.lk) < S.nrhs) ++S.lk;
     S.tile0 = (int)ht.size();
-    S.ymode = s->ymode;
+    // mixed batches, several right-hand sides: float32 inner passes in the materialized form
+    S.ymode = (mixed && S.nrhs > 1) ? 1 : s->ymode;
     bt->inst0[i] = bt->ninst;
     bt->ninst += bt->nrhs[i];
     const int lt = 4;   // long rows per item
@@ -1134,7 +1149,8 @@ naj_status batch_build(naj_batch* bt, hipStream_t st) {
     S.fs = (uint32_t)(nv * sizeof(float));
     S.xb = nullptr;
     S.fb = nullptr;
-    if ((rc = batch_alloc(bt, &S.xb, nv * (3 + s->ymode))) != NAJ_OK) return rc;
+    // float64 iterates: mixed refinement keeps x and x + d (2 buffers), float64 solves 3 (+1 materialized y)
+    if ((rc = batch_alloc(bt, &S.xb, nv * (mixed ? 2 : 3 + S.ymode))) != NAJ_OK) return rc;
     if (mixed && (rc = batch_alloc(bt, &S.fb, nv * 5)) != NAJ_OK) return rc;
     if ((rc = batch_alloc(bt, &S.b, nv)) != NAJ_OK) return rc;
     if ((rc = batch_alloc(bt, &S.part, (size_t)kPartStride * S.ntiles * S.nrhs)) != NAJ_OK) return rc;
@@ -1211,6 +1227,9 @@ void naj_opts_default(naj_opts* o) {
   o->inner_tol = 1e-4;
   o->max_refine = 50;
   o->inner_stall = 200;
+  o->stop = NAJ_STOP_RELRES;
+  o->pad_ = 0;
+  o->fstar = 0.0;
 }
 
 const char* naj_last_error(void) { return g_err.c_str(); }
@@ -1457,11 +1476,20 @@ naj_status naj_solve(naj_system* s, const double* b, const double* x0, const naj
     res->status = NAJ_EDEVICE;
     return fail(NAJ_EDEVICE, "grid barrier wait timed out inside the solve kernel");
   }
-  if ((hc.status == ST_NOT_CONVERGED || hc.status == ST_BREAKDOWN) && hc.result >= 0 && hc.nb > 0.0) {
+  res->objgap = __builtin_nan("");
+  const bool obj = o.stop == NAJ_STOP_OBJECTIVE;
+  if (obj && hc.status == ST_OK) res->objgap = hc.nb > 0.0 ? hc.relres : 0.0;
+  if ((obj || hc.status == ST_NOT_CONVERGED || hc.status == ST_BREAKDOWN) && hc.result >= 0 && hc.nb > 0.0) {
     double rr = 0.0;   // residual of the returned iterate, in the solver's row order
     rc = residual_norm2(s, s->vec[hc.result], b_in, nullptr, &rr, st);
     if (rc != NAJ_OK) return rc;
     res->relres = std::sqrt(rr) / hc.nb;
+    if (obj && hc.status != ST_OK) {   // the objective gap of the returned iterate
+      double fx = 0.0;
+      rc = residual_norm2(s, s->vec[hc.result], b_in, nullptr, &fx, st, true);
+      if (rc != NAJ_OK) return rc;
+      res->objgap = std::fabs(fx - o.fstar) / (1.0 + std::fabs(o.fstar));
+    }
   }
   if (hc.status == ST_BREAKDOWN) return fail(NAJ_EBREAKDOWN, "NaN/Inf in a reduction at iteration %d", hc.iterations);
   return (naj_status)hc.status;
@@ -1563,6 +1591,7 @@ naj_status naj_batch_create(int32_t nsys, naj_system* const* systems, const int3
   if (opts) o = *opts; else naj_opts_default(&o);
   naj_status rc = check_opts(o);
   if (rc != NAJ_OK) return rc;
+  if (o.stop != NAJ_STOP_RELRES) return fail(NAJ_EINVAL, "batches stop on the relative residual only");
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
   for (int i = 0; i < nsys; ++i) {

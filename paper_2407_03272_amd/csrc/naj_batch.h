@@ -97,6 +97,7 @@ __device__ __forceinline__ SolveArgs batch_ctrl_args(const BatchArgs& ba, const 
   a.inner_stall = ba.inner_stall;
   a.inner_tol = ba.inner_tol;
   a.ymode = S.ymode;
+  a.ypar = 1;
   return a;
 }
 
@@ -879,16 +880,201 @@ __device__ __forceinline__ void slice_inner_rows(const BatchSys& S, int64_t s, i
   }
 }
 
+// Materialized form of the row-form inner pass (systems of mixed batches with several
+// right-hand sides; with one, the two-iterate form measured faster when many systems run
+// together, the extra y store outweighing the halved gathers): the pass
+// gathers y^t from one buffer and writes y^{t+1} = x^t + beta_next (x^t - x^{t-1}) for the
+// next pass, one gathered vector instead of two.  The y buffers (roles 2 and 3) alternate
+// with the system's pass count, which is the same for all its right-hand sides, so every
+// right-hand side that reads y in a pass reads the same buffer and a gathered row's G
+// values come in one vector load.  Right-hand sides right after a restart (y = P = x^{t-1})
+// or at an inner solve's first step (y = 0) take their values by selects; the iterates
+// alternate between roles 0 and 1.
+template <int G>
+struct InnerGroupY {
+  int act;          // bit q: right-hand side j0+q is in the inner phase
+  int all;          // every right-hand side of the group is active
+  int bz, zp;       // bit q: y = P; previous iterate zero (y = 0)
+  int ybuf;         // y buffer of the right-hand sides that read y (-1: none reads y)
+  int ymix;         // they do not share one buffer (then both are loaded and selected)
+  int prot;         // common P buffer of the active right-hand sides, -1 if they differ
+  int wyn;          // buffer receiving y^{t+1} (-1: no active right-hand side writes one)
+  int yb[G];        // y buffer per right-hand side
+  int psig[G];      // P buffer per right-hand side (0 or 1)
+  float bnext[G];
+};
+
+template <int G>
+__device__ __forceinline__ InnerGroupY<G> inner_group_y(const PassView* views, int j0) {
+  InnerGroupY<G> g;
+  g.act = g.bz = g.zp = 0;
+  g.ybuf = g.wyn = -1;
+  g.ymix = 0;
+  int psigs = 0, p0 = 0;
+#pragma unroll
+  for (int q = 0; q < G; ++q) {
+    const NAJ_GLOBAL PassView& v = gptr(views)[j0 + q];
+    const bool on = uni(v.phase) == PH_INNER32;
+    g.psig[q] = uni(v.iP) & 1;
+    g.yb[q] = uni(v.iR) == 3 ? 3 : 2;
+    g.bnext[q] = uni_f((float)v.beta_next);
+    const bool bz = uni(v.bz) != 0, zp = uni(v.zp) != 0;
+    const int yn = uni(v.iYn);
+    if (!on) continue;
+    g.act |= 1 << q;
+    if (bz) g.bz |= 1 << q;
+    if (zp) g.zp |= 1 << q;
+    if (!bz && !zp) {
+      if (g.ybuf >= 0 && g.ybuf != g.yb[q]) g.ymix = 1;
+      g.ybuf = g.yb[q];
+    }
+    if (yn >= 0) g.wyn = yn;
+    psigs |= 1 << g.psig[q];
+    p0 = g.psig[q];
+  }
+  g.all = g.act == (1 << G) - 1;
+  g.prot = (psigs & (psigs - 1)) == 0 ? p0 : -1;
+  return g;
+}
+
+// y values of the group's right-hand sides at interleaved offset e.
+template <int G>
+__device__ __forceinline__ void y_at(const float* F, uint32_t fs, uint32_t e, const InnerGroupY<G>& g,
+                                     float (&y)[G]) {
+  float yv[G], pv[G];
+  if (g.ybuf >= 0 && !g.ymix) {
+    ld_vec<G>(F, (uint32_t)g.ybuf * fs + e, yv);
+  } else if (g.ymix) {
+    float t2[G], t3[G];
+    ld_vec<G>(F, 2u * fs + e, t2);
+    ld_vec<G>(F, 3u * fs + e, t3);
+#pragma unroll
+    for (int q = 0; q < G; ++q) yv[q] = g.yb[q] == 3 ? t3[q] : t2[q];
+  } else {
+#pragma unroll
+    for (int q = 0; q < G; ++q) yv[q] = 0.0f;
+  }
+  if (g.bz) {
+    if (g.prot >= 0) {
+      ld_vec<G>(F, (uint32_t)g.prot * fs + e, pv);
+    } else {
+      float t0[G], t1[G];
+      ld_vec<G>(F, e, t0);
+      ld_vec<G>(F, fs + e, t1);
+#pragma unroll
+      for (int q = 0; q < G; ++q) pv[q] = g.psig[q] ? t1[q] : t0[q];
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < G; ++q) pv[q] = 0.0f;
+  }
+#pragma unroll
+  for (int q = 0; q < G; ++q) y[q] = ((g.zp >> q) & 1) ? 0.0f : (((g.bz >> q) & 1) ? pv[q] : yv[q]);
+}
+
+template <int G>
+__device__ __forceinline__ void slice_inner_rows_ym(const BatchSys& S, int64_t s, int lane, int j0,
+                                                    const InnerGroupY<G>& g, double (&ps)[G], double (&pgg)[G]) {
+  constexpr int U = kRowUnroll;
+  const int lk = S.lk;
+  const int64_t row = S.A.row0 + s * kWave + lane;
+  const bool live = row < S.A.n;
+  const int64_t rr = live ? row : 0;
+  const float* F = S.fb;
+  const uint32_t fs = S.fs;
+  const int64_t base = uni(gptr(S.A.slice_ptr)[s]);
+  const int width = (int)((uni(gptr(S.A.slice_ptr)[s + 1]) - base) >> 6);
+  const uint32_t eo = elem<4>(rr, lk, (uint32_t)j0);
+  const NAJ_GLOBAL int32_t* cp = gptr(S.A.col) + base + lane;
+  const NAJ_GLOBAL float* vp = gptr(S.A.val32) + base + lane;
+  float acc[G];
+#pragma unroll
+  for (int q = 0; q < G; ++q) acc[q] = 0.0f;
+  float asum = 0.0f;
+  for (int k0 = 0; k0 < width; k0 += kRowChunk) {
+    int cr[kRowChunk];
+    float w[kRowChunk];
+#pragma unroll
+    for (int u = 0; u < kRowChunk; ++u) {   // past the slice width: reload the last column (cached), not added
+      const int kq = k0 + u < width ? k0 + u : width - 1;
+      cr[u] = mat_load(cp + kq * kWave);
+      w[u] = mat_load(vp + kq * kWave);
+    }
+#pragma unroll
+    for (int u0 = 0; u0 < kRowChunk; u0 += U) {
+      if (k0 + u0 >= width) break;
+      float yj[U][G];
+#pragma unroll
+      for (int u = 0; u < U; ++u) y_at<G>(F, fs, elem<4>(cr[u0 + u], lk, (uint32_t)j0), g, yj[u]);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (k0 + u0 + u >= width) break;
+        asum = asum + fabsf(w[u0 + u]);
+#pragma unroll
+        for (int q = 0; q < G; ++q)
+          if ((g.act >> q) & 1) acc[q] = acc[q] + w[u0 + u] * yj[u][q];
+      }
+    }
+  }
+  // own-row operands after the column loop (fewer registers live across it)
+  float Pi[G], yi[G], bi[G];
+  if (g.prot >= 0) {
+    ld_vec<G>(F, (uint32_t)g.prot * fs + eo, Pi);
+  } else {
+    float t0[G], t1[G];
+    ld_vec<G>(F, eo, t0);
+    ld_vec<G>(F, fs + eo, t1);
+#pragma unroll
+    for (int q = 0; q < G; ++q) Pi[q] = g.psig[q] ? t1[q] : t0[q];
+  }
+  y_at<G>(F, fs, eo, g, yi);
+  ld_vec<G>(F, 4u * fs + eo, bi);
+  const double di = S.dinv ? gptr(S.dinv)[rr] : 0.0;
+  if (live) {
+    const float dv = S.dinv ? (float)di : 1.0f / (asum == 0.0f ? 1.0f : asum);
+    float xo[G], yo[G];
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+      const float P0 = ((g.zp >> q) & 1) ? 0.0f : Pi[q];
+      const float gr = acc[q] - bi[q];
+      const float xi = yi[q] - dv * gr;
+      const float d = xi - P0;
+      xo[q] = xi;
+      yo[q] = xi + g.bnext[q] * d;
+      if ((g.act >> q) & 1) {
+        const double g64 = (double)gr, d64 = (double)d;
+        ps[q] = ps[q] + g64 * d64;
+        pgg[q] = pgg[q] + g64 * g64;
+      }
+    }
+    const uint32_t er = elem<4>(row, lk, (uint32_t)j0);
+    if (g.all && g.prot >= 0) {   // one W buffer for the group: one vector store
+      st_vec<G>(S.fb, (uint32_t)(1 - g.prot) * fs + er, xo);
+    } else {
+#pragma unroll
+      for (int q = 0; q < G; ++q)
+        if ((g.act >> q) & 1) st_at(S.fb, (uint32_t)(1 - g.psig[q]) * fs + er + 4u * q, xo[q]);
+    }
+    // y^{t+1} for the whole group: a right-hand side that does not use it next pass (not
+    // active, or restarting) never reads this slot before rewriting it
+    if (g.wyn >= 0) st_vec<G>(S.fb, (uint32_t)g.wyn * fs + er, yo);
+  }
+}
+
 // The slices of an item in the row form, every right-hand side of the inner phase; the
 // wave's sums for right-hand side j are added to lane j's p0, p1.
-template <int KP>
+template <int KP, bool YM>
 __device__ __forceinline__ void tile_inner_rows(const BatchSys& S, const BatchTile& T, const PassView* views, int lane,
                                                 double& p0, double& p1) {
   constexpr int G = KP < kRowGroup ? KP : kRowGroup;
   constexpr int NG = KP / G;
-  InnerGroup<G> grp[NG];
+  using Group = typename std::conditional<YM, InnerGroupY<G>, InnerGroup<G>>::type;
+  Group grp[NG];
 #pragma unroll
-  for (int gi = 0; gi < NG; ++gi) grp[gi] = inner_group<G>(views, gi * G);
+  for (int gi = 0; gi < NG; ++gi) {
+    if constexpr (YM) grp[gi] = inner_group_y<G>(views, gi * G);
+    else grp[gi] = inner_group<G>(views, gi * G);
+  }
   double a[NG][G], b[NG][G];
 #pragma unroll
   for (int gi = 0; gi < NG; ++gi)
@@ -897,7 +1083,10 @@ __device__ __forceinline__ void tile_inner_rows(const BatchSys& S, const BatchTi
   for (int64_t s = T.s0; s < T.s1; ++s) {
 #pragma unroll
     for (int gi = 0; gi < NG; ++gi)
-      if (grp[gi].act) slice_inner_rows<G>(S, s, lane, gi * G, grp[gi], a[gi], b[gi]);
+      if (grp[gi].act) {
+        if constexpr (YM) slice_inner_rows_ym<G>(S, s, lane, gi * G, grp[gi], a[gi], b[gi]);
+        else slice_inner_rows<G>(S, s, lane, gi * G, grp[gi], a[gi], b[gi]);
+      }
   }
 #pragma unroll
   for (int gi = 0; gi < NG; ++gi)
@@ -929,7 +1118,7 @@ __device__ __forceinline__ void item_phase(const BatchSys& S, const BatchTile& T
       p0 = p0 + x * x;
     }
   }
-  if (mine && (PH != PH_INNER32 || S.ymode)) {   // two-iterate float32 inner slices run in the row form
+  if (mine && PH != PH_INNER32) {   // float32 inner slices run in the row form
     const int nu = (T.s1 - T.s0) << lk;
     for (int u = 0; u < nu; ++u) {
       const int64_t s = (int64_t)T.s0 + (u >> lk);
@@ -965,13 +1154,15 @@ __device__ __forceinline__ void batch_item(const BatchSys& S, const BatchTile& T
   p0 = rhs_sum(p0, kp);
   p1 = rhs_sum(p1, kp);
   p2 = rhs_sum(p2, kp);
-  if (MIXED && !S.ymode && __any(v.phase == PH_INNER32)) {
-    // two-iterate float32 inner slices in the row form; a right-hand side is in one phase
-    // only, so one of the two terms added to lane j is zero
-    if (KPMAX >= 8 && kp == 8) tile_inner_rows<(KPMAX >= 8 ? 8 : 1)>(S, T, S.vt, lane, p0, p1);
-    else if (KPMAX >= 4 && kp == 4) tile_inner_rows<(KPMAX >= 4 ? 4 : 1)>(S, T, S.vt, lane, p0, p1);
-    else if (KPMAX >= 2 && kp == 2) tile_inner_rows<(KPMAX >= 2 ? 2 : 1)>(S, T, S.vt, lane, p0, p1);
-    else tile_inner_rows<1>(S, T, S.vt, lane, p0, p1);
+  if (MIXED && __any(v.phase == PH_INNER32)) {
+    // float32 inner slices in the row form (materialized form for several right-hand
+    // sides: mixed batches set it for every such system); a right-hand side is in one
+    // phase only, so one of the two terms added to lane j is zero
+    if (KPMAX >= 8 && kp == 8) tile_inner_rows<(KPMAX >= 8 ? 8 : 1), true>(S, T, S.vt, lane, p0, p1);
+    else if (KPMAX >= 4 && kp == 4) tile_inner_rows<(KPMAX >= 4 ? 4 : 1), true>(S, T, S.vt, lane, p0, p1);
+    else if (KPMAX >= 2 && kp == 2) tile_inner_rows<(KPMAX >= 2 ? 2 : 1), true>(S, T, S.vt, lane, p0, p1);
+    else if (S.ymode) tile_inner_rows<1, true>(S, T, S.vt, lane, p0, p1);
+    else tile_inner_rows<1, false>(S, T, S.vt, lane, p0, p1);
   }
 }
 

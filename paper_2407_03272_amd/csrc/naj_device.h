@@ -131,6 +131,9 @@ struct SolveArgs {
   const double* jinv;         // block J: inverse blocks, row r of a block holding row r of its inverse
   const float* jinv32;        // the same in float32 (inner solves)
   int jblock;                 // block J: rows per block (1, 2, 4 or 8; divides 64)
+  int stop_obj;               // 1: stop on the objective gap |f(x) - f*| / (1 + |f*|) (float64 solves)
+  double fstar;               // f* of that stop
+  double fscale;              // 1 + |f*|
   const double* b;
   double* buf0;
   double* buf1;
@@ -162,6 +165,9 @@ struct SolveArgs {
   float* f3;
   float* r32;                 // float32 right-hand side of the inner solve
   int ymode;                  // materialized momentum form (y written by each pass, one gathered vector)
+  int ypar;                   // materialized form in the float32 inner phase: the two y buffers alternate
+                              // with the pass count (batches: every right-hand side of a system reads y
+                              // from the same buffer in a pass)
 };
 
 // How a pass forms y^t and whether it writes y^{t+1}.
@@ -299,14 +305,17 @@ __device__ __forceinline__ void iter_slice(const SolveArgs& a, int64_t s, int la
     if (YM && m.Yn) m.Yn[row] = xi + m.beta_next * d;
     const double gd = g * d;
     ps = ps + gd;
-    pgg = pgg + g * g;
+    // monitor: ||Q y - b||^2, or with the objective stop f(y) = sum_i y_i (u_i / 2 - b_i)
+    pgg = pgg + (a.stop_obj ? yi * (0.5 * acc - bi) : g * g);
     psabs = psabs + fabs(gd);
   }
 }
 
-// One slice of r = b - Q x; accumulates ||r||^2 and optionally stores r.
+// One slice of r = b - Q x; accumulates ||r||^2 (with obj: f(x) = sum_i x_i ((Q x)_i / 2 - b_i))
+// and optionally stores r.
 __device__ __forceinline__ void resid_slice(const Sell& A, int64_t s, int lane, const double* __restrict__ X,
-                                            const double* __restrict__ b, double* __restrict__ out, double& prr) {
+                                            const double* __restrict__ b, double* __restrict__ out, double& prr,
+                                            bool obj = false) {
   const int64_t base = A.slice_ptr[s];
   const int width = (int)((A.slice_ptr[s + 1] - base) >> 6);
   const int64_t row = A.row0 + s * kWave + lane;
@@ -334,7 +343,7 @@ __device__ __forceinline__ void resid_slice(const Sell& A, int64_t s, int lane, 
   if (live) {
     const double r = bi - acc;
     if (out) out[row] = r;
-    prr = prr + r * r;
+    prr = prr + (obj ? X[row] * (0.5 * acc - bi) : r * r);
   }
 }
 
@@ -546,20 +555,21 @@ __device__ __forceinline__ void iter_long(const SolveArgs& a, int64_t r, int lan
     if (YM && m.Yn) m.Yn[r] = xi + m.beta_next * dd;
     const double gd = g * dd;
     ps = ps + gd;
-    pgg = pgg + g * g;
+    pgg = pgg + (a.stop_obj ? yi * (0.5 * acc - a.b[r]) : g * g);
     psabs = psabs + fabs(gd);
   }
 }
 
 __device__ __forceinline__ void resid_long(const Sell& A, int64_t r, int lane, const double* __restrict__ X,
-                                           const double* __restrict__ b, double* __restrict__ out, double& prr) {
+                                           const double* __restrict__ b, double* __restrict__ out, double& prr,
+                                           bool obj = false) {
   double acc, asum;
   long_row_sums<double>(A.lcol, A.lval, A.lrowptr[r], A.lrowptr[r + 1], lane, [&](int c) { return X[c]; }, acc, asum);
   acc = wave_sum(acc);
   if (lane == 0) {
     const double res = b[r] - acc;
     if (out) out[r] = res;
-    prr = prr + res * res;
+    prr = prr + (obj ? X[r] * (0.5 * acc - b[r]) : res * res);
   }
 }
 

@@ -146,8 +146,8 @@ naj_status naj_server_create(int64_t mem_budget, int32_t max_slots, int32_t max_
   else naj_opts_default(&o);
   if (!(o.tol > 0.0) || o.max_iter < 1 || o.k0 < 2 || o.confirm_gap < 1 ||
       (o.precision != NAJ_FP64 && o.precision != NAJ_MIXED) || !(o.inner_tol > 0.0 && o.inner_tol < 1.0) ||
-      o.max_refine < 1 || o.inner_stall < 1)
-    return fail(NAJ_EINVAL, "invalid options");
+      o.max_refine < 1 || o.inner_stall < 1 || o.stop != NAJ_STOP_RELRES)
+    return fail(NAJ_EINVAL, "invalid options (servers stop on the relative residual)");
   naj_server* sv = new naj_server();
   sv->opts = o;
   sv->max_slots = max_slots;
@@ -285,7 +285,8 @@ naj_status naj_server_admit(naj_server* sv, int64_t n, int64_t nnz, const int32_
   }
   sl.used = true;
   sl.tile0 = tile0;
-  sl.xb = (double*)sv->pool.alloc(nv * sizeof(double) * (3 + s->ymode));
+  const int ym = (mixed && nrhs > 1) ? 1 : s->ymode;   // as in batches
+  sl.xb = (double*)sv->pool.alloc(nv * sizeof(double) * (mixed ? 2 : 3 + ym));
   sl.fb = mixed ? (float*)sv->pool.alloc(nv * sizeof(float) * 5) : nullptr;
   sl.b = (double*)sv->pool.alloc(nv * sizeof(double));
   sl.part = (double*)sv->pool.alloc(sizeof(double) * kPartStride * ntiles * nrhs);
@@ -316,7 +317,7 @@ naj_status naj_server_admit(naj_server* sv, int64_t n, int64_t nnz, const int32_
   rec.nrhs = nrhs;
   rec.tile0 = (int)tile0;
   rec.ntiles = ntiles;
-  rec.ymode = s->ymode;
+  rec.ymode = ym;
   sl.gen = (int)(sv->next_ticket & 0x3fffffff) + 1;
   rec.gen = sl.gen;
   // the pass stream takes the slot after the admission work, between chunks

@@ -35,6 +35,14 @@ __device__ inline void ymode_plan_next(Ctrl* c) {
   c->iYn = bn == 0.0 ? -1 : (c->beta_zero ? 2 : (c->iR == 2 ? 3 : 2));
 }
 
+// The same with the y buffers chosen by the parity of the pass count (consecutive inner passes
+// alternate between buffers 2 and 3, so the buffer read is never the one written).
+__device__ inline void ymode_plan_parity(Ctrl* c) {
+  const double bn = (c->alpha - 1.0) / alpha_next(c->alpha);
+  c->beta_next = bn;
+  c->iYn = bn == 0.0 ? -1 : 2 + (c->passes & 1);
+}
+
 // Roles after a pass that did not restart, materialized form: x^t becomes the previous
 // iterate, and y^{t+1} is the buffer just written (or x^t itself).
 __device__ inline void ymode_advance(Ctrl* c) {
@@ -211,7 +219,10 @@ __device__ inline void mixed_after_inner(const SolveArgs& a, Ctrl* c, double s, 
     }
     c->zp = 0;
   }
-  if (a.ymode) ymode_plan_next(c);
+  if (a.ymode) {
+    if (a.ypar) ymode_plan_parity(c);
+    else ymode_plan_next(c);
+  }
   if (t >= a.max_iter) {
     mixed_finish_inner(a, c, c->iP, a.max_iter);   // d = the last iterate
     return;
@@ -253,7 +264,8 @@ __device__ inline void control_update(const SolveArgs& a, Ctrl* c, double r0, do
   if (phase == PH_ITER) {
     const int t = c->t;
     const double s = r0, gg = r1, sabs = r2;
-    const double mon = sqrt(gg) / c->nb;
+    // monitor at y^t: relative residual, or relative objective gap (gg then holds f(y^t))
+    const double mon = a.stop_obj ? fabs(gg - a.fstar) / a.fscale : sqrt(gg) / c->nb;
     if (a.hist && t - 1 < a.hist_cap) a.hist[t - 1] = mon;
     if (a.trace && t - 1 < a.trace_cap) {
       a.trace[2 * (t - 1)] = s;
@@ -286,7 +298,7 @@ __device__ inline void control_update(const SolveArgs& a, Ctrl* c, double r0, do
     return;
   }
   if (phase == PH_CONFIRM) {
-    const double rho = sqrt(r0) / c->nb;
+    const double rho = a.stop_obj ? fabs(r0 - a.fstar) / a.fscale : sqrt(r0) / c->nb;
     c->confirms += 1;
     if (rho <= a.tol) {
       c->status = ST_OK;
@@ -336,15 +348,15 @@ __device__ __forceinline__ void pass_iter64(const SolveArgs& a, const double* P,
   for (int64_t s = wr.first; s < wr.end; s += wr.step) iter_slice<JM, YM>(a, s, lane, P, m, W, p0, p1, p2);
 }
 
-// The workgroup's share of r = b - Q X (float64); ||r||^2 in p0.
+// The workgroup's share of r = b - Q X (float64); ||r||^2 in p0 (with obj: f(X)).
 template <int BS>
 __device__ __forceinline__ void pass_resid64(const Sell& A, int nxcd, const double* X, const double* b, double* out,
-                                             double& p0) {
+                                             double& p0, bool obj = false) {
   const int lane = threadIdx.x % kWave;
   const LongRange<BS> lr;
-  for (int64_t r = lr.first; r < A.n_long; r += lr.step) resid_long(A, r, lane, X, b, out, p0);
+  for (int64_t r = lr.first; r < A.n_long; r += lr.step) resid_long(A, r, lane, X, b, out, p0, obj);
   const WaveRange wr = wave_range<BS>(A, nxcd);
-  for (int64_t s = wr.first; s < wr.end; s += wr.step) resid_slice(A, s, lane, X, b, out, p0);
+  for (int64_t s = wr.first; s < wr.end; s += wr.step) resid_slice(A, s, lane, X, b, out, p0, obj);
 }
 
 // The workgroup's share of one pass; partial sums in p0..p2 (per thread).
@@ -362,7 +374,7 @@ __device__ __forceinline__ void run_pass(const SolveArgs& a, const PassView& v, 
     m.ym = YM;
     pass_iter64<JM, BS, YM>(a, pick(a, v.iP), m, pick(a, v.iW), p0, p1, p2);
   } else if (v.phase == PH_CONFIRM) {
-    pass_resid64<BS>(a.A, a.nxcd, pick(a, v.iW), a.b, nullptr, p0);
+    pass_resid64<BS>(a.A, a.nxcd, pick(a, v.iW), a.b, nullptr, p0, a.stop_obj != 0);
   } else if (v.phase == PH_INNER32) {
     const float* P = pickf(a, v.iP);
     float* W = pickf(a, v.iW);

@@ -27,6 +27,8 @@ NAJ_EBREAKDOWN = -4
 NAJ_EBUSY = -6
 NAJ_FP64 = 0
 NAJ_MIXED = 1
+NAJ_STOP_RELRES = 0
+NAJ_STOP_OBJECTIVE = 1
 
 
 class NajError(RuntimeError):
@@ -38,14 +40,15 @@ class NajError(RuntimeError):
 class NajOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("restart", ctypes.c_int32),
                 ("k0", ctypes.c_int32), ("confirm_gap", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int32), ("inner_stall", ctypes.c_int32)]
+                ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int32), ("inner_stall", ctypes.c_int32),
+                ("stop", ctypes.c_int32), ("pad_", ctypes.c_int32), ("fstar", ctypes.c_double)]
 
 
 class NajResult(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iterations", ctypes.c_int32), ("restarts", ctypes.c_int32),
                 ("confirmations", ctypes.c_int32), ("relres", ctypes.c_double), ("hist_len", ctypes.c_int32),
                 ("nrestart_log", ctypes.c_int32), ("kernel_ms", ctypes.c_double), ("passes", ctypes.c_int32),
-                ("grid", ctypes.c_int32)]
+                ("grid", ctypes.c_int32), ("objgap", ctypes.c_double)]
 
 
 _lib = None
@@ -155,6 +158,7 @@ class SolveInfo:
     kernel_ms: float = 0.0
     passes: int = 0
     grid: int = 0
+    objgap: float = float("nan")
 
 
 class System:
@@ -244,7 +248,7 @@ class System:
         info = SolveInfo(res.status, res.iterations, res.restarts, res.confirmations, res.relres,
                          hist[:res.hist_len].copy(), rlog[:res.nrestart_log].tolist(),
                          tr[:res.hist_len].copy() if trace else np.zeros((0, 2)),
-                         res.kernel_ms, res.passes, res.grid)
+                         res.kernel_ms, res.passes, res.grid, res.objgap)
         return x, info
 
     def step(self, p, r, beta: float, b, stream=None):

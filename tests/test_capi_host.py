@@ -22,8 +22,9 @@ def test_opts_defaults_and_struct_layout():
     o = naj.default_opts()
     assert o.tol == 1e-8 and o.max_iter == 20000 and o.restart == 1 and o.k0 == 2
     assert o.confirm_gap == 8 and o.precision == naj.NAJ_FP64 and o.inner_stall == 200
-    assert ctypes.sizeof(naj.NajOpts) == 48
-    assert ctypes.sizeof(naj.NajResult) == 48
+    assert o.stop == naj.NAJ_STOP_RELRES and o.fstar == 0.0
+    assert ctypes.sizeof(naj.NajOpts) == 64
+    assert ctypes.sizeof(naj.NajResult) == 56
 
 
 def test_version_and_error_string():
