@@ -632,9 +632,9 @@ naj_status choose_grid(naj_system* s, hipStream_t st) {
   int g = per_cu * s->cus;
   g -= g % nxcd;
   if (g < nxcd) g = nxcd;
-  // no more workgroups than give each wave one slice
+  // no more workgroups than give each wave one slice or one long row
   const int wpb = bs / kWave;
-  int64_t want = (s->nslices + wpb - 1) / wpb;
+  int64_t want = (s->nslices + s->n_long + wpb - 1) / wpb;
   want = ((want + nxcd - 1) / nxcd) * nxcd;
   s->max_grid = (int)std::max<int64_t>(nxcd, std::min<int64_t>(g, want));
   const int small_slices = env_int("NAJ_SMALL_SLICES", 256);
@@ -654,7 +654,7 @@ naj_status choose_grid(naj_system* s, hipStream_t st) {
     resident -= resident % nxcd;
     if (resident < nxcd) return fail(NAJ_EDEVICE, "persistent solve kernel cannot be resident");
     const int wpb1 = kSmallBlock / kWave;
-    int64_t w1 = (s->nslices + wpb1 - 1) / wpb1;
+    int64_t w1 = (s->nslices + s->n_long + wpb1 - 1) / wpb1;
     w1 = ((w1 + nxcd - 1) / nxcd) * nxcd;
     s->grid = (int)std::max<int64_t>(nxcd, std::min<int64_t>(resident, w1));
     s->max_grid = std::max(s->max_grid, s->grid);
@@ -662,7 +662,7 @@ naj_status choose_grid(naj_system* s, hipStream_t st) {
   {
     int ga = 8 * s->cus;
     ga -= ga % nxcd;
-    int64_t wa = (s->nslices + kAux / kWave - 1) / (kAux / kWave);
+    int64_t wa = (s->nslices + s->n_long + kAux / kWave - 1) / (kAux / kWave);
     wa = ((wa + nxcd - 1) / nxcd) * nxcd;
     s->aux_grid = (int)std::max<int64_t>(nxcd, std::min<int64_t>(std::max(ga, nxcd), wa));
     s->max_grid = std::max(s->max_grid, s->aux_grid);
