@@ -1113,8 +1113,8 @@ naj_status batch_build(naj_batch* bt, hipStream_t st) {
     S.lk = 0;
     while ((1 << S.lk) < S.nrhs) ++S.lk;
     S.tile0 = (int)ht.size();
-    // mixed batches, several right-hand sides: float32 inner passes in the materialized form
-    S.ymode = (mixed && S.nrhs > 1) ? 1 : s->ymode;
+    // several right-hand sides: the materialized form (one gathered vector per pass)
+    S.ymode = S.nrhs > 1 ? 1 : s->ymode;
     bt->inst0[i] = bt->ninst;
     bt->ninst += bt->nrhs[i];
     const int lt = 4;   // long rows per item

@@ -285,7 +285,7 @@ naj_status naj_server_admit(naj_server* sv, int64_t n, int64_t nnz, const int32_
   }
   sl.used = true;
   sl.tile0 = tile0;
-  const int ym = (mixed && nrhs > 1) ? 1 : s->ymode;   // as in batches
+  const int ym = nrhs > 1 ? 1 : s->ymode;   // as in batches
   sl.xb = (double*)sv->pool.alloc(nv * sizeof(double) * (mixed ? 2 : 3 + ym));
   sl.fb = mixed ? (float*)sv->pool.alloc(nv * sizeof(float) * 5) : nullptr;
   sl.b = (double*)sv->pool.alloc(nv * sizeof(double));
