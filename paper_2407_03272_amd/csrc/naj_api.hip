@@ -611,6 +611,14 @@ const void* pass_kernel(int jm, int bs, bool ym) {
   return ym ? pass_kernel_ym<true>(jm, bs) : pass_kernel_ym<false>(jm, bs);
 }
 
+// LDS-resident single-workgroup solve: 32 n bytes of vectors must fit beside the kernel's own LDS.
+constexpr int64_t kLdsMaxN = 4800;
+
+const void* solve_lds_kernel(int jm) {
+  if (jm == kJBlock) return (const void*)k_solve_lds<kJBlock, kSmallBlock>;
+  return jm ? (const void*)k_solve_lds<kJUser, kSmallBlock> : (const void*)k_solve_lds<kJRowSum, kSmallBlock>;
+}
+
 const void* solve_kernel(int jm, bool ym) {
   if (jm == kJBlock) return (const void*)k_solve64<kJBlock, kSmallBlock, false>;
   if (ym) return jm ? (const void*)k_solve64<kJUser, kSmallBlock, true> : (const void*)k_solve64<kJRowSum, kSmallBlock, true>;
@@ -954,6 +962,15 @@ naj_status build_layout(naj_system* s, const int32_t* rowptr, const int32_t* col
 naj_status run_solve(naj_system* s, SolveArgs& a, const naj_opts& o, hipStream_t st) {
   const int ud = jm_of(s);
   void* kargs[] = {&a};
+  if (s->mode == kModeSmall && !s->ymode && s->n <= kLdsMaxN && env_int("NAJ_LDS", 1)) {
+    const void* fn = solve_lds_kernel(ud);
+    const size_t bytes = (size_t)32 * s->n;
+    HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    HIP_TRY(hipEventRecord(s->ev0, st));
+    HIP_TRY(hipLaunchKernel(fn, dim3(1), dim3(kSmallBlock), kargs, bytes, st));
+    HIP_TRY(hipEventRecord(s->ev1, st));
+    return NAJ_OK;
+  }
   if (s->mode == kModeSmall) {
     HIP_TRY(hipEventRecord(s->ev0, st));
     HIP_TRY(hipLaunchKernel(solve_kernel(ud, s->ymode != 0), dim3(1), dim3(kSmallBlock), kargs, 0, st));

@@ -610,4 +610,47 @@ __global__ void k_peek_phase(const Ctrl* c, int* dst) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *dst = c->phase;
 }
 
+// Small systems whose vectors fit in LDS: one workgroup runs the whole solve with the three
+// iterates, b and the control block in LDS (the matrix stays in global memory and L2).  The
+// gathers and the scalar control then pay LDS latency instead of L2 latency, which is what
+// bounds a pass of a system this small.  The pass functions take generic pointers, so they
+// run unchanged on the LDS copies.  On exit the iterates and the control block are written
+// back, so the host reads the answer as after the other drivers.  Two-iterate form only.
+template <int JM, int BS>
+__global__ void __launch_bounds__(BS) k_solve_lds(SolveArgs a) {
+  extern __shared__ double lds[];   // [4 n]: iterates 0, 1, 2, then b
+  __shared__ double sh[3][BS / kWave];
+  __shared__ PassView v;
+  __shared__ Ctrl c;
+  const int64_t n = a.A.n;
+  for (int64_t i = threadIdx.x; i < n; i += BS) {
+    lds[i] = a.buf0[i];
+    lds[3 * n + i] = a.b[i];
+  }
+  if (threadIdx.x == 0) c = *a.ctrl;
+  __syncthreads();
+  SolveArgs al = a;
+  al.buf0 = lds;
+  al.buf1 = lds + n;
+  al.buf2 = lds + 2 * n;
+  al.b = lds + 3 * n;
+  al.ctrl = &c;
+  for (;;) {
+    if (threadIdx.x == 0) load_view(&c, &v);
+    __syncthreads();
+    if (v.phase == PH_DONE) break;
+    double p0 = 0.0, p1 = 0.0, p2 = 0.0;
+    run_pass<JM, BS, false>(al, v, p0, p1, p2);
+    block_sum3<BS>(p0, p1, p2, sh);
+    if (threadIdx.x == 0) control_update(al, &c, p0, p1, p2);
+    __syncthreads();
+  }
+  for (int64_t i = threadIdx.x; i < n; i += BS) {
+    a.buf0[i] = lds[i];
+    a.buf1[i] = lds[n + i];
+    a.buf2[i] = lds[2 * n + i];
+  }
+  if (threadIdx.x == 0) *a.ctrl = c;
+}
+
 }  // namespace naj

@@ -126,20 +126,27 @@ def test_solve_poisson2d_matches_oracle_bitwise(naj):
     assert info.relres <= 1e-8
 
 
-@pytest.mark.parametrize("mode", ["0", "1", "2"])
-def test_every_driver_matches_oracle(naj, mode, monkeypatch):
-    """The three solve drivers (one launch per pass / one workgroup / cooperative persistent grid) share the
-    pass and must all reproduce the oracle's run, on a regular and on a ragged matrix."""
-    _say("driver", mode)
+@pytest.mark.parametrize("mode,lds", [("0", "1"), ("1", "1"), ("1", "0"), ("2", "1")])
+def test_every_driver_matches_oracle(naj, mode, lds, monkeypatch):
+    """The solve drivers (one launch per pass / one workgroup with the vectors in LDS / one workgroup on
+    global memory / cooperative persistent grid) share the pass and must all reproduce the oracle's run,
+    on a regular and on a ragged matrix."""
+    _say("driver", mode, "lds", lds)
     monkeypatch.setenv("NAJ_MODE", mode)
     s = W.poisson2d_64()
     sysm = naj.System(s.rowptr, s.colidx, s.vals)
     rowptr, colidx, vals = W.random_spd(1000, 0.02, 5)
     sysr = naj.System(rowptr, colidx, vals)
     monkeypatch.delenv("NAJ_MODE")
+    monkeypatch.setenv("NAJ_LDS", lds)      # read by each solve
     _compare_solve(naj, sysm, s.rowptr, s.colidx, s.vals, s.b, tol=1e-8, max_iter=20000, bitwise=True)
     b = np.random.default_rng(3).standard_normal(1000)
     _compare_solve(naj, sysr, rowptr, colidx, vals, b, tol=1e-9, max_iter=20000)
+    x, info = sysm.solve(s.b, tol=1e-8, precision=naj.NAJ_MIXED)
+    m = O.accelerated_jacobi_mixed(s.rowptr, s.colidx, s.vals, s.b, tol=1e-8)
+    assert info.status == 0 and info.iterations == m.inner_total
+    assert np.array_equal(x.cpu().numpy(), m.x)
+    monkeypatch.delenv("NAJ_LDS")
 
 
 def test_solve_without_restart_is_algorithm1(naj):
