@@ -1239,26 +1239,32 @@ inline const void* batch_pass_kernel(bool mixed, int kpmax) {
   return (const void*)k_batch_pass<true, 8>;
 }
 
-// After a pass: for every system with an unfinished instance (one workgroup each, one
-// wavefront per right-hand side, so the instances of a system decide concurrently), the
-// items' partial sums of the instance in item order (lane l adds items l, l + 64, ...,
-// then a fixed butterfly over the lanes), the scalar decision, and the view of the next
-// pass.  The order depends only on the system's item count.
+// After a pass: for every system with an unfinished instance (one workgroup each), the
+// items' partial sums of each instance, the scalar decision, and the view of the next pass.
+// The workgroup's 8 wavefronts are shared out among the right-hand-side lanes kp (the power
+// of two >= k): 8/kp wavefronts per right-hand side, so the instances decide concurrently and
+// a system with one right-hand side adds its items with all 8.  Wavefront part q of a
+// right-hand side adds items q*64 + l, q*64 + l + 64*8/kp, ... in lane l, then a fixed
+// butterfly over the lanes, then the parts are added in order q = 0, 1, ...; the order
+// depends only on the system's item count and right-hand-side count.
 constexpr int kDecideBlock = kWave * kMaxRhs;
 
 __global__ void __launch_bounds__(kDecideBlock) k_batch_decide(BatchArgs ba) {
+  __shared__ double ws[kDecideBlock / kWave][3];
   const int nsact = uni(*gptr(ba.nsact));
   if ((int)blockIdx.x >= nsact) return;
   const int sys = uni(gptr(ba.sact)[blockIdx.x]);
   const BatchSys S = uniform_sys(ba.sys[sys]);
-  const int j = wave_id();
+  const int w = wave_id();
+  const int wpr = (kDecideBlock / kWave) >> S.lk;   // wavefronts per right-hand side
+  const int j = w / wpr, q = w % wpr;
   const int lane = (int)threadIdx.x % kWave;
-  if (j < S.nrhs && uni(gptr(S.vt)[j].phase) != PH_DONE) {
-    const SolveArgs a = batch_ctrl_args(ba, S);
+  const bool act = j < S.nrhs && uni(gptr(S.vt)[j].phase) != PH_DONE;
+  double r0 = 0.0, r1 = 0.0, r2 = 0.0;
+  if (act) {
     const NAJ_GLOBAL double* part = gptr(S.part) + (size_t)j * S.ntiles * kPartStride;
-    double r0 = 0.0, r1 = 0.0, r2 = 0.0;
 #pragma unroll 4
-    for (int i = lane; i < S.ntiles; i += kWave) {
+    for (int i = q * kWave + lane; i < S.ntiles; i += wpr * kWave) {
       r0 = r0 + part[(size_t)i * kPartStride + 0];
       r1 = r1 + part[(size_t)i * kPartStride + 1];
       r2 = r2 + part[(size_t)i * kPartStride + 2];
@@ -1266,17 +1272,30 @@ __global__ void __launch_bounds__(kDecideBlock) k_batch_decide(BatchArgs ba) {
     r0 = wave_sum(r0);
     r1 = wave_sum(r1);
     r2 = wave_sum(r2);
-    if (lane == 0) {
-      Ctrl* c = S.ctrl + j;
-      control_update(a, c, r0, r1, r2);
-      load_view(c, S.vt + j);
-      if (c->phase == PH_DONE) __hip_atomic_fetch_add(ba.done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (lane == 0) {
+    ws[w][0] = r0;
+    ws[w][1] = r1;
+    ws[w][2] = r2;
+  }
+  __syncthreads();
+  if (act && q == 0 && lane == 0) {
+    double s0 = ws[w][0], s1 = ws[w][1], s2 = ws[w][2];
+    for (int k = 1; k < wpr; ++k) {
+      s0 = s0 + ws[w + k][0];
+      s1 = s1 + ws[w + k][1];
+      s2 = s2 + ws[w + k][2];
     }
+    const SolveArgs a = batch_ctrl_args(ba, S);
+    Ctrl* c = S.ctrl + j;
+    control_update(a, c, s0, s1, s2);
+    load_view(c, S.vt + j);
+    if (c->phase == PH_DONE) __hip_atomic_fetch_add(ba.done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   __syncthreads();   // the views written above are visible to the workgroup
   if (ba.slot_done && threadIdx.x == 0) {
     bool all = true;
-    for (int q = 0; q < S.nrhs; ++q) all = all && S.vt[q].phase == PH_DONE;
+    for (int k = 0; k < S.nrhs; ++k) all = all && S.vt[k].phase == PH_DONE;
     if (all) ba.slot_done[sys] = S.gen;
   }
 }
