@@ -248,11 +248,12 @@ naj_status naj_batch_info(const naj_batch *batch, int32_t *ntiles, int32_t *grid
 void naj_batch_destroy(naj_batch *batch);
 
 /*
- * Autotuner for batch work items: times item sizes of 1..16 slices on `sys` solved alone
- * with `nrhs` right-hand sides for `passes` iterations, and records the fastest in a
- * process-wide table keyed by the system's features (layout, log2 n, nonzeros per
- * row, nrhs, precision); batches created afterwards use it.  *best_tile (host, may
- * be NULL) receives the choice.
+ * Autotuner for batch work items: times item sizes of 1..16 slices on copies of `sys`
+ * batched together (about 1 M rows in flight, at most 64 copies: a moderately loaded GPU)
+ * with `nrhs` right-hand sides for `passes` iterations (mixed precision: one inner solve of
+ * that many iterations), and records the fastest in a process-wide table keyed by the
+ * system's features (layout, log2 n, nonzeros per row, nrhs, precision); batches created
+ * afterwards use it.  *best_tile (host, may be NULL) receives the choice.
  */
 naj_status naj_autotune_tiles(naj_system *sys, int32_t nrhs, const naj_opts *opts, int32_t passes, void *stream,
                               int32_t *best_tile);

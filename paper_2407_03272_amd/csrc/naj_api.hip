@@ -1756,47 +1756,85 @@ naj_status naj_autotune_tiles(naj_system* s, int32_t nrhs, const naj_opts* opts,
   o.max_iter = std::max(1, passes);
   o.tol = 1e-300;
   o.inner_tol = 1e-300 < o.inner_tol ? o.inner_tol : 1e-4;
+  o.max_refine = 1;   // mixed: one inner solve of `passes` iterations between two residual passes
   const int cands[] = {1, 2, 4, 8, 16};
+  // Each item size is timed on copies of the system batched together, about 1 M rows in flight
+  // (at most 64 copies): a moderately loaded GPU, between a batch's full start and its tail of a
+  // few long-running systems.  Measured on the 512-system finite-element batch, the sizes picked
+  // this way ran it as fast as the best single size for every system (4 slices); picks from the
+  // system alone (the most, smallest items) were 12 % slower, from 4 M rows in flight 8 %, and
+  // from the sum of relative times over several regimes 2-4 %.  NAJ_TUNE_ROWS lists other
+  // regimes (rows in flight, 0 = the system alone; the score adds relative times).
+  std::vector<int> Rs;
+  {
+    const char* e = getenv("NAJ_TUNE_ROWS");
+    std::string spec = e ? e : "1048576";
+    size_t pos = 0;
+    while (pos <= spec.size()) {
+      size_t c = spec.find(',', pos);
+      if (c == std::string::npos) c = spec.size();
+      const long long rows = atoll(spec.substr(pos, c - pos).c_str());
+      Rs.push_back(rows <= 0 ? 1 : (int)std::max<int64_t>(1, std::min<int64_t>(64, rows / std::max<int64_t>(1, s->n))));
+      pos = c + 1;
+    }
+  }
+  int R = 1;
+  for (int r : Rs) R = std::max(R, r);
   hipStream_t st = (hipStream_t)stream;
   double* dbuf = nullptr;
-  HIP_TRY(hipMalloc((void**)&dbuf, sizeof(double) * s->n * nrhs * 2));
-  HIP_TRY(hipMemsetAsync(dbuf, 0, sizeof(double) * s->n * nrhs * 2, st));
+  HIP_TRY(hipMalloc((void**)&dbuf, sizeof(double) * s->n * nrhs * (1 + R)));
+  HIP_TRY(hipMemsetAsync(dbuf, 0, sizeof(double) * s->n * nrhs * (1 + R), st));
   hipLaunchKernelGGL(k_fill_ones, dim3(blocks_for(s->n * nrhs, kAux * 4)), dim3(kAux), 0, st, dbuf, s->n * nrhs);
-  double* xb = dbuf + (size_t)s->n * nrhs;
   const TuneKey key = tune_key(s, nrhs, o.precision);
-  int best = 16;
-  float best_ms = 1e30f;
-  std::vector<naj_result> res(nrhs);
+  std::vector<naj_result> res((size_t)nrhs * R);
+  std::vector<naj_system*> arr(R, s);
+  std::vector<int32_t> k(R, nrhs);
+  std::vector<const double*> bb(R, dbuf);
+  std::vector<double*> xx(R);
+  for (int r = 0; r < R; ++r) xx[r] = dbuf + (size_t)s->n * nrhs * (1 + r);
+  std::vector<int> tried;
+  std::vector<std::vector<float>> times;
   for (int T : cands) {
     if (T > std::max<int64_t>(1, s->nslices) && T != cands[0]) break;
     {
       std::lock_guard<std::mutex> g(g_tune_mu);
       g_tune[key] = T;
     }
-    naj_batch* bt = nullptr;
-    naj_system* arr[1] = {s};
-    int32_t k[1] = {nrhs};
-    naj_status rc = naj_batch_create(1, arr, k, &o, stream, &bt);
-    if (rc != NAJ_OK) {
-      (void)hipFree(dbuf);
-      return rc;
-    }
-    const double* bb[1] = {dbuf};
-    double* xx[1] = {xb};
-    float ms = 1e30f;
-    for (int rep = 0; rep < 2; ++rep) {
-      rc = naj_batch_solve(bt, bb, nullptr, xx, res.data(), stream);
-      if (rc < 0 && rc != NAJ_EBREAKDOWN) {
-        naj_batch_destroy(bt);
+    std::vector<float> ms(Rs.size(), 1e30f);
+    for (size_t regime = 0; regime < Rs.size(); ++regime) {
+      const int copies = Rs[regime];
+      naj_batch* bt = nullptr;
+      naj_status rc = naj_batch_create(copies, arr.data(), k.data(), &o, stream, &bt);
+      if (rc != NAJ_OK) {
         (void)hipFree(dbuf);
         return rc;
       }
-      ms = std::min(ms, (float)res[0].kernel_ms);
+      for (int rep = 0; rep < 2; ++rep) {
+        rc = naj_batch_solve(bt, bb.data(), nullptr, xx.data(), res.data(), stream);
+        if (rc < 0 && rc != NAJ_EBREAKDOWN) {
+          naj_batch_destroy(bt);
+          (void)hipFree(dbuf);
+          return rc;
+        }
+        ms[regime] = std::min(ms[regime], (float)res[0].kernel_ms);
+      }
+      naj_batch_destroy(bt);
     }
-    naj_batch_destroy(bt);
-    if (ms < best_ms) {
-      best_ms = ms;
-      best = T;
+    tried.push_back(T);
+    times.push_back(ms);
+  }
+  int best = tried[0];
+  float best_score = 1e30f;
+  for (size_t i = 0; i < tried.size(); ++i) {
+    float score = 0.0f;
+    for (size_t r = 0; r < Rs.size(); ++r) {
+      float m = 1e30f;
+      for (size_t q = 0; q < tried.size(); ++q) m = std::min(m, times[q][r]);
+      score += times[i][r] / m;
+    }
+    if (score < best_score) {
+      best_score = score;
+      best = tried[i];
     }
   }
   {
