@@ -300,6 +300,8 @@ naj_status naj_server_admit(naj_server* sv, int64_t n, int64_t nnz, const int32_
   hipLaunchKernelGGL(k_batch_load, g1, b1, 0, sv->adm, b, nrhs, kp, s->perm, s->n, sl.b);
   hipLaunchKernelGGL(k_batch_load, g1, b1, 0, sv->adm, x0, nrhs, kp, s->perm, s->n, sl.xb);
   HIP_TRY(hipGetLastError());
+  // the caller's b and x0 may be freed or reused once this call returns: the copies finish first
+  HIP_TRY(hipStreamSynchronize(sv->adm));
   BatchSys rec = {};
   rec.A = sell_of(s);
   rec.A.dom_bounds = nullptr;
