@@ -54,32 +54,35 @@ def measured_traffic(workload: str):
     return rec["traffic_bytes_per_pass"]
 
 
-def bytes_per_iteration(n: int, nnz: int, s_v: int = 8, s_x: int = 8, k: int = 1, jb: int = 0) -> int:
-    """Algorithmic bytes of one fused pass: CSR values + int32 columns, int32 row pointers, and four vector
-    streams (read x^{t-1}, read y^t / x^{t-2}, read b, write x^t); with a block J of jb-row blocks, each row
-    also reads its row of the block's inverse (jb values)."""
-    return (s_v + 4) * nnz + 4 * (n + 1) + 4 * k * s_x * n + jb * s_x * n
+def bytes_per_iteration(n: int, nnz: int, s_v: int = 8, s_x: int = 8, k: int = 1, jb: int = 0,
+                        nnz_off: int = 0) -> int:
+    """Algorithmic bytes of one fused pass: matrix values, int32 column indices (none for the nnz_off
+    nonzeros of slices in the column-offset form, whose columns follow from the slice's offset list),
+    int32 row pointers, and four vector streams (read x^{t-1}, read y^t / x^{t-2}, read b, write x^t);
+    with a block J of jb-row blocks, each row also reads its row of the block's inverse (jb values)."""
+    return s_v * nnz + 4 * (nnz - nnz_off) + 4 * (n + 1) + 4 * k * s_x * n + jb * s_x * n
 
 
-def bytes_per_residual(n: int, nnz: int) -> int:
+def bytes_per_residual(n: int, nnz: int, nnz_off: int = 0) -> int:
     """Algorithmic bytes of one float64 residual pass r = b - Q x: matrix, row pointers, read x and b."""
-    return 12 * nnz + 4 * (n + 1) + 2 * 8 * n
+    return 8 * nnz + 4 * (nnz - nnz_off) + 4 * (n + 1) + 2 * 8 * n
 
 
-def bytes_per_refinement_residual(n: int, nnz: int) -> int:
+def bytes_per_refinement_residual(n: int, nnz: int, nnz_off: int = 0) -> int:
     """Float64 residual pass of the mixed loop with the update fused: matrix, row pointers, read x (f64), d (f32)
     and b, write x + d (f64) and fl32(r) (f32)."""
-    return 12 * nnz + 4 * (n + 1) + 8 * n + 4 * n + 8 * n + 8 * n + 4 * n
+    return 8 * nnz + 4 * (nnz - nnz_off) + 4 * (n + 1) + 8 * n + 4 * n + 8 * n + 8 * n + 4 * n
 
 
-def solve_bytes(n: int, nnz: int, info, mixed: bool, jb: int = 0) -> int:
+def solve_bytes(n: int, nnz: int, info, mixed: bool, jb: int = 0, nnz_off: int = 0) -> int:
     """Algorithmic bytes of a whole solve from its pass counts (norm of b = 8n bytes)."""
     if not mixed:
         it = info.iterations
         conf = info.passes - it - 1
-        return 8 * n + it * bytes_per_iteration(n, nnz, jb=jb) + conf * bytes_per_residual(n, nnz)
-    return (8 * n + info.iterations * bytes_per_iteration(n, nnz, s_v=4, s_x=4, jb=jb)
-            + info.confirmations * bytes_per_refinement_residual(n, nnz))
+        return (8 * n + it * bytes_per_iteration(n, nnz, jb=jb, nnz_off=nnz_off)
+                + conf * bytes_per_residual(n, nnz, nnz_off))
+    return (8 * n + info.iterations * bytes_per_iteration(n, nnz, s_v=4, s_x=4, jb=jb, nnz_off=nnz_off)
+            + info.confirmations * bytes_per_refinement_residual(n, nnz, nnz_off))
 
 
 def make_workload(name: str):
@@ -480,16 +483,18 @@ def main():
     total, lat, kms, infos = timed(mixed, args.steps, args.warmup)
     progress(f"timed {args.steps} solves: {total / args.steps * 1e3:.2f} ms each")
     info = infos[-1]
-    alg_bytes = solve_bytes(n, nnz, info, mixed, jb)
+    sinfo = sysm.info()
+    nnz_off = sinfo["offset_nnz"]
+    alg_bytes = solve_bytes(n, nnz, info, mixed, jb, nnz_off)
     kernel_s = float(np.mean(kms)) / 1e3
     achieved = alg_bytes / kernel_s / 1e9
     solves_s = args.steps / total
     if mixed:
-        per_launch = bytes_per_iteration(n, nnz, s_v=4, s_x=4, jb=jb)
+        per_launch = bytes_per_iteration(n, nnz, s_v=4, s_x=4, jb=jb, nnz_off=nnz_off)
         wl = (f"{sysobj.name}: n={n}, nnz={nnz}; float32 inner accelerated Jacobi with float64 reductions inside "
               f"float64 iterative refinement, x0=0, restart on, K0=2, inner tol 1e-4, final relres <= 1e-8, single solve")
     else:
-        per_launch = bytes_per_iteration(n, nnz, jb=jb)
+        per_launch = bytes_per_iteration(n, nnz, jb=jb, nnz_off=nnz_off)
         wl = (f"{sysobj.name}: n={n}, nnz={nnz}, float64, x0=0, restart on, K0=2, tol 1e-8, single solve "
               f"(plain FP64 one system at a time)")
     if jb:
@@ -512,7 +517,8 @@ def main():
         "config": {"workload": wl, "n": n, "nnz": nnz, "precision": args.precision, "tol": tol,
                    "iterations": info.iterations, "restarts": info.restarts, "confirmations": info.confirmations,
                    "passes": info.passes, "grid": info.grid, "relres": info.relres,
-                   "layout": sysm.info()["layout"], "jblock": jb, "stop": args.stop,
+                   "layout": sinfo["layout"], "offset_slices": sinfo["offset_slices"],
+                   "nslices": sinfo["nslices"], "offset_nnz": nnz_off, "jblock": jb, "stop": args.stop,
                    "objgap": info.objgap if obj else None},
         "p50_ms": float(np.percentile(lat, 50) * 1e3),
         "p99_ms": float(np.percentile(lat, 99) * 1e3),
@@ -534,7 +540,7 @@ def main():
                            "p50_ms": float(np.percentile(clat, 50) * 1e3),
                            "p99_ms": float(np.percentile(clat, 99) * 1e3),
                            "iterations": ci.iterations, "confirmations": ci.confirmations, "relres": ci.relres,
-                           "gbps_solve": solve_bytes(n, nnz, ci, not mixed, jb) / (float(np.mean(ckms)) / 1e3) / 1e9}
+                           "gbps_solve": solve_bytes(n, nnz, ci, not mixed, jb, nnz_off) / (float(np.mean(ckms)) / 1e3) / 1e9}
     it = info.iterations
     if not args.no_cpu_baseline:
         progress("cpu baseline")

@@ -88,7 +88,7 @@ typedef struct naj_result {
     int32_t nrestart_log;   /* entries written to the restart log                                      */
     double  kernel_ms;      /* device time of the solve kernel(s), from HIP events on `stream`         */
     int32_t passes;         /* matrix passes of the solve kernel(s): iterations + confirmations (+ refinement residuals) */
-    int32_t grid;           /* workgroups of the persistent solve kernel                               */
+    int32_t grid;           /* workgroups per launch of the solve driver (mixed solves: their own grid) */
     double  objgap;         /* NAJ_STOP_OBJECTIVE: |f(x) - f*| / (1 + |f*|) of the returned x, else NaN  */
 } naj_result;
 
@@ -162,6 +162,23 @@ void naj_destroy_system(naj_system *sys);
  */
 naj_status naj_system_info(const naj_system *sys, int64_t *n, int64_t *nnz, int64_t *device_bytes,
                            int32_t *layout, int64_t *stored_entries);
+
+/*
+ * Slices of the sliced layout (layout 0) stored in the column-offset form.  When all 64 rows of a
+ * slice store their entries at columns row + S[0] < row + S[1] < ... of one increasing offset list
+ * S common to the slice (a stencil pattern; at most 15 offsets, every row + S[k] inside [0, n)),
+ * the slice keeps S once and the single-solve passes form its column indices instead of loading
+ * them (4 bytes less per stored entry).  A row lacking an offset stores an explicit zero there,
+ * which leaves every sum, and so every result, unchanged.  The form is taken where S is no longer
+ * than the slice's longest row (so no more entries are stored); NAJ_OFFSETS=0 in the environment at
+ * creation disables it.
+ *   offset_slices : slices in the column-offset form (0 with layout 1)
+ *   nslices       : slices of the layout
+ *   offset_nnz    : the caller's nonzeros held in those slices (no column index is read for them)
+ * Any output may be NULL.  Errors: NAJ_EINVAL for a NULL system.
+ */
+naj_status naj_system_offset_slices(const naj_system *sys, int64_t *offset_slices, int64_t *nslices,
+                                    int64_t *offset_nnz);
 
 /*
  * Solve Q x = b for one right-hand side (Algorithm 3; with NAJ_MIXED the same

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -241,8 +242,59 @@ __global__ void k_slice_width(const int32_t* rowptr, int64_t row0, int64_t n, in
   if ((threadIdx.x % kWave) == 0 && s < nslices) width[s] = len;
 }
 
+__device__ __forceinline__ long long wave_min_ll(long long v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const long long o = __shfl_xor(v, off, 64);
+    v = o < v ? o : v;
+  }
+  return v;
+}
+
+// Column-offset records of the slices of the regular layout (rows 64 s + lane).  One wavefront per
+// slice merges its rows' offsets (column - row) into the increasing list S.  The slice qualifies when
+// all 64 rows exist, every row's offsets increase strictly (so its entries, in stored order, take
+// increasing positions of S), |S| < kOffRec, and row + S[k] lies in [0, n) for every lane and k.
+// rec[0] = |S|, or 0 when the slice does not qualify.  Every loop ends: a row's scan is bounded by
+// its length, and each merge step either stops or advances the lanes holding the minimum.
+__global__ void k_slice_offsets(const int32_t* rowptr, const int32_t* colidx, int64_t n, int64_t nslices,
+                                int32_t* soff) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t s = t / kWave;   // the same for the whole wavefront (blockDim is a multiple of 64)
+  if (s >= nslices) return;
+  const int lane = (int)(t % kWave);
+  const int64_t row = s * kWave + lane;
+  int32_t* rec = soff + s * kOffRec;
+  const bool live = row < n;
+  int64_t p = live ? rowptr[row] : 0;
+  const int64_t e = live ? rowptr[row + 1] : 0;
+  bool mono = true;
+  for (int64_t q = p + 1; q < e; ++q) mono = mono && colidx[q] > colidx[q - 1];
+  bool good = __all(live && mono) != 0;
+  int cnt = 0;
+  while (good) {
+    const long long cur = p < e ? (long long)colidx[p] - row : LLONG_MAX;
+    const long long m = wave_min_ll(cur);
+    if (m == LLONG_MAX) break;
+    const bool inr = row + m >= 0 && row + m < n;
+    if (cnt == kOffRec - 1 || !__all(inr)) {
+      good = false;
+      break;
+    }
+    if (lane == 0) rec[1 + cnt] = (int32_t)m;
+    ++cnt;
+    if (cur == m) ++p;
+  }
+  if (lane == 0) rec[0] = good ? cnt : 0;
+}
+
+// Fills the slices: rows row0 + 64 s + lane.  An ordinary slice stores a row's entries in its first
+// positions and pads with zeros pointing at the row itself; a slice in the column-offset form (its
+// record's count > 0, regular layout) stores entry k of a row at column row + S[k], taking the row's
+// next stored entry when its column matches and an explicit zero otherwise.
 __global__ void k_sell_fill(const int32_t* rowptr, const int32_t* colidx, const double* vals, int64_t row0, int64_t n,
-                            int64_t nslices, const int64_t* slice_ptr, int32_t* col, double* val, float* val32) {
+                            int64_t nslices, const int64_t* slice_ptr, const int32_t* soff, int32_t* col, double* val,
+                            float* val32) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t s = t / kWave;
   if (s >= nslices) return;
@@ -253,6 +305,25 @@ __global__ void k_sell_fill(const int32_t* rowptr, const int32_t* colidx, const 
   const int64_t r0 = row < n ? rowptr[row] : 0;
   const int len = row < n ? (int)(rowptr[row + 1] - r0) : 0;
   const int32_t self = row < n ? (int32_t)row : 0;
+  const int32_t* rec = soff ? soff + s * kOffRec : nullptr;
+  if (rec && rec[0] > 0) {   // every lane of such a slice holds a row (row < n)
+    int p = 0;
+    for (int k = 0; k < width; ++k) {
+      const int64_t dst = base + (int64_t)k * kWave + lane;
+      const int32_t c = (int32_t)(row + rec[1 + k]);
+      col[dst] = c;
+      if (p < len && colidx[r0 + p] == c) {
+        const double v = vals[r0 + p];
+        val[dst] = v;
+        val32[dst] = (float)v;
+        ++p;
+      } else {
+        val[dst] = 0.0;
+        val32[dst] = 0.0f;
+      }
+    }
+    return;
+  }
   for (int k = 0; k < width; ++k) {
     const int64_t dst = base + (int64_t)k * kWave + lane;
     if (k < len) {
@@ -505,6 +576,9 @@ struct naj_system {
   double* lval = nullptr;
   float* lval32 = nullptr;
   int layout = 0;                  // 0 = slices in caller order; 1 = sorted slices + long rows
+  int32_t* soff = nullptr;         // column-offset records [nslices * kOffRec] (regular layout), or null
+  int64_t off_slices = 0;          // slices stored in the column-offset form
+  int64_t off_nnz = 0;             // the caller's nonzeros in those slices
   std::vector<int64_t> hslice;     // host copy of slice_ptr (for the domain split)
   int64_t* dom_bounds = nullptr;   // [nxcd+1] device copy of the balanced domain split
   double* vec[4] = {nullptr, nullptr, nullptr, nullptr};   // x buffers; the 4th only in the materialized form
@@ -522,8 +596,10 @@ struct naj_system {
   int max_grid = 0;                // largest grid of any driver (sizes the partial-sum array)
   int aux_grid = 0;                // grid of the stand-alone 256-thread one-pass kernels
   int grid = 0;                    // grid of the solve driver in use
+  int grid_mx = 0;                 // grid of the per-pass driver in mixed-precision solves
   int mode = 0;                    // kModePass / kModeSmall / kModePersistent
   int pass_bs = 256;               // block size of the per-pass kernel
+  int pass_bs_mx = 512;            // the same in mixed-precision solves
   int nxcd = 1;
   int cus = 0;
   long long spin_ticks = 0;
@@ -569,7 +645,7 @@ void free_system(naj_system* s) {
   for (void* p : {(void*)s->slice_ptr, (void*)s->col, (void*)s->val, (void*)s->val32, (void*)s->dinv, (void*)s->jinv, (void*)s->jinv32, (void*)s->perm,
                   (void*)s->dom_bounds, (void*)s->bperm, (void*)s->lrowptr, (void*)s->lcol, (void*)s->lval,
                   (void*)s->lval32, (void*)s->part, (void*)s->ctrl, (void*)s->bar, (void*)s->counters, (void*)s->hist,
-                  (void*)s->trace, (void*)s->scal})
+                  (void*)s->trace, (void*)s->scal, (void*)s->soff})
     sys_free(s, p);
   for (auto& v : s->vec) sys_free(s, v);
   for (auto& v : s->fvec) sys_free(s, v);
@@ -655,6 +731,25 @@ naj_status choose_grid(naj_system* s, hipStream_t st) {
   if (force >= 0 && force <= 2) s->mode = force;
   s->grid = s->max_grid;
   if (s->mode == kModeSmall) s->grid = 1;
+  {
+    // Mixed-precision solves: the float32 inner pass moves 8 instead of 12 bytes per stored entry
+    // (4 with the column-offset form) and needs more waves in flight on regular layouts: 512 threads
+    // x 3 per CU measured best on the 128^3 Laplacian (25.8 against 35.4 us per pass with the float64
+    // shape) and on 160^3 (40.7 against 61.4 us).  The sorted layout's gather-bound pass keeps the
+    // float64 shape (Chung-Lu n = 2^22: 728 against 800 us per pass).
+    const int bsm_default = s->layout == 0 ? 512 : 256;
+    int bsm = env_int("NAJ_BS_MIXED", bsm_default);
+    if (bsm != 256 && bsm != 512 && bsm != 1024) bsm = bsm_default;
+    s->pass_bs_mx = bsm;
+    int gm = std::max(1, env_int("NAJ_WG_PER_CU_MIXED", 3)) * s->cus;
+    gm -= gm % nxcd;
+    if (gm < nxcd) gm = nxcd;
+    const int wpbm = bsm / kWave;
+    int64_t wantm = (s->nslices + s->n_long + wpbm - 1) / wpbm;
+    wantm = ((wantm + nxcd - 1) / nxcd) * nxcd;
+    s->grid_mx = (int)std::max<int64_t>(nxcd, std::min<int64_t>(gm, wantm));
+    s->max_grid = std::max(s->max_grid, s->grid_mx);
+  }
   if (s->mode == kModePersistent) {
     int coop = 0;
     HIP_TRY(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, s->device));
@@ -734,6 +829,7 @@ Sell sell_of(const naj_system* s) {
   A.lcol = s->lcol;
   A.lval = s->lval;
   A.lval32 = s->lval32;
+  A.soff = s->soff;
   return A;
 }
 
@@ -932,13 +1028,47 @@ naj_status build_layout(naj_system* s, const int32_t* rowptr, const int32_t* col
   const int64_t row0 = s->n_long;
   s->nslices = (n - row0 + kWave - 1) / kWave;
   const std::vector<int32_t>& rp = layout == 1 ? hrp2 : hrp;
+  // column-offset records (regular layout): a slice takes the offset form when it qualifies and its
+  // offset list is no longer than its longest row, so the layout stores no more entries than without
+  // the form (the batch passes, which load every column index, read the same bytes either way)
+  std::vector<int32_t> hsoff;
+  if (layout == 0 && s->nslices > 0 && env_int("NAJ_OFFSETS", 1)) {
+    rc = dev_alloc(s, &s->soff, (size_t)s->nslices * kOffRec);
+    if (rc != NAJ_OK) return rc;
+    hipLaunchKernelGGL(k_slice_offsets, dim3(blocks_for(s->nslices * kWave, kAux)), dim3(kAux), 0, st, rowptr, colidx,
+                       n, s->nslices, s->soff);
+    HIP_TRY(hipGetLastError());
+    hsoff.resize((size_t)s->nslices * kOffRec);
+    HIP_TRY(hipMemcpyAsync(hsoff.data(), s->soff, sizeof(int32_t) * hsoff.size(), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+  }
+  s->off_slices = 0;
+  s->off_nnz = 0;
   std::vector<int64_t> hp(s->nslices + 1);
   hp[0] = 0;
   for (int64_t sl = 0; sl < s->nslices; ++sl) {
     int w = 0;
-    for (int64_t r = row0 + sl * kWave; r < std::min<int64_t>(n, row0 + (sl + 1) * kWave); ++r)
-      w = std::max(w, rp[r + 1] - rp[r]);
+    const int64_t ra = row0 + sl * kWave, rb = std::min<int64_t>(n, row0 + (sl + 1) * kWave);
+    for (int64_t r = ra; r < rb; ++r) w = std::max(w, rp[r + 1] - rp[r]);
+    if (!hsoff.empty()) {
+      int32_t& cnt = hsoff[(size_t)sl * kOffRec];
+      if (cnt > 0 && cnt <= w) {
+        w = cnt;
+        s->off_slices += 1;
+        s->off_nnz += (int64_t)rp[rb] - rp[ra];
+      } else {
+        cnt = 0;
+      }
+    }
     hp[sl + 1] = hp[sl] + (int64_t)w * kWave;
+  }
+  if (!hsoff.empty()) {
+    if (s->off_slices == 0) {
+      sys_free(s, s->soff);
+      s->soff = nullptr;
+    } else {
+      HIP_TRY(hipMemcpyAsync(s->soff, hsoff.data(), sizeof(int32_t) * hsoff.size(), hipMemcpyHostToDevice, st));
+    }
   }
   s->stored = hp[s->nslices] + (layout == 1 ? (int64_t)rp[row0] : 0);
   rc = dev_alloc(s, &s->slice_ptr, (size_t)s->nslices + 1);
@@ -950,7 +1080,7 @@ naj_status build_layout(naj_system* s, const int32_t* rowptr, const int32_t* col
   s->hslice = hp;
   if (s->nslices > 0) {
     hipLaunchKernelGGL(k_sell_fill, dim3(blocks_for(s->nslices * kWave, kAux)), dim3(kAux), 0, st, src_rp, src_col,
-                       src_val, row0, n, s->nslices, s->slice_ptr, s->col, s->val, s->val32);
+                       src_val, row0, n, s->nslices, s->slice_ptr, s->soff, s->col, s->val, s->val32);
     HIP_TRY(hipGetLastError());
   }
   HIP_TRY(hipStreamSynchronize(st));
@@ -988,8 +1118,9 @@ naj_status run_solve(naj_system* s, SolveArgs& a, const naj_opts& o, hipStream_t
   }
   // one launch per pass, enqueued in chunks; the host checks the phase word of
   // the previous chunk while the current one runs, so the device never waits
-  const void* fn = pass_kernel(ud, s->pass_bs, s->ymode != 0);
-  const dim3 grid(s->grid), block(s->pass_bs);
+  const bool mx = o.precision == NAJ_MIXED;
+  const void* fn = pass_kernel(ud, mx ? s->pass_bs_mx : s->pass_bs, s->ymode != 0);
+  const dim3 grid(mx ? s->grid_mx : s->grid), block(mx ? s->pass_bs_mx : s->pass_bs);
   // passes: norm of b + iterations + confirmations (at most one per confirm_gap iterations, plus one)
   const int64_t max_pass = o.precision == NAJ_MIXED
                                ? 2 + (int64_t)(o.max_refine + 1) * (1 + (int64_t)o.max_iter)
@@ -1413,6 +1544,15 @@ naj_status naj_system_info(const naj_system* s, int64_t* n, int64_t* nnz, int64_
   return NAJ_OK;
 }
 
+naj_status naj_system_offset_slices(const naj_system* s, int64_t* offset_slices, int64_t* nslices,
+                                    int64_t* offset_nnz) {
+  if (!s) return fail(NAJ_EINVAL, "system is NULL");
+  if (offset_slices) *offset_slices = s->off_slices;
+  if (nslices) *nslices = s->nslices;
+  if (offset_nnz) *offset_nnz = s->off_nnz;
+  return NAJ_OK;
+}
+
 naj_status naj_solve(naj_system* s, const double* b, const double* x0, const naj_opts* opts, double* x,
                      naj_result* res, double* hist, int32_t hist_cap, int32_t* restart_log, int32_t log_cap,
                      double* trace, int32_t trace_cap, void* stream) {
@@ -1491,7 +1631,7 @@ naj_status naj_solve(naj_system* s, const double* b, const double* x0, const naj
   HIP_TRY(hipEventElapsedTime(&ms, s->ev0, s->ev1));
   res->kernel_ms = ms;
   res->passes = hc.passes;
-  res->grid = s->grid;
+  res->grid = (s->mode == kModePass && o.precision == NAJ_MIXED) ? s->grid_mx : s->grid;
   if (hc.timeout) {
     res->status = NAJ_EDEVICE;
     return fail(NAJ_EDEVICE, "grid barrier wait timed out inside the solve kernel");

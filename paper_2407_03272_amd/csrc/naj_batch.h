@@ -173,6 +173,7 @@ __device__ __forceinline__ BatchSys uniform_sys(const BatchSys& g) {
   S.A.lcol = uni(g.A.lcol);
   S.A.lval = uni(g.A.lval);
   S.A.lval32 = uni(g.A.lval32);
+  S.A.soff = nullptr;   // batch passes load every column index
   S.dinv = uni(g.dinv);
   S.xb = uni(g.xb);
   S.fb = uni(g.fb);

@@ -115,7 +115,32 @@ struct Sell {
   const int32_t* lcol;
   const double* lval;
   const float* lval32;
+  const int32_t* soff;        // [nslices * kOffRec] column-offset records of the slices, or null
 };
+
+// Column-offset form of a slice.  When every row r of a 64-row slice stores its entries at columns
+// r + S[0] < r + S[1] < ... (a subsequence of one increasing offset list S common to the slice, as in
+// a stencil), entry k of every lane has column r + S[k]: a row without offset S[k] holds an explicit
+// zero there (which leaves its sums unchanged), and the slice's width is |S|.  The column indices
+// then follow from S and are not loaded.  Record s holds |S| at [0] (0: ordinary slice) and S at
+// [1 .. |S|].  The col array is filled either way, so code that loads columns reads the same values.
+constexpr int kOffRec = 16;
+
+__device__ __forceinline__ const int32_t* slice_offsets(const Sell& A, int64_t s) {
+  if (!A.soff) return nullptr;
+  const int32_t* r = A.soff + s * kOffRec;
+  return r[0] ? r + 1 : nullptr;
+}
+
+// Column index of column step k of a slice's lane: formed from the slice's offsets (OFF) or loaded.
+template <bool OFF>
+__device__ __forceinline__ int slice_col(const int32_t* __restrict__ cp, const int32_t* __restrict__ so, int32_t row,
+                                         int k) {
+  if constexpr (OFF)
+    return row + so[k];
+  else
+    return stream_load(cp + k * kWave);
+}
 
 // Which J a pass applies (template parameter JM of the pass functions):
 //  0  J of eq. (J-diag), recomputed from the row's values as its absolute sum;
@@ -233,6 +258,103 @@ __device__ __forceinline__ WaveRange wave_range(const Sell& A, int nxcd) {
   return slice_range(A.nslices, nxcd, (int)gridDim.x, (int)blockIdx.x, wave_id(), BS / kWave, A.dom_bounds);
 }
 
+template <typename T>
+__device__ __forceinline__ T abs_of(T v) {
+  if constexpr (sizeof(T) == 4)
+    return fabsf(v);
+  else
+    return fabs(v);
+}
+
+// One lane's sums over its slice's column steps in the fused pass, in stored order:
+// acc = sum_k v_k y_{c_k} and asum = sum_k |v_k|, with y = P + beta (P - R) (two-iterate form),
+// y = R (materialized form), y = P (bz) or y = 0 (zy).  OFF: the slice's columns come from its
+// offsets.  The two column sources are separate instances so each keeps its own register budget.
+template <bool OFF, bool YM, typename T>
+__device__ __forceinline__ void fused_row_sums(const int32_t* __restrict__ cp, const int32_t* __restrict__ so,
+                                               int32_t row, const T* __restrict__ vp, int width,
+                                               const T* __restrict__ P, const T* __restrict__ R, T beta, bool bz,
+                                               bool zy, T& acc, T& asum) {
+  for (int k0 = 0; k0 < width; k0 += kUnroll) {
+    int c[kUnroll];
+    T v[kUnroll], y[kUnroll];
+#pragma unroll
+    for (int j = 0; j < kUnroll; ++j)
+      if (k0 + j < width) {
+        c[j] = slice_col<OFF>(cp, so, row, k0 + j);
+        v[j] = stream_load(vp + (k0 + j) * kWave);
+      }
+    if (zy) {
+#pragma unroll
+      for (int j = 0; j < kUnroll; ++j) y[j] = T(0);
+    } else if (bz) {
+#pragma unroll
+      for (int j = 0; j < kUnroll; ++j)
+        if (k0 + j < width) y[j] = P[c[j]];
+    } else if (YM) {
+#pragma unroll
+      for (int j = 0; j < kUnroll; ++j)
+        if (k0 + j < width) y[j] = R[c[j]];
+    } else {
+      T pj[kUnroll], rj[kUnroll];
+#pragma unroll
+      for (int j = 0; j < kUnroll; ++j)
+        if (k0 + j < width) {
+          pj[j] = P[c[j]];
+          rj[j] = R[c[j]];
+        }
+#pragma unroll
+      for (int j = 0; j < kUnroll; ++j)
+        if (k0 + j < width) y[j] = pj[j] + beta * (pj[j] - rj[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < kUnroll; ++j)
+      if (k0 + j < width) {
+        acc = acc + v[j] * y[j];
+        asum = asum + abs_of(v[j]);
+      }
+  }
+}
+
+// One lane's sum_k v_k x_{c_k} over its slice (OFF as above); with D, x = X + (double)D at every
+// gathered column.
+template <bool OFF>
+__device__ __forceinline__ double resid_row_sum(const int32_t* __restrict__ cp, const int32_t* __restrict__ so,
+                                                int32_t row, const double* __restrict__ vp, int width,
+                                                const double* __restrict__ X, const float* __restrict__ D) {
+  double acc = 0.0;
+  for (int k0 = 0; k0 < width; k0 += kUnroll) {
+    int c[kUnroll];
+    double v[kUnroll], xj[kUnroll];
+#pragma unroll
+    for (int j = 0; j < kUnroll; ++j)
+      if (k0 + j < width) {
+        c[j] = slice_col<OFF>(cp, so, row, k0 + j);
+        v[j] = stream_load(vp + (k0 + j) * kWave);
+      }
+    if (D) {
+      float dj[kUnroll];
+#pragma unroll
+      for (int j = 0; j < kUnroll; ++j)
+        if (k0 + j < width) {
+          xj[j] = X[c[j]];
+          dj[j] = D[c[j]];
+        }
+#pragma unroll
+      for (int j = 0; j < kUnroll; ++j)
+        if (k0 + j < width) xj[j] = xj[j] + (double)dj[j];
+    } else {
+#pragma unroll
+      for (int j = 0; j < kUnroll; ++j)
+        if (k0 + j < width) xj[j] = X[c[j]];
+    }
+#pragma unroll
+    for (int j = 0; j < kUnroll; ++j)
+      if (k0 + j < width) acc = acc + v[j] * xj[j];
+  }
+  return acc;
+}
+
 // One slice of the fused pass: u = Q y, g = u - b, x = y - J^{-1} g, d = x - P,
 // with y = P + beta (P - R) formed at every gathered column (y = P when bz).
 template <int JM, bool YM>
@@ -254,45 +376,13 @@ __device__ __forceinline__ void iter_slice(const SolveArgs& a, int64_t s, int la
   const double bi = a.b[rr];
   const double di = (JM == 1) ? a.dinv[rr] : 0.0;
   const int32_t* __restrict__ cp = a.A.col + base + lane;
+  const int32_t* __restrict__ so = slice_offsets(a.A, s);
   const double* __restrict__ vp = a.A.val + base + lane;
   double acc = 0.0, asum = 0.0;
-  for (int k0 = 0; k0 < width; k0 += kUnroll) {
-    int c[kUnroll];
-    double v[kUnroll], y[kUnroll];
-#pragma unroll
-    for (int j = 0; j < kUnroll; ++j) {
-      if (k0 + j < width) {
-        c[j] = stream_load(cp + (k0 + j) * kWave);
-        v[j] = stream_load(vp + (k0 + j) * kWave);
-      }
-    }
-    if (bz) {
-#pragma unroll
-      for (int j = 0; j < kUnroll; ++j)
-        if (k0 + j < width) y[j] = P[c[j]];
-    } else if (ym) {
-#pragma unroll
-      for (int j = 0; j < kUnroll; ++j)
-        if (k0 + j < width) y[j] = R[c[j]];
-    } else {
-      double pj[kUnroll], rj[kUnroll];
-#pragma unroll
-      for (int j = 0; j < kUnroll; ++j)
-        if (k0 + j < width) {
-          pj[j] = P[c[j]];
-          rj[j] = R[c[j]];
-        }
-#pragma unroll
-      for (int j = 0; j < kUnroll; ++j)
-        if (k0 + j < width) y[j] = pj[j] + beta * (pj[j] - rj[j]);
-    }
-#pragma unroll
-    for (int j = 0; j < kUnroll; ++j)
-      if (k0 + j < width) {
-        acc = acc + v[j] * y[j];
-        asum = asum + fabs(v[j]);
-      }
-  }
+  if (so)
+    fused_row_sums<true, YM>(cp, so, (int32_t)rr, vp, width, P, R, beta, bz, false, acc, asum);
+  else
+    fused_row_sums<false, YM>(cp, so, (int32_t)rr, vp, width, P, R, beta, bz, false, acc, asum);
   double z = 0.0;
   if constexpr (JM == kJBlock) z = block_apply(a.jinv, s, lane, a.jblock, live ? acc - bi : 0.0);
   if (live) {
@@ -322,24 +412,11 @@ __device__ __forceinline__ void resid_slice(const Sell& A, int64_t s, int lane, 
   const bool live = row < A.n;
   const double bi = b[live ? row : 0];
   const int32_t* __restrict__ cp = A.col + base + lane;
+  const int32_t* __restrict__ so = slice_offsets(A, s);
   const double* __restrict__ vp = A.val + base + lane;
-  double acc = 0.0;
-  for (int k0 = 0; k0 < width; k0 += kUnroll) {
-    int c[kUnroll];
-    double v[kUnroll], xj[kUnroll];
-#pragma unroll
-    for (int j = 0; j < kUnroll; ++j)
-      if (k0 + j < width) {
-        c[j] = stream_load(cp + (k0 + j) * kWave);
-        v[j] = stream_load(vp + (k0 + j) * kWave);
-      }
-#pragma unroll
-    for (int j = 0; j < kUnroll; ++j)
-      if (k0 + j < width) xj[j] = X[c[j]];
-#pragma unroll
-    for (int j = 0; j < kUnroll; ++j)
-      if (k0 + j < width) acc = acc + v[j] * xj[j];
-  }
+  const int32_t rw = (int32_t)(live ? row : 0);
+  const double acc = so ? resid_row_sum<true>(cp, so, rw, vp, width, X, nullptr)
+                        : resid_row_sum<false>(cp, so, rw, vp, width, X, nullptr);
   if (live) {
     const double r = bi - acc;
     if (out) out[row] = r;
@@ -369,47 +446,13 @@ __device__ __forceinline__ void inner_slice(const SolveArgs& a, int64_t s, int l
   const float bi = a.r32[rr];
   const double di = (JM == 1) ? a.dinv[rr] : 0.0;
   const int32_t* __restrict__ cp = a.A.col + base + lane;
+  const int32_t* __restrict__ so = slice_offsets(a.A, s);
   const float* __restrict__ vp = a.A.val32 + base + lane;
   float acc = 0.0f, asum = 0.0f;
-  for (int k0 = 0; k0 < width; k0 += kUnroll) {
-    int c[kUnroll];
-    float v[kUnroll], y[kUnroll];
-#pragma unroll
-    for (int j = 0; j < kUnroll; ++j)
-      if (k0 + j < width) {
-        c[j] = stream_load(cp + (k0 + j) * kWave);
-        v[j] = stream_load(vp + (k0 + j) * kWave);
-      }
-    if (zp) {
-#pragma unroll
-      for (int j = 0; j < kUnroll; ++j) y[j] = 0.0f;
-    } else if (bz) {
-#pragma unroll
-      for (int j = 0; j < kUnroll; ++j)
-        if (k0 + j < width) y[j] = P[c[j]];
-    } else if (ym) {
-#pragma unroll
-      for (int j = 0; j < kUnroll; ++j)
-        if (k0 + j < width) y[j] = R[c[j]];
-    } else {
-      float pj[kUnroll], rj[kUnroll];
-#pragma unroll
-      for (int j = 0; j < kUnroll; ++j)
-        if (k0 + j < width) {
-          pj[j] = P[c[j]];
-          rj[j] = R[c[j]];
-        }
-#pragma unroll
-      for (int j = 0; j < kUnroll; ++j)
-        if (k0 + j < width) y[j] = pj[j] + beta * (pj[j] - rj[j]);
-    }
-#pragma unroll
-    for (int j = 0; j < kUnroll; ++j)
-      if (k0 + j < width) {
-        acc = acc + v[j] * y[j];
-        asum = asum + fabsf(v[j]);
-      }
-  }
+  if (so)
+    fused_row_sums<true, YM>(cp, so, (int32_t)rr, vp, width, P, R, beta, bz, zp, acc, asum);
+  else
+    fused_row_sums<false, YM>(cp, so, (int32_t)rr, vp, width, P, R, beta, bz, zp, acc, asum);
   float z = 0.0f;
   if constexpr (JM == kJBlock) z = block_apply(a.jinv32, s, lane, a.jblock, live ? acc - bi : 0.0f);
   if (live) {
@@ -444,37 +487,10 @@ __device__ __forceinline__ void resid_mixed_slice(const SolveArgs& a, int64_t s,
   const double xi0 = X[rr];
   const float di0 = D ? D[rr] : 0.0f;
   const int32_t* __restrict__ cp = a.A.col + base + lane;
+  const int32_t* __restrict__ so = slice_offsets(a.A, s);
   const double* __restrict__ vp = a.A.val + base + lane;
-  double acc = 0.0;
-  for (int k0 = 0; k0 < width; k0 += kUnroll) {
-    int c[kUnroll];
-    double v[kUnroll], xj[kUnroll];
-#pragma unroll
-    for (int j = 0; j < kUnroll; ++j)
-      if (k0 + j < width) {
-        c[j] = stream_load(cp + (k0 + j) * kWave);
-        v[j] = stream_load(vp + (k0 + j) * kWave);
-      }
-    if (D) {
-      float dj[kUnroll];
-#pragma unroll
-      for (int j = 0; j < kUnroll; ++j)
-        if (k0 + j < width) {
-          xj[j] = X[c[j]];
-          dj[j] = D[c[j]];
-        }
-#pragma unroll
-      for (int j = 0; j < kUnroll; ++j)
-        if (k0 + j < width) xj[j] = xj[j] + (double)dj[j];
-    } else {
-#pragma unroll
-      for (int j = 0; j < kUnroll; ++j)
-        if (k0 + j < width) xj[j] = X[c[j]];
-    }
-#pragma unroll
-    for (int j = 0; j < kUnroll; ++j)
-      if (k0 + j < width) acc = acc + v[j] * xj[j];
-  }
+  const double acc = so ? resid_row_sum<true>(cp, so, (int32_t)rr, vp, width, X, D)
+                        : resid_row_sum<false>(cp, so, (int32_t)rr, vp, width, X, D);
   if (live) {
     if (D) Xn[row] = xi0 + (double)di0;
     const double r = bi - acc;
