@@ -123,6 +123,16 @@ __device__ __forceinline__ T mat_load(const NAJ_GLOBAL T* p) {
 #endif
 }
 
+#define NAJ_CONST __attribute__((address_space(4)))
+
+// The column-offset list of slice s (see slice_offsets), or null for an ordinary slice.  The records
+// are written only when the system is created, so they are read through the scalar cache.
+__device__ __forceinline__ const NAJ_CONST int32_t* batch_offsets(const Sell& A, int64_t s) {
+  if (!A.soff) return nullptr;
+  const NAJ_CONST int32_t* r = (const NAJ_CONST int32_t*)(A.soff + s * kOffRec);
+  return r[0] ? r + 1 : nullptr;
+}
+
 // Element access at a byte offset from a buffer block: the buffer role of the lane's
 // instance times the buffer size, plus the element's offset.
 template <typename T>
@@ -173,7 +183,7 @@ __device__ __forceinline__ BatchSys uniform_sys(const BatchSys& g) {
   S.A.lcol = uni(g.A.lcol);
   S.A.lval = uni(g.A.lval);
   S.A.lval32 = uni(g.A.lval32);
-  S.A.soff = nullptr;   // batch passes load every column index
+  S.A.soff = uni(g.A.soff);
   S.dinv = uni(g.dinv);
   S.xb = uni(g.xb);
   S.fb = uni(g.fb);
@@ -242,6 +252,8 @@ __device__ __forceinline__ void unit_iter(const BatchSys& S, int64_t s, int sub,
   const double bi = ld_at((const double*)S.b, ei);
   const double di = S.dinv ? gptr(S.dinv)[u.rr] : 0.0;
   const NAJ_GLOBAL int32_t* cp = gptr(S.A.col) + base + u.rl;
+  const NAJ_CONST int32_t* so = batch_offsets(S.A, s);   // every row of such a slice is live
+  const int32_t rowc = (int32_t)u.rr;
   const NAJ_GLOBAL double* vp = gptr(S.A.val) + base + u.rl;
   double acc = 0.0, asum = 0.0;
   // U column steps: all loads issued before any is used; entries added in column order
@@ -249,12 +261,15 @@ __device__ __forceinline__ void unit_iter(const BatchSys& S, int64_t s, int sub,
     constexpr int U = decltype(U_)::value;
     int cr[U];
     double w[U], y[U];
+    if (so) {   // past the slice width: reuse the last column (cached), not added
 #pragma unroll
-    for (int q = 0; q < U; ++q) {   // past the slice width: reload the last column (cached), not added
-      const int kq = k0 + q < width ? k0 + q : width - 1;
-      cr[q] = mat_load(cp + kq * kWave);
-      w[q] = mat_load(vp + kq * kWave);
+      for (int q = 0; q < U; ++q) cr[q] = rowc + so[k0 + q < width ? k0 + q : width - 1];
+    } else {
+#pragma unroll
+      for (int q = 0; q < U; ++q) cr[q] = mat_load(cp + (k0 + q < width ? k0 + q : width - 1) * kWave);
     }
+#pragma unroll
+    for (int q = 0; q < U; ++q) w[q] = mat_load(vp + (k0 + q < width ? k0 + q : width - 1) * kWave);
     if (ym) {   // materialized form: y^t is P (bz) or R, one gathered vector
       const uint32_t oG = bz ? oP : oR;
 #pragma unroll
@@ -315,18 +330,23 @@ __device__ __forceinline__ void unit_inner(const BatchSys& S, int64_t s, int sub
   const float bi = ld_at(F, oB + ei);
   const double di = S.dinv ? gptr(S.dinv)[u.rr] : 0.0;
   const NAJ_GLOBAL int32_t* cp = gptr(S.A.col) + base + u.rl;
+  const NAJ_CONST int32_t* so = batch_offsets(S.A, s);   // every row of such a slice is live
+  const int32_t rowc = (int32_t)u.rr;
   const NAJ_GLOBAL float* vp = gptr(S.A.val32) + base + u.rl;
   float acc = 0.0f, asum = 0.0f;
   auto step = [&](auto U_, int k0) {
     constexpr int U = decltype(U_)::value;
     int cr[U];
     float w[U], y[U];
+    if (so) {   // past the slice width: reuse the last column (cached), not added
 #pragma unroll
-    for (int q = 0; q < U; ++q) {   // past the slice width: reload the last column (cached), not added
-      const int kq = k0 + q < width ? k0 + q : width - 1;
-      cr[q] = mat_load(cp + kq * kWave);
-      w[q] = mat_load(vp + kq * kWave);
+      for (int q = 0; q < U; ++q) cr[q] = rowc + so[k0 + q < width ? k0 + q : width - 1];
+    } else {
+#pragma unroll
+      for (int q = 0; q < U; ++q) cr[q] = mat_load(cp + (k0 + q < width ? k0 + q : width - 1) * kWave);
     }
+#pragma unroll
+    for (int q = 0; q < U; ++q) w[q] = mat_load(vp + (k0 + q < width ? k0 + q : width - 1) * kWave);
     if (ym) {
       const uint32_t oG = bz ? oP : oR;
 #pragma unroll
@@ -378,18 +398,23 @@ __device__ __forceinline__ void unit_resid(const BatchSys& S, int64_t s, int sub
   const int width = (int)((uni(gptr(S.A.slice_ptr)[s + 1]) - base) >> 6);
   const double bi = ld_at((const double*)S.b, elem<8>(u.rr, lk, j));
   const NAJ_GLOBAL int32_t* cp = gptr(S.A.col) + base + u.rl;
+  const NAJ_CONST int32_t* so = batch_offsets(S.A, s);   // every row of such a slice is live
+  const int32_t rowc = (int32_t)u.rr;
   const NAJ_GLOBAL double* vp = gptr(S.A.val) + base + u.rl;
   double acc = 0.0;
   auto step = [&](auto U_, int k0) {
     constexpr int U = decltype(U_)::value;
     int cr[U];
     double w[U], xj[U];
+    if (so) {   // past the slice width: reuse the last column (cached), not added
 #pragma unroll
-    for (int q = 0; q < U; ++q) {   // past the slice width: reload the last column (cached), not added
-      const int kq = k0 + q < width ? k0 + q : width - 1;
-      cr[q] = mat_load(cp + kq * kWave);
-      w[q] = mat_load(vp + kq * kWave);
+      for (int q = 0; q < U; ++q) cr[q] = rowc + so[k0 + q < width ? k0 + q : width - 1];
+    } else {
+#pragma unroll
+      for (int q = 0; q < U; ++q) cr[q] = mat_load(cp + (k0 + q < width ? k0 + q : width - 1) * kWave);
     }
+#pragma unroll
+    for (int q = 0; q < U; ++q) w[q] = mat_load(vp + (k0 + q < width ? k0 + q : width - 1) * kWave);
 #pragma unroll
     for (int q = 0; q < U; ++q) xj[q] = ld_at(X, oX + elem<8>(cr[q], lk, j));
 #pragma unroll
@@ -422,6 +447,8 @@ __device__ __forceinline__ void unit_resid_mixed(const BatchSys& S, int64_t s, i
   const double xi0 = ld_at(X, oX + 2u * e4);
   const float di0 = ld_at(F, oD + e4);
   const NAJ_GLOBAL int32_t* cp = gptr(S.A.col) + base + u.rl;
+  const NAJ_CONST int32_t* so = batch_offsets(S.A, s);   // every row of such a slice is live
+  const int32_t rowc = (int32_t)u.rr;
   const NAJ_GLOBAL double* vp = gptr(S.A.val) + base + u.rl;
   double acc = 0.0;
   auto step = [&](auto U_, int k0) {
@@ -429,12 +456,15 @@ __device__ __forceinline__ void unit_resid_mixed(const BatchSys& S, int64_t s, i
     int cr[U];
     double w[U], xj[U];
     float dj[U];
+    if (so) {   // past the slice width: reuse the last column (cached), not added
 #pragma unroll
-    for (int q = 0; q < U; ++q) {   // past the slice width: reload the last column (cached), not added
-      const int kq = k0 + q < width ? k0 + q : width - 1;
-      cr[q] = mat_load(cp + kq * kWave);
-      w[q] = mat_load(vp + kq * kWave);
+      for (int q = 0; q < U; ++q) cr[q] = rowc + so[k0 + q < width ? k0 + q : width - 1];
+    } else {
+#pragma unroll
+      for (int q = 0; q < U; ++q) cr[q] = mat_load(cp + (k0 + q < width ? k0 + q : width - 1) * kWave);
     }
+#pragma unroll
+    for (int q = 0; q < U; ++q) w[q] = mat_load(vp + (k0 + q < width ? k0 + q : width - 1) * kWave);
 #pragma unroll
     for (int q = 0; q < U; ++q) {
       const uint32_t o = elem<4>(cr[q], lk, j);
@@ -815,6 +845,8 @@ __device__ __forceinline__ void slice_inner_rows(const BatchSys& S, int64_t s, i
   ld_vec<G>(F, 4u * fs + eo, bi);
   const double di = S.dinv ? gptr(S.dinv)[rr] : 0.0;
   const NAJ_GLOBAL int32_t* cp = gptr(S.A.col) + base + lane;
+  const NAJ_CONST int32_t* so = batch_offsets(S.A, s);   // every row of such a slice is live
+  const int32_t rowc = (int32_t)rr;
   const NAJ_GLOBAL float* vp = gptr(S.A.val32) + base + lane;
   float acc[G];
 #pragma unroll
@@ -823,12 +855,15 @@ __device__ __forceinline__ void slice_inner_rows(const BatchSys& S, int64_t s, i
   for (int k0 = 0; k0 < width; k0 += kRowChunk) {
     int cr[kRowChunk];
     float w[kRowChunk];
+    if (so) {   // past the slice width: reuse the last column (cached), not added
 #pragma unroll
-    for (int u = 0; u < kRowChunk; ++u) {   // past the slice width: reload the last column (cached), not added
-      const int kq = k0 + u < width ? k0 + u : width - 1;
-      cr[u] = mat_load(cp + kq * kWave);
-      w[u] = mat_load(vp + kq * kWave);
+      for (int u = 0; u < kRowChunk; ++u) cr[u] = rowc + so[k0 + u < width ? k0 + u : width - 1];
+    } else {
+#pragma unroll
+      for (int u = 0; u < kRowChunk; ++u) cr[u] = mat_load(cp + (k0 + u < width ? k0 + u : width - 1) * kWave);
     }
+#pragma unroll
+    for (int u = 0; u < kRowChunk; ++u) w[u] = mat_load(vp + (k0 + u < width ? k0 + u : width - 1) * kWave);
 #pragma unroll
     for (int u0 = 0; u0 < kRowChunk; u0 += U) {
       if (k0 + u0 >= width) break;
@@ -990,6 +1025,8 @@ __device__ __forceinline__ void slice_inner_rows_ym(const BatchSys& S, int64_t s
   const int width = (int)((uni(gptr(S.A.slice_ptr)[s + 1]) - base) >> 6);
   const uint32_t eo = elem<4>(rr, lk, (uint32_t)j0);
   const NAJ_GLOBAL int32_t* cp = gptr(S.A.col) + base + lane;
+  const NAJ_CONST int32_t* so = batch_offsets(S.A, s);   // every row of such a slice is live
+  const int32_t rowc = (int32_t)rr;
   const NAJ_GLOBAL float* vp = gptr(S.A.val32) + base + lane;
   float acc[G];
 #pragma unroll
@@ -998,12 +1035,15 @@ __device__ __forceinline__ void slice_inner_rows_ym(const BatchSys& S, int64_t s
   for (int k0 = 0; k0 < width; k0 += kRowChunk) {
     int cr[kRowChunk];
     float w[kRowChunk];
+    if (so) {   // past the slice width: reuse the last column (cached), not added
 #pragma unroll
-    for (int u = 0; u < kRowChunk; ++u) {   // past the slice width: reload the last column (cached), not added
-      const int kq = k0 + u < width ? k0 + u : width - 1;
-      cr[u] = mat_load(cp + kq * kWave);
-      w[u] = mat_load(vp + kq * kWave);
+      for (int u = 0; u < kRowChunk; ++u) cr[u] = rowc + so[k0 + u < width ? k0 + u : width - 1];
+    } else {
+#pragma unroll
+      for (int u = 0; u < kRowChunk; ++u) cr[u] = mat_load(cp + (k0 + u < width ? k0 + u : width - 1) * kWave);
     }
+#pragma unroll
+    for (int u = 0; u < kRowChunk; ++u) w[u] = mat_load(vp + (k0 + u < width ? k0 + u : width - 1) * kWave);
 #pragma unroll
     for (int u0 = 0; u0 < kRowChunk; u0 += U) {
       if (k0 + u0 >= width) break;
