@@ -123,16 +123,6 @@ __device__ __forceinline__ T mat_load(const NAJ_GLOBAL T* p) {
 #endif
 }
 
-#define NAJ_CONST __attribute__((address_space(4)))
-
-// The column-offset list of slice s (see slice_offsets), or null for an ordinary slice.  The records
-// are written only when the system is created, so they are read through the scalar cache.
-__device__ __forceinline__ const NAJ_CONST int32_t* batch_offsets(const Sell& A, int64_t s) {
-  if (!A.soff) return nullptr;
-  const NAJ_CONST int32_t* r = (const NAJ_CONST int32_t*)(A.soff + s * kOffRec);
-  return r[0] ? r + 1 : nullptr;
-}
-
 // Element access at a byte offset from a buffer block: the buffer role of the lane's
 // instance times the buffer size, plus the element's offset.
 template <typename T>
@@ -252,7 +242,7 @@ __device__ __forceinline__ void unit_iter(const BatchSys& S, int64_t s, int sub,
   const double bi = ld_at((const double*)S.b, ei);
   const double di = S.dinv ? gptr(S.dinv)[u.rr] : 0.0;
   const NAJ_GLOBAL int32_t* cp = gptr(S.A.col) + base + u.rl;
-  const NAJ_CONST int32_t* so = batch_offsets(S.A, s);   // every row of such a slice is live
+  const OffPtr so = slice_offsets(S.A, s);   // every row of such a slice is live
   const int32_t rowc = (int32_t)u.rr;
   const NAJ_GLOBAL double* vp = gptr(S.A.val) + base + u.rl;
   double acc = 0.0, asum = 0.0;
@@ -330,7 +320,7 @@ __device__ __forceinline__ void unit_inner(const BatchSys& S, int64_t s, int sub
   const float bi = ld_at(F, oB + ei);
   const double di = S.dinv ? gptr(S.dinv)[u.rr] : 0.0;
   const NAJ_GLOBAL int32_t* cp = gptr(S.A.col) + base + u.rl;
-  const NAJ_CONST int32_t* so = batch_offsets(S.A, s);   // every row of such a slice is live
+  const OffPtr so = slice_offsets(S.A, s);   // every row of such a slice is live
   const int32_t rowc = (int32_t)u.rr;
   const NAJ_GLOBAL float* vp = gptr(S.A.val32) + base + u.rl;
   float acc = 0.0f, asum = 0.0f;
@@ -398,7 +388,7 @@ __device__ __forceinline__ void unit_resid(const BatchSys& S, int64_t s, int sub
   const int width = (int)((uni(gptr(S.A.slice_ptr)[s + 1]) - base) >> 6);
   const double bi = ld_at((const double*)S.b, elem<8>(u.rr, lk, j));
   const NAJ_GLOBAL int32_t* cp = gptr(S.A.col) + base + u.rl;
-  const NAJ_CONST int32_t* so = batch_offsets(S.A, s);   // every row of such a slice is live
+  const OffPtr so = slice_offsets(S.A, s);   // every row of such a slice is live
   const int32_t rowc = (int32_t)u.rr;
   const NAJ_GLOBAL double* vp = gptr(S.A.val) + base + u.rl;
   double acc = 0.0;
@@ -447,7 +437,7 @@ __device__ __forceinline__ void unit_resid_mixed(const BatchSys& S, int64_t s, i
   const double xi0 = ld_at(X, oX + 2u * e4);
   const float di0 = ld_at(F, oD + e4);
   const NAJ_GLOBAL int32_t* cp = gptr(S.A.col) + base + u.rl;
-  const NAJ_CONST int32_t* so = batch_offsets(S.A, s);   // every row of such a slice is live
+  const OffPtr so = slice_offsets(S.A, s);   // every row of such a slice is live
   const int32_t rowc = (int32_t)u.rr;
   const NAJ_GLOBAL double* vp = gptr(S.A.val) + base + u.rl;
   double acc = 0.0;
@@ -845,7 +835,7 @@ __device__ __forceinline__ void slice_inner_rows(const BatchSys& S, int64_t s, i
   ld_vec<G>(F, 4u * fs + eo, bi);
   const double di = S.dinv ? gptr(S.dinv)[rr] : 0.0;
   const NAJ_GLOBAL int32_t* cp = gptr(S.A.col) + base + lane;
-  const NAJ_CONST int32_t* so = batch_offsets(S.A, s);   // every row of such a slice is live
+  const OffPtr so = slice_offsets(S.A, s);   // every row of such a slice is live
   const int32_t rowc = (int32_t)rr;
   const NAJ_GLOBAL float* vp = gptr(S.A.val32) + base + lane;
   float acc[G];
@@ -1025,7 +1015,7 @@ __device__ __forceinline__ void slice_inner_rows_ym(const BatchSys& S, int64_t s
   const int width = (int)((uni(gptr(S.A.slice_ptr)[s + 1]) - base) >> 6);
   const uint32_t eo = elem<4>(rr, lk, (uint32_t)j0);
   const NAJ_GLOBAL int32_t* cp = gptr(S.A.col) + base + lane;
-  const NAJ_CONST int32_t* so = batch_offsets(S.A, s);   // every row of such a slice is live
+  const OffPtr so = slice_offsets(S.A, s);   // every row of such a slice is live
   const int32_t rowc = (int32_t)rr;
   const NAJ_GLOBAL float* vp = gptr(S.A.val32) + base + lane;
   float acc[G];

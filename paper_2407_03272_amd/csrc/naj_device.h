@@ -126,16 +126,20 @@ struct Sell {
 // [1 .. |S|].  The col array is filled either way, so code that loads columns reads the same values.
 constexpr int kOffRec = 16;
 
-__device__ __forceinline__ const int32_t* slice_offsets(const Sell& A, int64_t s) {
+// The records are written only when the system is created, so they are read through the scalar
+// cache (constant address space): one scalar load per offset for the whole wavefront.
+#define NAJ_CONST __attribute__((address_space(4)))
+using OffPtr = const NAJ_CONST int32_t*;
+
+__device__ __forceinline__ OffPtr slice_offsets(const Sell& A, int64_t s) {
   if (!A.soff) return nullptr;
-  const int32_t* r = A.soff + s * kOffRec;
+  const OffPtr r = (OffPtr)(A.soff + s * kOffRec);
   return r[0] ? r + 1 : nullptr;
 }
 
 // Column index of column step k of a slice's lane: formed from the slice's offsets (OFF) or loaded.
 template <bool OFF>
-__device__ __forceinline__ int slice_col(const int32_t* __restrict__ cp, const int32_t* __restrict__ so, int32_t row,
-                                         int k) {
+__device__ __forceinline__ int slice_col(const int32_t* __restrict__ cp, OffPtr so, int32_t row, int k) {
   if constexpr (OFF)
     return row + so[k];
   else
@@ -271,7 +275,7 @@ __device__ __forceinline__ T abs_of(T v) {
 // y = R (materialized form), y = P (bz) or y = 0 (zy).  OFF: the slice's columns come from its
 // offsets.  The two column sources are separate instances so each keeps its own register budget.
 template <bool OFF, bool YM, typename T>
-__device__ __forceinline__ void fused_row_sums(const int32_t* __restrict__ cp, const int32_t* __restrict__ so,
+__device__ __forceinline__ void fused_row_sums(const int32_t* __restrict__ cp, OffPtr so,
                                                int32_t row, const T* __restrict__ vp, int width,
                                                const T* __restrict__ P, const T* __restrict__ R, T beta, bool bz,
                                                bool zy, T& acc, T& asum) {
@@ -319,7 +323,7 @@ __device__ __forceinline__ void fused_row_sums(const int32_t* __restrict__ cp, c
 // One lane's sum_k v_k x_{c_k} over its slice (OFF as above); with D, x = X + (double)D at every
 // gathered column.
 template <bool OFF>
-__device__ __forceinline__ double resid_row_sum(const int32_t* __restrict__ cp, const int32_t* __restrict__ so,
+__device__ __forceinline__ double resid_row_sum(const int32_t* __restrict__ cp, OffPtr so,
                                                 int32_t row, const double* __restrict__ vp, int width,
                                                 const double* __restrict__ X, const float* __restrict__ D) {
   double acc = 0.0;
@@ -376,7 +380,7 @@ __device__ __forceinline__ void iter_slice(const SolveArgs& a, int64_t s, int la
   const double bi = a.b[rr];
   const double di = (JM == 1) ? a.dinv[rr] : 0.0;
   const int32_t* __restrict__ cp = a.A.col + base + lane;
-  const int32_t* __restrict__ so = slice_offsets(a.A, s);
+  const OffPtr so = slice_offsets(a.A, s);
   const double* __restrict__ vp = a.A.val + base + lane;
   double acc = 0.0, asum = 0.0;
   if (so)
@@ -412,7 +416,7 @@ __device__ __forceinline__ void resid_slice(const Sell& A, int64_t s, int lane, 
   const bool live = row < A.n;
   const double bi = b[live ? row : 0];
   const int32_t* __restrict__ cp = A.col + base + lane;
-  const int32_t* __restrict__ so = slice_offsets(A, s);
+  const OffPtr so = slice_offsets(A, s);
   const double* __restrict__ vp = A.val + base + lane;
   const int32_t rw = (int32_t)(live ? row : 0);
   const double acc = so ? resid_row_sum<true>(cp, so, rw, vp, width, X, nullptr)
@@ -446,7 +450,7 @@ __device__ __forceinline__ void inner_slice(const SolveArgs& a, int64_t s, int l
   const float bi = a.r32[rr];
   const double di = (JM == 1) ? a.dinv[rr] : 0.0;
   const int32_t* __restrict__ cp = a.A.col + base + lane;
-  const int32_t* __restrict__ so = slice_offsets(a.A, s);
+  const OffPtr so = slice_offsets(a.A, s);
   const float* __restrict__ vp = a.A.val32 + base + lane;
   float acc = 0.0f, asum = 0.0f;
   if (so)
@@ -487,7 +491,7 @@ __device__ __forceinline__ void resid_mixed_slice(const SolveArgs& a, int64_t s,
   const double xi0 = X[rr];
   const float di0 = D ? D[rr] : 0.0f;
   const int32_t* __restrict__ cp = a.A.col + base + lane;
-  const int32_t* __restrict__ so = slice_offsets(a.A, s);
+  const OffPtr so = slice_offsets(a.A, s);
   const double* __restrict__ vp = a.A.val + base + lane;
   const double acc = so ? resid_row_sum<true>(cp, so, (int32_t)rr, vp, width, X, D)
                         : resid_row_sum<false>(cp, so, (int32_t)rr, vp, width, X, D);
