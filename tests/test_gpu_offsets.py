@@ -78,8 +78,8 @@ def test_poisson3d_offset_form_per_pass_driver(naj, monkeypatch):
     on, off = _pair(naj, monkeypatch, s.rowptr, s.colidx, s.vals)
     ns = on.info()["nslices"]
     assert ns - 2 * (1600 // 64 + 1) <= on.info()["offset_slices"] < ns
-    monkeypatch.setenv("NAJ_MODE", "1")
     x, info = _same_solve(on, off, s.b, tol=1e-8, max_iter=20000)
+    assert info.grid > 1   # the per-pass driver: the one this size gets at creation
     orc = O.accelerated_jacobi(s.rowptr, s.colidx, s.vals, s.b, tol=1e-8, max_iter=20000)
     if info.restart_log == orc.restarts:
         assert info.iterations == orc.iterations and np.array_equal(x, orc.x)
@@ -91,7 +91,6 @@ def test_poisson3d_offset_form_per_pass_driver(naj, monkeypatch):
     Q = O.csr(s.rowptr, s.colidx, s.vals)
     fstar = -0.5 * float(s.b @ orc.x)
     _same_solve(on, off, s.b, tol=1e-9, stop=naj.NAJ_STOP_OBJECTIVE, fstar=fstar, max_iter=20000)
-    monkeypatch.delenv("NAJ_MODE")
     rng = np.random.default_rng(5)
     p, r = rng.standard_normal(s.n), rng.standard_normal(s.n)
     xg, (s_, gg, sabs) = on.step(p, r, 0.3, s.b)
