@@ -28,9 +28,41 @@ def _say(*a):
     print("[gpu-case]", *a, flush=True)
 
 
+def _expected_offset_slices(rowptr, colidx):
+    """The qualification rule restated on the host: a full slice of 64 rows whose rows have strictly
+    increasing columns, whose offsets (column - row) have at most 15 distinct values, no more than the
+    slice's longest row, and with row + offset inside [0, n) for every row and offset of the union."""
+    rowptr = np.asarray(rowptr, np.int64)
+    colidx = np.asarray(colidx, np.int64)
+    n = len(rowptr) - 1
+    count = nnz = 0
+    for s in range(n // 64):
+        r0, r1 = 64 * s, 64 * s + 64
+        rows = np.repeat(np.arange(r0, r1), np.diff(rowptr[r0:r1 + 1]))
+        cols = colidx[rowptr[r0]:rowptr[r1]]
+        offs = cols - rows
+        same_row = rows[1:] == rows[:-1]
+        if np.any(cols[1:][same_row] <= cols[:-1][same_row]):
+            continue
+        u = np.unique(offs)
+        w = int(np.diff(rowptr[r0:r1 + 1]).max())
+        if len(u) == 0 or len(u) > 15 or len(u) > w or r0 + u[0] < 0 or r1 - 1 + u[-1] >= n:
+            continue
+        count += 1
+        nnz += int(rowptr[r1] - rowptr[r0])
+    return count, nnz
+
+
+def _check_count(sysm, rowptr, colidx):
+    c, z = _expected_offset_slices(rowptr, colidx)
+    info = sysm.info()
+    assert (info["offset_slices"], info["offset_nnz"]) == (c, z)
+
+
 def _pair(naj, monkeypatch, rowptr, colidx, vals):
     """The system with the offset form (default) and without it."""
     on = naj.System(rowptr, colidx, vals)
+    _check_count(on, rowptr, colidx)
     monkeypatch.setenv("NAJ_OFFSETS", "0")
     off = naj.System(rowptr, colidx, vals)
     monkeypatch.delenv("NAJ_OFFSETS")
@@ -125,10 +157,16 @@ def test_unsorted_row_keeps_its_slice_ordinary(naj, monkeypatch):
 
 
 def test_no_pattern_no_offset_slices(naj):
-    """Random sparsity has no common offsets; the sorted layout never uses the form."""
-    _say("offset form absent")
+    """Random sparsity has no common offsets; the sorted layout never uses the form; finite-element
+    systems on jittered grids get the slices the host rule predicts."""
+    _say("offset form absent / FE")
     rowptr, colidx, vals = W.random_spd(1000, 0.02, 5)
     assert naj.System(rowptr, colidx, vals).info()["offset_slices"] == 0
+    for x in W.fe_batch(6, nrhs=1, workers=1):
+        sm = naj.System(x.rowptr, x.colidx, x.vals)
+        _check_count(sm, x.rowptr, x.colidx)
+        assert sm.info()["offset_slices"] > 0
+        sm.close()
     c = W.chung_lu_laplacian(1 << 13, 16, 2.5, seed=46, b_seed=47)
     i = naj.System(c.rowptr, c.colidx, c.vals).info()
     assert i["layout"] == 1 and i["offset_slices"] == 0
