@@ -7,7 +7,9 @@
 // step is one contiguous 256 B (indices) / 512 B (float64 values) access.
 // Each row keeps its CSR order, so a lane's running sum adds the products in
 // the same order as a row-by-row CSR product.  Padding entries have value 0
-// and point at the row itself (always a valid, cache-hot address).
+// and point at the row itself (always a valid, cache-hot address); in a slice
+// of the column-offset form (below) they sit between a row's entries instead,
+// at the offsets the row lacks, which adds zeros in the same order.
 //
 // All float arithmetic is compiled without contraction, so every product,
 // sum and quotient is a separately rounded IEEE operation.
