@@ -168,9 +168,9 @@ def bench_fe_batch(args, progress):
         total = time.perf_counter() - t_all
         info = bt.info()
         bt.close()
-        return total, times, kms, infos, info
+        return total, times, kms, infos, info, outs
 
-    total, times, kms, infos, binfo = run_batch(prec, args.steps, args.warmup)
+    total, times, kms, infos, binfo, xs_main = run_batch(prec, args.steps, args.warmup)
     ninst = len(infos)
     progress(f"batch: {total / args.steps * 1e3:.1f} ms per {ninst} solves")
     # algorithmic bytes: matrix once per system pass, vectors per instance pass
@@ -216,10 +216,19 @@ def bench_fe_batch(args, progress):
     }
     if not args.no_compare:
         other = naj.NAJ_FP64 if prec == naj.NAJ_MIXED else naj.NAJ_MIXED
-        ctot, ctimes, ckms, cinfos, _ = run_batch(other, max(2, args.steps // 2), 1)
+        ctot, ctimes, ckms, cinfos, _, xs_other = run_batch(other, max(2, args.steps // 2), 1)
+        # every instance's mixed answer against its float64 answer (both to relres 1e-8)
+        errs = []
+        for a, c in zip(xs_main, xs_other):
+            d = torch.linalg.vector_norm((a - c).reshape(a.shape[0], -1), dim=0)
+            errs.append((d / torch.linalg.vector_norm(c.reshape(c.shape[0], -1), dim=0)).cpu().numpy())
+        errs = np.concatenate(errs)
         line["compare_batch"] = {"precision": "fp64" if other == naj.NAJ_FP64 else "mixed",
                                  "solves_per_s": ninst * len(ctimes) / ctot,
-                                 "ms_per_batch": ctot / len(ctimes) * 1e3}
+                                 "ms_per_batch": ctot / len(ctimes) * 1e3,
+                                 "rel_err_mixed_vs_fp64": {"instances": int(errs.size),
+                                                           "median": float(np.median(errs)),
+                                                           "max": float(np.max(errs))}}
         progress("batch comparison done")
         # plain float64, one system and one right-hand side at a time (every 16th system, all 8 rhs)
         sample = list(range(0, len(systems), 16))
@@ -312,7 +321,7 @@ def run_server(naj, reqs, budget, slots, closed_loop, progress, label):
         if np.linalg.norm(b - Q @ xh) / np.linalg.norm(b) > reqs[i]["tol"]:
             bad += 1
     progress(f"{label}: {len(kept)} sampled answers checked")
-    return lat, makespan, busy_max, bad
+    return lat, makespan, busy_max, bad, dict(kept)
 
 
 def bench_serve(args, progress):
@@ -326,7 +335,7 @@ def bench_serve(args, progress):
              f"{sum(r['fe'] for r in reqs)} finite-element, {sum(not r['fe'] for r in reqs)} Laplacians")
     budget = int(args.serve_budget_mb) << 20
     # open loop at the trace's arrival times
-    lat, span, qmax, bad = run_server(naj, reqs, budget, args.serve_slots, False, progress, "open loop")
+    lat, span, qmax, bad, served = run_server(naj, reqs, budget, args.serve_slots, False, progress, "open loop")
     if bad:
         raise SystemExit(f"serve: {bad} requests did not converge or missed their tolerance")
     L = lat[warm:] * 1e3
@@ -335,7 +344,7 @@ def bench_serve(args, progress):
     progress(f"open loop: p50 {np.percentile(L, 50):.1f} ms, p99 {np.percentile(L, 99):.1f} ms, "
              f"{achieved:.1f} solves/s")
     # closed loop: every request queued at t = 0 (saturation throughput)
-    clat, cspan, _, cbad = run_server(naj, reqs, budget, args.serve_slots, True, progress, "closed loop")
+    clat, cspan, _, cbad, _ = run_server(naj, reqs, budget, args.serve_slots, True, progress, "closed loop")
     if cbad:
         raise SystemExit(f"serve (closed loop): {cbad} requests did not converge or missed their tolerance")
     sat = nreq / cspan
@@ -360,8 +369,8 @@ def bench_serve(args, progress):
         "roofline": None,
     }
     if args.serve_small_budget_mb:
-        slat, sspan, sq, sbad = run_server(naj, reqs, int(args.serve_small_budget_mb) << 20, args.serve_slots, False,
-                                           progress, "small budget")
+        slat, sspan, sq, sbad, _ = run_server(naj, reqs, int(args.serve_small_budget_mb) << 20, args.serve_slots,
+                                              False, progress, "small budget")
         if sbad:
             raise SystemExit(f"serve (small budget): {sbad} requests did not converge or missed their tolerance")
         S = slat[warm:] * 1e3
@@ -370,17 +379,24 @@ def bench_serve(args, progress):
                                "solves_per_s": (nreq - warm) / (sspan - first)}
     if not args.no_compare:
         # plain float64, one request at a time (a sample of the trace, system built per request as in serving)
-        sample = reqs[warm: warm + args.serve_fp64_sample]
+        sample = range(warm, min(nreq, warm + args.serve_fp64_sample))
+        errs = []
         t0 = time.perf_counter()
-        for r in sample:
+        for i in sample:
+            r = reqs[i]
             s = r["sys"]
             sm = naj.System(s.rowptr, s.colidx, s.vals)
             x, inf = sm.solve(r["b"], tol=r["tol"], max_iter=20000, hist_cap=0)
-            xh = x.cpu()
+            xh = x.cpu().numpy()
             sm.close()
+            if i in served:   # the served (mixed) answer against this float64 answer to the same tolerance
+                errs.append(float(np.linalg.norm(served[i] - xh) / np.linalg.norm(xh)))
         dt = time.perf_counter() - t0
         out["compare_one_at_a_time"] = {"precision": "fp64", "sampled_requests": len(sample), "seconds": dt,
-                                        "solves_per_s": len(sample) / dt}
+                                        "solves_per_s": len(sample) / dt,
+                                        "rel_err_served_vs_fp64": {"requests": len(errs),
+                                                                   "median": float(np.median(errs)) if errs else None,
+                                                                   "max": float(np.max(errs)) if errs else None}}
         progress(f"float64 one at a time: {len(sample) / dt:.1f} solves/s")
     return out
 
@@ -458,6 +474,7 @@ def main():
     b = torch.as_tensor(sysobj.b).to(dev)
     x = torch.empty(n, dtype=torch.float64, device=dev)
     mixed = args.precision == "mixed"
+    singular = args.workload.startswith("chunglu")   # graph Laplacians: answers are defined up to the null space
 
     def timed(mixed_: bool, steps: int, warmup: int):
         opts = dict(tol=tol, max_iter=20000, precision=naj.NAJ_MIXED if mixed_ else naj.NAJ_FP64,
@@ -481,6 +498,7 @@ def main():
 
     progress("system created")
     total, lat, kms, infos = timed(mixed, args.steps, args.warmup)
+    x_main = x.clone()
     progress(f"timed {args.steps} solves: {total / args.steps * 1e3:.2f} ms each")
     info = infos[-1]
     sinfo = sysm.info()
@@ -536,10 +554,15 @@ def main():
         # the same system solved in the other precision, for the mixed-vs-FP64 comparison
         ctot, clat, ckms, cinfos = timed(not mixed, max(3, args.steps // 2), 1)
         ci = cinfos[-1]
+        # the mixed answer against the float64 one (which equals the oracle's in the parity tests); a singular
+        # system's answers may differ by a null-space component, so none is stated there
+        xm, xf = (x_main, x) if mixed else (x, x_main)
+        rel_err = None if singular else float(torch.linalg.vector_norm(xm - xf) / torch.linalg.vector_norm(xf))
         line["compare"] = {"precision": "fp64" if mixed else "mixed", "solves_per_s": len(clat) / ctot,
                            "p50_ms": float(np.percentile(clat, 50) * 1e3),
                            "p99_ms": float(np.percentile(clat, 99) * 1e3),
                            "iterations": ci.iterations, "confirmations": ci.confirmations, "relres": ci.relres,
+                           "rel_err_mixed_vs_fp64": rel_err,
                            "gbps_solve": solve_bytes(n, nnz, ci, not mixed, jb, nnz_off) / (float(np.mean(ckms)) / 1e3) / 1e9}
     it = info.iterations
     if not args.no_cpu_baseline:
