@@ -56,10 +56,11 @@ def measured_traffic(workload: str):
 
 def bytes_per_iteration(n: int, nnz: int, s_v: int = 8, s_x: int = 8, k: int = 1, jb: int = 0,
                         nnz_off: int = 0) -> int:
-    """Algorithmic bytes of one fused pass: matrix values, int32 column indices (none for the nnz_off
-    nonzeros of slices in the column-offset form, whose columns follow from the slice's offset list),
-    int32 row pointers, and four vector streams (read x^{t-1}, read y^t / x^{t-2}, read b, write x^t);
-    with a block J of jb-row blocks, each row also reads its row of the block's inverse (jb values)."""
+    """Algorithmic bytes of one fused pass, CSR int32 yardstick: values + int32 columns, int32 row pointers,
+    and four vector streams (read x^{t-1}, read y^t / x^{t-2}, read b, write x^t); with a block J of jb-row
+    blocks, each row also reads its row of the block's inverse (jb values).  With nnz_off > 0: the bytes the
+    layout itself moves, without the column indices of the nnz_off nonzeros held in column-offset slices
+    (their columns follow from the slice's offset list)."""
     return s_v * nnz + 4 * (nnz - nnz_off) + 4 * (n + 1) + 4 * k * s_x * n + jb * s_x * n
 
 
@@ -75,7 +76,8 @@ def bytes_per_refinement_residual(n: int, nnz: int, nnz_off: int = 0) -> int:
 
 
 def solve_bytes(n: int, nnz: int, info, mixed: bool, jb: int = 0, nnz_off: int = 0) -> int:
-    """Algorithmic bytes of a whole solve from its pass counts (norm of b = 8n bytes)."""
+    """Bytes of a whole solve from its pass counts (norm of b = 8n bytes): the CSR yardstick, or with
+    nnz_off the bytes the layout moves."""
     if not mixed:
         it = info.iterations
         conf = info.passes - it - 1
@@ -503,16 +505,19 @@ def main():
     info = infos[-1]
     sinfo = sysm.info()
     nnz_off = sinfo["offset_nnz"]
-    alg_bytes = solve_bytes(n, nnz, info, mixed, jb, nnz_off)
+    alg_bytes = solve_bytes(n, nnz, info, mixed, jb)                  # CSR int32 yardstick
+    moved_bytes = solve_bytes(n, nnz, info, mixed, jb, nnz_off)      # what the layout reads and writes
     kernel_s = float(np.mean(kms)) / 1e3
     achieved = alg_bytes / kernel_s / 1e9
     solves_s = args.steps / total
     if mixed:
-        per_launch = bytes_per_iteration(n, nnz, s_v=4, s_x=4, jb=jb, nnz_off=nnz_off)
+        per_launch = bytes_per_iteration(n, nnz, s_v=4, s_x=4, jb=jb)
+        moved_launch = bytes_per_iteration(n, nnz, s_v=4, s_x=4, jb=jb, nnz_off=nnz_off)
         wl = (f"{sysobj.name}: n={n}, nnz={nnz}; float32 inner accelerated Jacobi with float64 reductions inside "
               f"float64 iterative refinement, x0=0, restart on, K0=2, inner tol 1e-4, final relres <= 1e-8, single solve")
     else:
-        per_launch = bytes_per_iteration(n, nnz, jb=jb, nnz_off=nnz_off)
+        per_launch = bytes_per_iteration(n, nnz, jb=jb)
+        moved_launch = bytes_per_iteration(n, nnz, jb=jb, nnz_off=nnz_off)
         wl = (f"{sysobj.name}: n={n}, nnz={nnz}, float64, x0=0, restart on, K0=2, tol 1e-8, single solve "
               f"(plain FP64 one system at a time)")
     if jb:
@@ -548,6 +553,9 @@ def main():
                      "kernel": "k_pass64 (fused iteration pass, one launch per pass)",
                      "launches_per_solve": info.passes,
                      "algorithmic_bytes_per_launch": per_launch,
+                     "layout_bytes_per_launch": moved_launch,
+                     "layout_gbps": moved_bytes / kernel_s / 1e9,
+                     "layout_frac": moved_bytes / kernel_s / 1e9 / HBM_PEAK_GBS,
                      "mean_launch_us": kernel_s / info.passes * 1e6},
     }
     if not args.no_compare:
@@ -563,7 +571,7 @@ def main():
                            "p99_ms": float(np.percentile(clat, 99) * 1e3),
                            "iterations": ci.iterations, "confirmations": ci.confirmations, "relres": ci.relres,
                            "rel_err_mixed_vs_fp64": rel_err,
-                           "gbps_solve": solve_bytes(n, nnz, ci, not mixed, jb, nnz_off) / (float(np.mean(ckms)) / 1e3) / 1e9}
+                           "gbps_solve": solve_bytes(n, nnz, ci, not mixed, jb) / (float(np.mean(ckms)) / 1e3) / 1e9}
     it = info.iterations
     if not args.no_cpu_baseline:
         progress("cpu baseline")
