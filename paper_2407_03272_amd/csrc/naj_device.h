@@ -41,6 +41,17 @@ __device__ __forceinline__ T stream_load(const T* p) {
 #endif
 }
 
+// Matrix loads of the float64 iteration pass: non-temporal (NT) for systems whose pass does not fit the
+// 256 MB MALL, so the streamed entries do not evict the gathered vectors; ordinary loads otherwise
+// (the whole pass then stays in the MALL from one pass to the next).
+template <bool NT, typename T>
+__device__ __forceinline__ T mat_ld(const T* p) {
+  if constexpr (NT)
+    return __builtin_nontemporal_load(p);
+  else
+    return stream_load(p);
+}
+
 // PH_RESID64 and PH_INNER32 belong to the mixed-precision refinement loop.
 enum Phase : int { PH_NORMB = 0, PH_ITER = 1, PH_CONFIRM = 2, PH_DONE = 3, PH_RESID64 = 4, PH_INNER32 = 5 };
 
@@ -140,12 +151,12 @@ __device__ __forceinline__ OffPtr slice_offsets(const Sell& A, int64_t s) {
 }
 
 // Column index of column step k of a slice's lane: formed from the slice's offsets (OFF) or loaded.
-template <bool OFF>
+template <bool OFF, bool NT = false>
 __device__ __forceinline__ int slice_col(const int32_t* __restrict__ cp, OffPtr so, int32_t row, int k) {
   if constexpr (OFF)
     return row + so[k];
   else
-    return stream_load(cp + k * kWave);
+    return mat_ld<NT>(cp + k * kWave);
 }
 
 // Which J a pass applies (template parameter JM of the pass functions):
@@ -276,7 +287,7 @@ __device__ __forceinline__ T abs_of(T v) {
 // acc = sum_k v_k y_{c_k} and asum = sum_k |v_k|, with y = P + beta (P - R) (two-iterate form),
 // y = R (materialized form), y = P (bz) or y = 0 (zy).  OFF: the slice's columns come from its
 // offsets.  The two column sources are separate instances so each keeps its own register budget.
-template <bool OFF, bool YM, typename T>
+template <bool OFF, bool YM, bool NT, typename T>
 __device__ __forceinline__ void fused_row_sums(const int32_t* __restrict__ cp, OffPtr so,
                                                int32_t row, const T* __restrict__ vp, int width,
                                                const T* __restrict__ P, const T* __restrict__ R, T beta, bool bz,
@@ -287,8 +298,8 @@ __device__ __forceinline__ void fused_row_sums(const int32_t* __restrict__ cp, O
 #pragma unroll
     for (int j = 0; j < kUnroll; ++j)
       if (k0 + j < width) {
-        c[j] = slice_col<OFF>(cp, so, row, k0 + j);
-        v[j] = stream_load(vp + (k0 + j) * kWave);
+        c[j] = slice_col<OFF, NT>(cp, so, row, k0 + j);
+        v[j] = mat_ld<NT>(vp + (k0 + j) * kWave);
       }
     if (zy) {
 #pragma unroll
@@ -363,7 +374,7 @@ __device__ __forceinline__ double resid_row_sum(const int32_t* __restrict__ cp, 
 
 // One slice of the fused pass: u = Q y, g = u - b, x = y - J^{-1} g, d = x - P,
 // with y = P + beta (P - R) formed at every gathered column (y = P when bz).
-template <int JM, bool YM>
+template <int JM, bool YM, bool NT = false>
 __device__ __forceinline__ void iter_slice(const SolveArgs& a, int64_t s, int lane, const double* __restrict__ P,
                                            const Momentum<double>& m, double* __restrict__ W, double& ps, double& pgg,
                                            double& psabs) {
@@ -386,9 +397,9 @@ __device__ __forceinline__ void iter_slice(const SolveArgs& a, int64_t s, int la
   const double* __restrict__ vp = a.A.val + base + lane;
   double acc = 0.0, asum = 0.0;
   if (so)
-    fused_row_sums<true, YM>(cp, so, (int32_t)rr, vp, width, P, R, beta, bz, false, acc, asum);
+    fused_row_sums<true, YM, NT>(cp, so, (int32_t)rr, vp, width, P, R, beta, bz, false, acc, asum);
   else
-    fused_row_sums<false, YM>(cp, so, (int32_t)rr, vp, width, P, R, beta, bz, false, acc, asum);
+    fused_row_sums<false, YM, NT>(cp, so, (int32_t)rr, vp, width, P, R, beta, bz, false, acc, asum);
   double z = 0.0;
   if constexpr (JM == kJBlock) z = block_apply(a.jinv, s, lane, a.jblock, live ? acc - bi : 0.0);
   if (live) {
@@ -456,9 +467,9 @@ __device__ __forceinline__ void inner_slice(const SolveArgs& a, int64_t s, int l
   const float* __restrict__ vp = a.A.val32 + base + lane;
   float acc = 0.0f, asum = 0.0f;
   if (so)
-    fused_row_sums<true, YM>(cp, so, (int32_t)rr, vp, width, P, R, beta, bz, zp, acc, asum);
+    fused_row_sums<true, YM, false>(cp, so, (int32_t)rr, vp, width, P, R, beta, bz, zp, acc, asum);
   else
-    fused_row_sums<false, YM>(cp, so, (int32_t)rr, vp, width, P, R, beta, bz, zp, acc, asum);
+    fused_row_sums<false, YM, false>(cp, so, (int32_t)rr, vp, width, P, R, beta, bz, zp, acc, asum);
   float z = 0.0f;
   if constexpr (JM == kJBlock) z = block_apply(a.jinv32, s, lane, a.jblock, live ? acc - bi : 0.0f);
   if (live) {

@@ -337,7 +337,7 @@ __device__ __forceinline__ void load_view(const Ctrl* c, PassView* v) {
 // The workgroup's share of one float64 iteration pass (long rows, then slices).  YM: the
 // materialized momentum form (a compile-time choice, so the two-iterate kernel carries none
 // of the materialized form's code).
-template <int JM, int BS, bool YM>
+template <int JM, int BS, bool YM, bool NT = false>
 __device__ __forceinline__ void pass_iter64(const SolveArgs& a, const double* P, const Momentum<double>& m, double* W,
                                             double& p0, double& p1, double& p2) {
   const int lane = threadIdx.x % kWave;
@@ -345,7 +345,7 @@ __device__ __forceinline__ void pass_iter64(const SolveArgs& a, const double* P,
   if constexpr (JM != kJBlock)   // a block J uses the regular layout: no long rows
     for (int64_t r = lr.first; r < a.A.n_long; r += lr.step) iter_long<JM, YM>(a, r, lane, P, m, W, p0, p1, p2);
   const WaveRange wr = wave_range<BS>(a.A, a.nxcd);
-  for (int64_t s = wr.first; s < wr.end; s += wr.step) iter_slice<JM, YM>(a, s, lane, P, m, W, p0, p1, p2);
+  for (int64_t s = wr.first; s < wr.end; s += wr.step) iter_slice<JM, YM, NT>(a, s, lane, P, m, W, p0, p1, p2);
 }
 
 // The workgroup's share of r = b - Q X (float64); ||r||^2 in p0 (with obj: f(X)).
@@ -360,7 +360,7 @@ __device__ __forceinline__ void pass_resid64(const Sell& A, int nxcd, const doub
 }
 
 // The workgroup's share of one pass; partial sums in p0..p2 (per thread).
-template <int JM, int BS, bool YM>
+template <int JM, int BS, bool YM, bool NT = false>
 __device__ __forceinline__ void run_pass(const SolveArgs& a, const PassView& v, double& p0, double& p1,
                                          double& p2) {
   const int lane = threadIdx.x % kWave;
@@ -372,7 +372,7 @@ __device__ __forceinline__ void run_pass(const SolveArgs& a, const PassView& v, 
     m.beta_next = v.beta_next;
     m.bz = v.bz != 0;
     m.ym = YM;
-    pass_iter64<JM, BS, YM>(a, pick(a, v.iP), m, pick(a, v.iW), p0, p1, p2);
+    pass_iter64<JM, BS, YM, NT>(a, pick(a, v.iP), m, pick(a, v.iW), p0, p1, p2);
   } else if (v.phase == PH_CONFIRM) {
     pass_resid64<BS>(a.A, a.nxcd, pick(a, v.iW), a.b, nullptr, p0, a.stop_obj != 0);
   } else if (v.phase == PH_INNER32) {
@@ -410,7 +410,7 @@ __device__ __forceinline__ void run_pass(const SolveArgs& a, const PassView& v, 
 // One pass per launch.  The last workgroup to finish reduces the partials and
 // updates the control block for the next launch; launches after the solve has
 // finished return at once.
-template <int JM, int BS, bool YM>
+template <int JM, int BS, bool YM, bool NT = false>
 __global__ void __launch_bounds__(BS) k_pass64(SolveArgs a) {
   __shared__ double sh[3][BS / kWave];
   __shared__ PassView v;
@@ -419,7 +419,7 @@ __global__ void __launch_bounds__(BS) k_pass64(SolveArgs a) {
   __syncthreads();
   if (v.phase == PH_DONE) return;
   double p0 = 0.0, p1 = 0.0, p2 = 0.0;
-  run_pass<JM, BS, YM>(a, v, p0, p1, p2);
+  run_pass<JM, BS, YM, NT>(a, v, p0, p1, p2);
   block_sum3<BS>(p0, p1, p2, sh);
   const int G = gridDim.x;
   if (threadIdx.x == 0) {

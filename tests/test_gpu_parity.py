@@ -390,3 +390,30 @@ def test_materialized_momentum_form_is_bitwise(naj, mode, monkeypatch):
     m = O.accelerated_jacobi_mixed(s.rowptr, s.colidx, s.vals, s.b, tol=1e-8)
     x, info = sysm.solve(s.b, precision=naj.NAJ_MIXED)
     assert info.iterations == m.inner_total and np.array_equal(x.cpu().numpy(), m.x)
+
+
+def test_nontemporal_pass_is_bitwise(naj, monkeypatch):
+    """Systems whose float64 pass exceeds the 256 MB MALL load matrix entries non-temporally (a separate
+    kernel instance); forced on a 40^3 Poisson system (at creation), the solve and block-J solve equal the
+    ordinary pass's bit for bit, and the float64 solve equals the oracle's."""
+    _say("non-temporal pass, poisson 40^3")
+    s = W.poisson_system((40, 40, 40), 12)
+    out = []
+    for flag in ("1", "0"):
+        monkeypatch.setenv("NAJ_NT", flag)
+        sysm = naj.System(s.rowptr, s.colidx, s.vals)
+        sysb = naj.System(s.rowptr, s.colidx, s.vals, jblock=4)
+        monkeypatch.delenv("NAJ_NT")
+        x, info = sysm.solve(s.b, tol=1e-8, max_iter=20000)
+        xb, ib = sysb.solve(s.b, tol=1e-8, max_iter=20000)
+        assert info.grid > 1 and info.status == 0 and ib.status == 0
+        out.append((x.cpu().numpy(), info.iterations, info.restart_log, xb.cpu().numpy(), ib.iterations))
+        sysm.close()
+        sysb.close()
+    assert np.array_equal(out[0][0], out[1][0]) and out[0][1:3] == out[1][1:3]
+    assert np.array_equal(out[0][3], out[1][3]) and out[0][4] == out[1][4]
+    orc = O.accelerated_jacobi(s.rowptr, s.colidx, s.vals, s.b, tol=1e-8, max_iter=20000)
+    if out[0][2] == orc.restarts:
+        assert out[0][1] == orc.iterations and np.array_equal(out[0][0], orc.x)
+    else:
+        assert np.abs(out[0][0] - orc.x).max() <= 1e-10 * np.abs(orc.x).max()
