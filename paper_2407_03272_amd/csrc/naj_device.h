@@ -31,7 +31,8 @@ constexpr int kWave = 64;
 constexpr int kUnroll = NAJ_UNROLL;
 
 // Loads of matrix entries.  Ordinary cached loads measured faster than
-// non-temporal ones (which are kept as a build option).
+// non-temporal ones for passes that fit the MALL; larger float64 passes use
+// mat_ld<true> (below).  NAJ_NT_LOADS makes every such load non-temporal.
 template <typename T>
 __device__ __forceinline__ T stream_load(const T* p) {
 #if defined(NAJ_NT_LOADS)
