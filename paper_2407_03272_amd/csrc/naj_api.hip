@@ -680,10 +680,11 @@ const void* pass_kernel_ym(int jm, int bs) {
 }
 
 // A block-J system always uses the regular layout in the two-iterate form.  nt: the float64 iteration
-// passes load matrix entries non-temporally (instances for the 256-thread two-iterate pass only).
+// passes load matrix entries non-temporally (instances for the 256-thread pass only).
 const void* pass_kernel(int jm, int bs, bool ym, bool nt = false) {
-  if (nt && bs == 256 && !ym) {
+  if (nt && bs == 256) {
     if (jm == kJBlock) return (const void*)k_pass64<kJBlock, 256, false, true>;
+    if (ym) return jm ? (const void*)k_pass64<kJUser, 256, true, true> : (const void*)k_pass64<kJRowSum, 256, true, true>;
     return jm ? (const void*)k_pass64<kJUser, 256, false, true> : (const void*)k_pass64<kJRowSum, 256, false, true>;
   }
   if (jm == kJBlock) {
@@ -1484,11 +1485,12 @@ static naj_status create_system_impl(int64_t n, int64_t nnz, const int32_t* rowp
   STEP(choose_grid(s, st));
   {
     // A float64 iteration pass larger than the 256 MB MALL streams its matrix entries with
-    // non-temporal loads, so they do not evict the gathered vectors (160^3: 92.7 -> 83.3 us per pass).
-    // A pass that fits keeps ordinary loads: the whole pass then stays in the MALL between passes
-    // (128^3: 36.9 us; 46.5 us with non-temporal loads).
+    // non-temporal loads, so they do not evict the gathered vectors (160^3: 92.7 -> 83.1 us per pass;
+    // the Section 4.1 system n = 6000: 95.5 -> 89.4 us; Chung-Lu n = 2^22: 911 -> 892 us).  A pass that
+    // fits keeps ordinary loads: the whole pass then stays in the MALL between passes (128^3: 36.9 us;
+    // 46.5 us with non-temporal loads).
     const int64_t pass_bytes = 8 * s->stored + 4 * (s->stored - s->off_nnz) + 32 * n + 8 * (int64_t)jblock * n;
-    s->nt = env_int("NAJ_NT", (s->layout == 0 && pass_bytes > kMallBytes) ? 1 : 0) ? 1 : 0;
+    s->nt = env_int("NAJ_NT", pass_bytes > kMallBytes ? 1 : 0) ? 1 : 0;
   }
   if (!lean) {   // workspace of the single-solve drivers
     for (int i = 0; i < 3 + s->ymode; ++i) STEP(dev_alloc(s, &s->vec[i], (size_t)n));

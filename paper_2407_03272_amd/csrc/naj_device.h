@@ -533,7 +533,8 @@ __device__ __forceinline__ float wave_sum_f(float v) {
 }
 
 // sum_k v_k * y(c_k) and sum_k |v_k| over [s, e); Y maps a column to its (already formed) y value.
-template <typename T, typename VT, typename YF>
+// NT: the row's entries are loaded non-temporally (see mat_ld).
+template <typename T, typename VT, typename YF, bool NT = false>
 __device__ __forceinline__ void long_row_sums(const int32_t* __restrict__ col, const VT* __restrict__ val, int64_t s,
                                               int64_t e, int lane, YF yof, T& acc, T& asum) {
   acc = (T)0;
@@ -544,8 +545,8 @@ __device__ __forceinline__ void long_row_sums(const int32_t* __restrict__ col, c
 #pragma unroll
     for (int q = 0; q < kLongUnroll; ++q)
       if (k + q * kWave < e) {
-        c[q] = col[k + q * kWave];
-        v[q] = (T)val[k + q * kWave];
+        c[q] = mat_ld<NT>(col + k + q * kWave);
+        v[q] = (T)mat_ld<NT>(val + k + q * kWave);
       }
 #pragma unroll
     for (int q = 0; q < kLongUnroll; ++q)
@@ -559,7 +560,7 @@ __device__ __forceinline__ void long_row_sums(const int32_t* __restrict__ col, c
   }
 }
 
-template <int JM, bool YM>
+template <int JM, bool YM, bool NT = false>
 __device__ __forceinline__ void iter_long(const SolveArgs& a, int64_t r, int lane, const double* __restrict__ P,
                                           const Momentum<double>& m, double* __restrict__ W, double& ps, double& pgg,
                                           double& psabs) {
@@ -569,13 +570,15 @@ __device__ __forceinline__ void iter_long(const SolveArgs& a, int64_t r, int lan
   constexpr bool ym = YM;
   double acc, asum;
   const int64_t s = a.A.lrowptr[r], e = a.A.lrowptr[r + 1];
+  auto fP = [&](int c) { return P[c]; };
+  auto fR = [&](int c) { return R[c]; };
+  auto fY = [&](int c) { const double p = P[c]; return p + beta * (p - R[c]); };
   if (bz)
-    long_row_sums<double>(a.A.lcol, a.A.lval, s, e, lane, [&](int c) { return P[c]; }, acc, asum);
+    long_row_sums<double, double, decltype(fP), NT>(a.A.lcol, a.A.lval, s, e, lane, fP, acc, asum);
   else if (ym)
-    long_row_sums<double>(a.A.lcol, a.A.lval, s, e, lane, [&](int c) { return R[c]; }, acc, asum);
+    long_row_sums<double, double, decltype(fR), NT>(a.A.lcol, a.A.lval, s, e, lane, fR, acc, asum);
   else
-    long_row_sums<double>(a.A.lcol, a.A.lval, s, e, lane,
-                          [&](int c) { const double p = P[c]; return p + beta * (p - R[c]); }, acc, asum);
+    long_row_sums<double, double, decltype(fY), NT>(a.A.lcol, a.A.lval, s, e, lane, fY, acc, asum);
   acc = wave_sum(acc);
   asum = wave_sum(asum);
   if (lane == 0) {

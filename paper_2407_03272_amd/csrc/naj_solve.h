@@ -343,7 +343,7 @@ __device__ __forceinline__ void pass_iter64(const SolveArgs& a, const double* P,
   const int lane = threadIdx.x % kWave;
   const LongRange<BS> lr;
   if constexpr (JM != kJBlock)   // a block J uses the regular layout: no long rows
-    for (int64_t r = lr.first; r < a.A.n_long; r += lr.step) iter_long<JM, YM>(a, r, lane, P, m, W, p0, p1, p2);
+    for (int64_t r = lr.first; r < a.A.n_long; r += lr.step) iter_long<JM, YM, NT>(a, r, lane, P, m, W, p0, p1, p2);
   const WaveRange wr = wave_range<BS>(a.A, a.nxcd);
   for (int64_t s = wr.first; s < wr.end; s += wr.step) iter_slice<JM, YM, NT>(a, s, lane, P, m, W, p0, p1, p2);
 }

@@ -394,8 +394,9 @@ def test_materialized_momentum_form_is_bitwise(naj, mode, monkeypatch):
 
 def test_nontemporal_pass_is_bitwise(naj, monkeypatch):
     """Systems whose float64 pass exceeds the 256 MB MALL load matrix entries non-temporally (a separate
-    kernel instance); forced on a 40^3 Poisson system (at creation), the solve and block-J solve equal the
-    ordinary pass's bit for bit, and the float64 solve equals the oracle's."""
+    kernel instance); forced at creation on a 40^3 Poisson system, the solve and block-J solve equal the
+    ordinary pass's bit for bit and the float64 solve equals the oracle's; forced on a Chung-Lu Laplacian
+    (sorted layout, long rows), the solve equals the ordinary pass's bit for bit."""
     _say("non-temporal pass, poisson 40^3")
     s = W.poisson_system((40, 40, 40), 12)
     out = []
@@ -417,3 +418,16 @@ def test_nontemporal_pass_is_bitwise(naj, monkeypatch):
         assert out[0][1] == orc.iterations and np.array_equal(out[0][0], orc.x)
     else:
         assert np.abs(out[0][0] - orc.x).max() <= 1e-10 * np.abs(orc.x).max()
+    # the sorted layout (materialized form, long rows one wavefront each) with and without the loads
+    c = W.chung_lu_laplacian(1 << 15, 16, 2.5, seed=81, b_seed=82)
+    res = []
+    for flag in ("1", "0"):
+        monkeypatch.setenv("NAJ_NT", flag)
+        sysm = naj.System(c.rowptr, c.colidx, c.vals)
+        monkeypatch.delenv("NAJ_NT")
+        assert sysm.info()["layout"] == 1
+        x, info = sysm.solve(c.b, tol=1e-8, max_iter=20000)
+        assert info.status == 0 and info.grid > 1
+        res.append((x.cpu().numpy(), info.iterations, info.restart_log))
+        sysm.close()
+    assert np.array_equal(res[0][0], res[1][0]) and res[0][1:] == res[1][1:]
