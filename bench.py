@@ -428,7 +428,7 @@ def main():
                     help="run only a 1 GiB torch copy (counter calibration) and a 50-iteration solve, for rocprofv3 --pmc")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(a single system's solve runs on one device)", file=sys.stderr)
         sys.exit(2)
 
