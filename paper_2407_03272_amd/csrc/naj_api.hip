@@ -1074,6 +1074,7 @@ naj_status build_layout(naj_system* s, const int32_t* rowptr, const int32_t* col
     if (s->off_slices == 0) {
       sys_free(s, s->soff);
       s->soff = nullptr;
+      s->bytes -= (int64_t)(hsoff.size() * sizeof(int32_t));
     } else {
       HIP_TRY(hipMemcpyAsync(s->soff, hsoff.data(), sizeof(int32_t) * hsoff.size(), hipMemcpyHostToDevice, st));
     }

@@ -68,6 +68,9 @@ def _pair(naj, monkeypatch, rowptr, colidx, vals):
     monkeypatch.delenv("NAJ_OFFSETS")
     assert off.info()["offset_slices"] == 0
     assert on.info()["stored_entries"] == off.info()["stored_entries"]
+    # the form costs one 64-byte record per slice, kept only when some slice takes it
+    extra = 64 * on.info()["nslices"] if on.info()["offset_slices"] else 0
+    assert on.info()["device_bytes"] - off.info()["device_bytes"] == extra
     return on, off
 
 
@@ -156,12 +159,17 @@ def test_unsorted_row_keeps_its_slice_ordinary(naj, monkeypatch):
     assert np.abs(x - orc.x).max() <= 1e-10 * np.abs(orc.x).max()
 
 
-def test_no_pattern_no_offset_slices(naj):
+def test_no_pattern_no_offset_slices(naj, monkeypatch):
     """Random sparsity has no common offsets; the sorted layout never uses the form; finite-element
     systems on jittered grids get the slices the host rule predicts."""
     _say("offset form absent / FE")
     rowptr, colidx, vals = W.random_spd(1000, 0.02, 5)
-    assert naj.System(rowptr, colidx, vals).info()["offset_slices"] == 0
+    sm = naj.System(rowptr, colidx, vals)
+    assert sm.info()["offset_slices"] == 0
+    # the records were dropped and no longer count as the system's device memory
+    monkeypatch.setenv("NAJ_OFFSETS", "0")
+    assert naj.System(rowptr, colidx, vals).info()["device_bytes"] == sm.info()["device_bytes"]
+    monkeypatch.delenv("NAJ_OFFSETS")
     for x in W.fe_batch(6, nrhs=1, workers=1):
         sm = naj.System(x.rowptr, x.colidx, x.vals)
         _check_count(sm, x.rowptr, x.colidx)
