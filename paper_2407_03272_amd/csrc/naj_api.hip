@@ -585,6 +585,7 @@ struct naj_system {
   float* fvec[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // mixed: 4 inner iterates + r32 (lazy)
   int ymode = 0;                   // materialized momentum form (irregular layout: one gathered vector)
   int nt = 0;                      // float64 iteration passes load matrix entries non-temporally
+  int nt_mx = 0;                   // the same for the float32 inner passes of mixed solves
   double* part = nullptr;          // 3 * max_grid
   Ctrl* ctrl = nullptr;
   Barrier* bar = nullptr;
@@ -1128,7 +1129,7 @@ naj_status run_solve(naj_system* s, SolveArgs& a, const naj_opts& o, hipStream_t
   // one launch per pass, enqueued in chunks; the host checks the phase word of
   // the previous chunk while the current one runs, so the device never waits
   const bool mx = o.precision == NAJ_MIXED;
-  const void* fn = pass_kernel(ud, mx ? s->pass_bs_mx : s->pass_bs, s->ymode != 0, s->nt && !mx);
+  const void* fn = pass_kernel(ud, mx ? s->pass_bs_mx : s->pass_bs, s->ymode != 0, mx ? s->nt_mx != 0 : s->nt != 0);
   const dim3 grid(mx ? s->grid_mx : s->grid), block(mx ? s->pass_bs_mx : s->pass_bs);
   // passes: norm of b + iterations + confirmations (at most one per confirm_gap iterations, plus one)
   const int64_t max_pass = o.precision == NAJ_MIXED
@@ -1492,6 +1493,9 @@ static naj_status create_system_impl(int64_t n, int64_t nnz, const int32_t* rowp
     // 46.5 us with non-temporal loads).
     const int64_t pass_bytes = 8 * s->stored + 4 * (s->stored - s->off_nnz) + 32 * n + 8 * (int64_t)jblock * n;
     s->nt = env_int("NAJ_NT", pass_bytes > kMallBytes ? 1 : 0) ? 1 : 0;
+    // the same rule for the float32 inner pass of mixed solves (4-byte values, float32 vectors and r32)
+    const int64_t inner_bytes = 4 * s->stored + 4 * (s->stored - s->off_nnz) + 20 * n + 4 * (int64_t)jblock * n;
+    s->nt_mx = env_int("NAJ_NT_MIXED", inner_bytes > kMallBytes ? 1 : 0) ? 1 : 0;
   }
   if (!lean) {   // workspace of the single-solve drivers
     for (int i = 0; i < 3 + s->ymode; ++i) STEP(dev_alloc(s, &s->vec[i], (size_t)n));

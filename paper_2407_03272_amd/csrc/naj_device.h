@@ -446,7 +446,7 @@ __device__ __forceinline__ void resid_slice(const Sell& A, int64_t s, int lane, 
 // iter_slice on Q d = r32 with float32 values, vectors and row sums; the
 // restart inner product and the monitor are accumulated in float64 from
 // exactly converted float32 operands.  zp: the previous iterate is zero.
-template <int JM, bool YM>
+template <int JM, bool YM, bool NT = false>
 __device__ __forceinline__ void inner_slice(const SolveArgs& a, int64_t s, int lane, const float* __restrict__ P,
                                             const Momentum<float>& m, float* __restrict__ W, bool zp, double& ps,
                                             double& pgg, double& psabs) {
@@ -468,9 +468,9 @@ __device__ __forceinline__ void inner_slice(const SolveArgs& a, int64_t s, int l
   const float* __restrict__ vp = a.A.val32 + base + lane;
   float acc = 0.0f, asum = 0.0f;
   if (so)
-    fused_row_sums<true, YM, false>(cp, so, (int32_t)rr, vp, width, P, R, beta, bz, zp, acc, asum);
+    fused_row_sums<true, YM, NT>(cp, so, (int32_t)rr, vp, width, P, R, beta, bz, zp, acc, asum);
   else
-    fused_row_sums<false, YM, false>(cp, so, (int32_t)rr, vp, width, P, R, beta, bz, zp, acc, asum);
+    fused_row_sums<false, YM, NT>(cp, so, (int32_t)rr, vp, width, P, R, beta, bz, zp, acc, asum);
   float z = 0.0f;
   if constexpr (JM == kJBlock) z = block_apply(a.jinv32, s, lane, a.jblock, live ? acc - bi : 0.0f);
   if (live) {
@@ -610,7 +610,7 @@ __device__ __forceinline__ void resid_long(const Sell& A, int64_t r, int lane, c
   }
 }
 
-template <int JM, bool YM>
+template <int JM, bool YM, bool NT = false>
 __device__ __forceinline__ void inner_long(const SolveArgs& a, int64_t r, int lane, const float* __restrict__ P,
                                            const Momentum<float>& m, float* __restrict__ W, bool zp, double& ps,
                                            double& pgg, double& psabs) {
@@ -620,15 +620,18 @@ __device__ __forceinline__ void inner_long(const SolveArgs& a, int64_t r, int la
   constexpr bool ym = YM;
   float acc, asum;
   const int64_t s = a.A.lrowptr[r], e = a.A.lrowptr[r + 1];
+  auto f0 = [&](int c) { (void)c; return 0.0f; };
+  auto fP = [&](int c) { return P[c]; };
+  auto fR = [&](int c) { return R[c]; };
+  auto fY = [&](int c) { const float p = P[c]; return p + beta * (p - R[c]); };
   if (zp)
-    long_row_sums<float>(a.A.lcol, a.A.lval32, s, e, lane, [&](int c) { (void)c; return 0.0f; }, acc, asum);
+    long_row_sums<float, float, decltype(f0), NT>(a.A.lcol, a.A.lval32, s, e, lane, f0, acc, asum);
   else if (bz)
-    long_row_sums<float>(a.A.lcol, a.A.lval32, s, e, lane, [&](int c) { return P[c]; }, acc, asum);
+    long_row_sums<float, float, decltype(fP), NT>(a.A.lcol, a.A.lval32, s, e, lane, fP, acc, asum);
   else if (ym)
-    long_row_sums<float>(a.A.lcol, a.A.lval32, s, e, lane, [&](int c) { return R[c]; }, acc, asum);
+    long_row_sums<float, float, decltype(fR), NT>(a.A.lcol, a.A.lval32, s, e, lane, fR, acc, asum);
   else
-    long_row_sums<float>(a.A.lcol, a.A.lval32, s, e, lane,
-                         [&](int c) { const float p = P[c]; return p + beta * (p - R[c]); }, acc, asum);
+    long_row_sums<float, float, decltype(fY), NT>(a.A.lcol, a.A.lval32, s, e, lane, fY, acc, asum);
   acc = wave_sum_f(acc);
   asum = wave_sum_f(asum);
   if (lane == 0) {

@@ -388,9 +388,9 @@ __device__ __forceinline__ void run_pass(const SolveArgs& a, const PassView& v, 
     const bool zp = v.zp != 0;
     const LongRange<BS> lr;
     if constexpr (JM != kJBlock)
-      for (int64_t r = lr.first; r < a.A.n_long; r += lr.step) inner_long<JM, YM>(a, r, lane, P, m, W, zp, p0, p1, p2);
+      for (int64_t r = lr.first; r < a.A.n_long; r += lr.step) inner_long<JM, YM, NT>(a, r, lane, P, m, W, zp, p0, p1, p2);
     const WaveRange wr = wave_range<BS>(a.A, a.nxcd);
-    for (int64_t s = wr.first; s < wr.end; s += wr.step) inner_slice<JM, YM>(a, s, lane, P, m, W, zp, p0, p1, p2);
+    for (int64_t s = wr.first; s < wr.end; s += wr.step) inner_slice<JM, YM, NT>(a, s, lane, P, m, W, zp, p0, p1, p2);
   } else if (v.phase == PH_RESID64) {
     const double* X = pick(a, v.iX);
     const float* D = v.update ? pickf(a, v.iD) : nullptr;

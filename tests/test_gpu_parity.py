@@ -396,7 +396,7 @@ def test_nontemporal_pass_is_bitwise(naj, monkeypatch):
     """Systems whose float64 pass exceeds the 256 MB MALL load matrix entries non-temporally (a separate
     kernel instance); forced at creation on a 40^3 Poisson system, the solve and block-J solve equal the
     ordinary pass's bit for bit and the float64 solve equals the oracle's; forced on a Chung-Lu Laplacian
-    (sorted layout, long rows), the solve equals the ordinary pass's bit for bit."""
+    (sorted layout, long rows), the float64 and mixed solves equal the ordinary passes' bit for bit."""
     _say("non-temporal pass, poisson 40^3")
     s = W.poisson_system((40, 40, 40), 12)
     out = []
@@ -423,11 +423,15 @@ def test_nontemporal_pass_is_bitwise(naj, monkeypatch):
     res = []
     for flag in ("1", "0"):
         monkeypatch.setenv("NAJ_NT", flag)
+        monkeypatch.setenv("NAJ_NT_MIXED", flag)
         sysm = naj.System(c.rowptr, c.colidx, c.vals)
         monkeypatch.delenv("NAJ_NT")
+        monkeypatch.delenv("NAJ_NT_MIXED")
         assert sysm.info()["layout"] == 1
         x, info = sysm.solve(c.b, tol=1e-8, max_iter=20000)
-        assert info.status == 0 and info.grid > 1
-        res.append((x.cpu().numpy(), info.iterations, info.restart_log))
+        xm, im = sysm.solve(c.b, tol=1e-8, precision=naj.NAJ_MIXED)
+        assert info.status == 0 and info.grid > 1 and im.status == 0
+        res.append((x.cpu().numpy(), info.iterations, info.restart_log, xm.cpu().numpy(), im.iterations))
         sysm.close()
-    assert np.array_equal(res[0][0], res[1][0]) and res[0][1:] == res[1][1:]
+    assert np.array_equal(res[0][0], res[1][0]) and res[0][1:3] == res[1][1:3]
+    assert np.array_equal(res[0][3], res[1][3]) and res[0][4] == res[1][4]
