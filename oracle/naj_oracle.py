@@ -363,7 +363,7 @@ def block_apply_fp32(jinv32: np.ndarray, g: np.ndarray) -> np.ndarray:
 
 
 def inner_solve_fp32(Q32: sp.csr_matrix, dinv32: np.ndarray, r32: np.ndarray, *, inner_tol: float,
-                     max_iter: int, restart: bool, k0: int, stall: int = 200):
+                     max_iter: int, restart: bool, k0: int, stall: int = 200, log: list | None = None):
     """Algorithm 3 on Q d = r in float32 from d^0 = 0 with float64 reductions.
 
     ``dinv32`` is the float32 diagonal of J^{-1}, or, for the block J of
@@ -383,6 +383,7 @@ def inner_solve_fp32(Q32: sp.csr_matrix, dinv32: np.ndarray, r32: np.ndarray, *,
     has halved, a plateau is the slow start of the method on a smooth
     right-hand side (it lasts about the square root of the condition number),
     not the float32 floor, so the stall test is not applied.
+    ``log``, when given, receives the monitor value of every iteration (for tests).
     Returns (d, iterations, restarts, finite).
     """
     n = Q32.shape[0]
@@ -401,6 +402,8 @@ def inner_solve_fp32(Q32: sp.csr_matrix, dinv32: np.ndarray, r32: np.ndarray, *,
         x = (y - (dinv32 * g if dinv32.ndim == 1 else block_apply_fp32(dinv32, g))).astype(f32)
         g64 = g.astype(np.float64)
         mon = math.sqrt(float(g64 @ g64)) / nr
+        if log is not None:
+            log.append(mon)
         d = (x - x_prev).astype(f32)
         s = float(g64 @ d.astype(np.float64))
         if not (math.isfinite(mon) and math.isfinite(s)):
