@@ -179,6 +179,15 @@ def _laplacian_from_edges(n: int, u: np.ndarray, v: np.ndarray):
     return A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.astype(np.float64)
 
 
+def _inverse_cdf(cdf: np.ndarray, r: np.ndarray) -> np.ndarray:
+    """searchsorted(cdf, r, side="right") for each r, done on the sorted draws (the same indices, far
+    fewer cache misses than searching draws in random order)."""
+    order = np.argsort(r)
+    out = np.empty(r.shape[0], dtype=np.int64)
+    out[order] = np.searchsorted(cdf, r[order], side="right")
+    return out
+
+
 def chung_lu_edges(n: int, mean_degree: float = 16.0, gamma: float = 2.5, seed: int = 1003,
                    offset: float = 1.0):
     """Chung-Lu random graph with power-law expected degrees.
@@ -198,8 +207,8 @@ def chung_lu_edges(n: int, mean_degree: float = 16.0, gamma: float = 2.5, seed: 
     cdf = np.cumsum(w)
     cdf /= cdf[-1]
     m = int(round(n * mean_degree / 2))
-    a = np.searchsorted(cdf, rng.random(m), side="right").astype(np.int64)
-    c = np.searchsorted(cdf, rng.random(m), side="right").astype(np.int64)
+    a = _inverse_cdf(cdf, rng.random(m))
+    c = _inverse_cdf(cdf, rng.random(m))
     np.minimum(a, n - 1, out=a)
     np.minimum(c, n - 1, out=c)
     keep = a != c
