@@ -955,10 +955,24 @@ naj_status build_layout(naj_system* s, const int32_t* rowptr, const int32_t* col
   const int32_t* src_rp = rowptr;
   const int32_t* src_col = colidx;
   const double* src_val = vals;
-  int64_t* new_rp_d = nullptr;
-  int32_t* tmp_col = nullptr;
-  double* tmp_val = nullptr;
-  int32_t* tmp_rp32 = nullptr;
+  // Temporaries of the sorted layout, released on every exit (an early error return included, so a
+  // failed build inside a server pool gives their memory back).  The stream is drained first: a
+  // kernel enqueued before the failure may still read them.
+  struct Temps {
+    naj_system* s;
+    hipStream_t st;
+    int64_t* new_rp_d = nullptr;
+    int32_t* tmp_col = nullptr;
+    double* tmp_val = nullptr;
+    int32_t* tmp_rp32 = nullptr;
+    int32_t* iperm_d = nullptr;
+    double* dtmp = nullptr;
+    ~Temps() {
+      if (new_rp_d || tmp_col || tmp_val || tmp_rp32 || iperm_d || dtmp) (void)hipStreamSynchronize(st);
+      for (void* p : {(void*)new_rp_d, (void*)tmp_col, (void*)tmp_val, (void*)tmp_rp32, (void*)iperm_d, (void*)dtmp})
+        sys_free(s, p);
+    }
+  } tmp{s, st};
   std::vector<int32_t> hrp2;
   naj_status rc = NAJ_OK;
   if (layout == 1) {
@@ -988,29 +1002,25 @@ naj_status build_layout(naj_system* s, const int32_t* rowptr, const int32_t* col
     s->n_long = nlong;
     hrp2.resize(n + 1);
     for (int64_t i = 0; i <= n; ++i) hrp2[i] = (int32_t)nrp[i];
-    int32_t* iperm_d = nullptr;
     rc = dev_alloc(s, &s->perm, (size_t)n);
     if (rc != NAJ_OK) return rc;
-    HIP_TRY(sys_malloc(s, (void**)&iperm_d, sizeof(int32_t) * n));
-    HIP_TRY(sys_malloc(s, (void**)&new_rp_d, sizeof(int64_t) * (n + 1)));
-    HIP_TRY(sys_malloc(s, (void**)&tmp_rp32, sizeof(int32_t) * (n + 1)));
-    HIP_TRY(sys_malloc(s, (void**)&tmp_col, sizeof(int32_t) * std::max<int64_t>(1, s->nnz)));
-    HIP_TRY(sys_malloc(s, (void**)&tmp_val, sizeof(double) * std::max<int64_t>(1, s->nnz)));
+    HIP_TRY(sys_malloc(s, (void**)&tmp.iperm_d, sizeof(int32_t) * n));
+    HIP_TRY(sys_malloc(s, (void**)&tmp.new_rp_d, sizeof(int64_t) * (n + 1)));
+    HIP_TRY(sys_malloc(s, (void**)&tmp.tmp_rp32, sizeof(int32_t) * (n + 1)));
+    HIP_TRY(sys_malloc(s, (void**)&tmp.tmp_col, sizeof(int32_t) * std::max<int64_t>(1, s->nnz)));
+    HIP_TRY(sys_malloc(s, (void**)&tmp.tmp_val, sizeof(double) * std::max<int64_t>(1, s->nnz)));
     HIP_TRY(hipMemcpyAsync(s->perm, perm.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(iperm_d, iperm.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(new_rp_d, nrp.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(tmp_rp32, hrp2.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(tmp.iperm_d, iperm.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(tmp.new_rp_d, nrp.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(tmp.tmp_rp32, hrp2.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, st));
     hipLaunchKernelGGL(k_permute_rows, dim3(blocks_for(n * kWave, kAux)), dim3(kAux), 0, st, rowptr, colidx, vals, n,
-                       s->perm, iperm_d, new_rp_d, tmp_col, tmp_val);
+                       s->perm, tmp.iperm_d, tmp.new_rp_d, tmp.tmp_col, tmp.tmp_val);
     HIP_TRY(hipGetLastError());
     if (s->dinv) {   // caller's diagonal into solver order
-      double* t = nullptr;
-      HIP_TRY(sys_malloc(s, (void**)&t, sizeof(double) * n));
-      hipLaunchKernelGGL(k_gather, dim3(blocks_for(n, kAux)), dim3(kAux), 0, st, s->dinv, s->perm, t, n);
+      HIP_TRY(sys_malloc(s, (void**)&tmp.dtmp, sizeof(double) * n));
+      hipLaunchKernelGGL(k_gather, dim3(blocks_for(n, kAux)), dim3(kAux), 0, st, s->dinv, s->perm, tmp.dtmp, n);
       HIP_TRY(hipGetLastError());
-      HIP_TRY(hipMemcpyAsync(s->dinv, t, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
-      HIP_TRY(hipStreamSynchronize(st));
-      sys_free(s, t);
+      HIP_TRY(hipMemcpyAsync(s->dinv, tmp.dtmp, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
     }
     // long rows: the prefix of the renumbered CSR
     const int64_t lnnz = nrp[nlong];
@@ -1022,16 +1032,14 @@ naj_status build_layout(naj_system* s, const int32_t* rowptr, const int32_t* col
     if (rc != NAJ_OK) return rc;
     HIP_TRY(hipMemcpyAsync(s->lrowptr, nrp.data(), sizeof(int64_t) * (nlong + 1), hipMemcpyHostToDevice, st));
     if (lnnz > 0) {
-      HIP_TRY(hipMemcpyAsync(s->lcol, tmp_col, sizeof(int32_t) * lnnz, hipMemcpyDeviceToDevice, st));
-      HIP_TRY(hipMemcpyAsync(s->lval, tmp_val, sizeof(double) * lnnz, hipMemcpyDeviceToDevice, st));
+      HIP_TRY(hipMemcpyAsync(s->lcol, tmp.tmp_col, sizeof(int32_t) * lnnz, hipMemcpyDeviceToDevice, st));
+      HIP_TRY(hipMemcpyAsync(s->lval, tmp.tmp_val, sizeof(double) * lnnz, hipMemcpyDeviceToDevice, st));
       hipLaunchKernelGGL(k_to_float, dim3(blocks_for(lnnz, kAux)), dim3(kAux), 0, st, s->lval, s->lval32, lnnz);
       HIP_TRY(hipGetLastError());
     }
-    HIP_TRY(hipStreamSynchronize(st));
-    sys_free(s, iperm_d);
-    src_rp = tmp_rp32;
-    src_col = tmp_col;
-    src_val = tmp_val;
+    src_rp = tmp.tmp_rp32;
+    src_col = tmp.tmp_col;
+    src_val = tmp.tmp_val;
   }
   // slices over rows [n_long, n)
   const int64_t row0 = s->n_long;
@@ -1094,11 +1102,7 @@ naj_status build_layout(naj_system* s, const int32_t* rowptr, const int32_t* col
     HIP_TRY(hipGetLastError());
   }
   HIP_TRY(hipStreamSynchronize(st));
-  sys_free(s, new_rp_d);
-  sys_free(s, tmp_rp32);
-  sys_free(s, tmp_col);
-  sys_free(s, tmp_val);
-  return NAJ_OK;
+  return NAJ_OK;   // the temporaries are released by tmp's destructor
 }
 
 // Runs the solve kernels on `st` for the prepared control block; ev0/ev1 bracket them.
@@ -1516,6 +1520,7 @@ static naj_status create_system_impl(int64_t n, int64_t nnz, const int32_t* rowp
   *out = s;
   return NAJ_OK;
 bad:
+  (void)hipStreamSynchronize(st);   // kernels enqueued before the failure may still use the memory freed below
   if (flag) sys_free(s, flag);
   free_system(s);
   return rc;

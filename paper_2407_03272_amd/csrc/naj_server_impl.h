@@ -255,7 +255,10 @@ naj_status naj_server_admit(naj_server* sv, int64_t n, int64_t nnz, const int32_
   const size_t nv = (size_t)n << lk;
   if (nv * sizeof(double) * 4 >= (1ull << 32))
     return fail(NAJ_EINVAL, "n x right-hand sides too large for the server (solve it alone)");
-  // a lower bound of what the request needs; beyond the whole budget it can never fit
+  // a lower bound of what the request needs (matrix, vectors and, for a sorted layout, its row
+  // permutation); beyond the whole budget it can never fit.  A sorted layout also takes temporaries
+  // while it is built (about 12 bytes per nonzero and 20 per row); they are released on every exit
+  // of the build, so a build that runs out of budget returns all of it and may be retried.
   const size_t vec_bytes = nv * (sizeof(double) * 4 + (mixed ? sizeof(float) * 5 : 0));
   const size_t need = (size_t)nnz * (sizeof(int32_t) + sizeof(double) + sizeof(float)) + vec_bytes;
   if (need > sv->pool.size()) return fail(NAJ_ENOMEM, "request needs about %zu bytes, budget is %zu", need, sv->pool.size());
@@ -270,7 +273,11 @@ naj_status naj_server_admit(naj_server* sv, int64_t n, int64_t nnz, const int32_
   HIP_TRY(hipSetDevice(sv->device));
   naj_server::Slot& sl = sv->slots[slot];
   naj_system* s = nullptr;
+  bool idle = true;   // no other request holds budget
+  for (const naj_server::Slot& q : sv->slots) idle = idle && !q.used;
   naj_status rc = create_system_impl(n, nnz, rowptr, colidx, vals, D, sv->adm, &sv->pool, true, &s);
+  if (rc == NAJ_ENOMEM && idle)
+    return fail(NAJ_ENOMEM, "request does not fit the budget even with no other request admitted");
   if (rc == NAJ_ENOMEM) return fail(NAJ_EBUSY, "not enough free budget now (system)");
   if (rc != NAJ_OK) return rc;
   sl.sys = s;

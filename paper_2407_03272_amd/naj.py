@@ -7,9 +7,12 @@ include/naj.h.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 import re
+import sys
+import weakref
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -99,6 +102,26 @@ def header_functions(path: str = HEADER_PATH) -> list[str]:
     return sorted(set(re.findall(r"\b(naj_[a-z0-9_]+)\s*\(", text)))
 
 
+# Live handles, closed by an exit hook before the interpreter and the HIP runtime shut down.  Freeing
+# device memory from __del__ during interpreter finalization would run after the runtime (and a
+# profiler attached to it) has already been torn down, which can crash the process in exit().
+_live = {"server": weakref.WeakSet(), "batch": weakref.WeakSet(), "system": weakref.WeakSet()}
+
+
+def _close_all():
+    """Release every live server, batch and system (in that order: a batch or server refers to systems)."""
+    for kind in ("server", "batch", "system"):
+        for obj in list(_live[kind]):
+            try:
+                obj.close()
+            except Exception:
+                pass
+
+
+def _finalizing() -> bool:
+    return sys.is_finalizing()
+
+
 def load(path: str = LIB_PATH):
     """Load libnaj.so (fails loudly when it has not been built)."""
     global _lib
@@ -113,6 +136,7 @@ def load(path: str = LIB_PATH):
         fn.restype = res
         fn.argtypes = args
     _lib = lib
+    atexit.register(_close_all)
     return lib
 
 
@@ -195,6 +219,7 @@ class System:
                                            _ptr(self._D), _stream_ptr(stream), ctypes.byref(h))
         _check(st)
         self._h = h
+        _live["system"].add(self)
         # inputs are copied by the library; drop our references
         self._rowptr = self._colidx = self._vals = self._D = None
 
@@ -213,6 +238,8 @@ class System:
             self._h = None
 
     def __del__(self):
+        if _finalizing():   # the exit hook has released every handle; the runtime may be gone now
+            return
         try:
             self.close()
         except Exception:
@@ -320,6 +347,7 @@ class Batch:
             _check(load().naj_batch_create(len(self.systems), arr, ks, ctypes.byref(o), _stream_ptr(stream),
                                            ctypes.byref(h)))
         self._h = h
+        _live["batch"].add(self)
 
     def info(self) -> dict:
         nt, g, by = _I32(), _I32(), _I64()
@@ -332,6 +360,8 @@ class Batch:
             self._h = None
 
     def __del__(self):
+        if _finalizing():   # the exit hook has released every handle; the runtime may be gone now
+            return
         try:
             self.close()
         except Exception:
@@ -399,6 +429,7 @@ class Server:
             _check(load().naj_server_create(int(mem_budget), int(max_slots), int(max_rhs), ctypes.byref(o),
                                             ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
         self._h = h
+        _live["server"].add(self)
         self._req = {}     # ticket -> (x tensor, nrhs, inputs kept alive until admitted)
         self._done = (_I64 * 4096)()
 
@@ -471,6 +502,8 @@ class Server:
             self._h = None
 
     def __del__(self):
+        if _finalizing():   # the exit hook has released every handle; the runtime may be gone now
+            return
         try:
             self.close()
         except Exception:

@@ -161,3 +161,40 @@ def test_server_errors(naj):
     with pytest.raises(KeyError):
         srv.result(done[0])                                                 # taken already
     srv.close()
+
+
+def test_server_failed_layout_build_returns_budget(naj):
+    """A sorted-layout request whose build runs out of budget (while its temporaries are held) is
+    refused as busy and gives back every byte it took; with no other request admitted the same
+    request is an error (it can never fit), not a busy server."""
+    _say("server: failed sorted-layout build")
+    a = W.poisson_system((16, 16), 71, nrhs=1)
+    c = W.chung_lu_laplacian(4096, 16, 2.5, seed=72, b_seed=73)
+    probe = naj.Server(64 << 20, 4, precision=naj.NAJ_MIXED)
+    ta = probe.admit(a.rowptr, a.colidx, a.vals, a.b)
+    assert ta is not None
+    used_a = probe.info()["bytes_used"]
+    probe.close()
+    # the admission estimate for c (matrix 16 B per nonzero, vectors 52 B per row in mixed precision)
+    # fits the free budget, but the sorted layout's build needs its temporaries and slices on top
+    need_c = 16 * c.nnz + 52 * c.n
+    budget = used_a + need_c + (192 << 10)
+    srv = naj.Server(budget, 4, precision=naj.NAJ_MIXED)
+    ta = srv.admit(a.rowptr, a.colidx, a.vals, a.b)
+    assert ta is not None
+    before = srv.info()["bytes_used"]
+    assert before == used_a
+    assert srv.admit(c.rowptr, c.colidx, c.vals, c.b) is None             # busy: the build ran out of budget
+    assert srv.info()["bytes_used"] == before                              # nothing kept from the failed build
+    assert srv.info()["slots_used"] == 1
+    x = None
+    while x is None:
+        for t in srv.step(1):
+            x, inf = srv.result(t)
+    assert inf[0].status == 0
+    assert srv.info()["bytes_used"] == 0
+    with pytest.raises(naj.NajError) as e:
+        srv.admit(c.rowptr, c.colidx, c.vals, c.b)                         # alone it still cannot fit
+    assert e.value.status == naj.NAJ_ENOMEM
+    assert srv.info()["bytes_used"] == 0
+    srv.close()
