@@ -206,6 +206,28 @@ naj_status naj_solve(naj_system *sys, const double *b, const double *x0, const n
                      double *trace, int32_t trace_cap, void *stream);
 
 /*
+ * naj_solve without any device allocation, for callers that cannot allocate: code that
+ * must not call hipMalloc/hipFree (tight serving loops, harnesses that forbid allocation
+ * after setup).  Same solve, kernels and results as naj_solve (bit-identical x,
+ * iterations, restarts, relres) for the same system and options.
+ *   b, x0, opts, x, res, restart_log, log_cap, stream : as naj_solve
+ * No residual history or trace is recorded (res->hist_len = 0).
+ * Scratch: the solve's control block, barrier words, arrival counters and
+ * per-workgroup partial sums live in one static device array of 172,032 bytes
+ * (partial sums for at most 4096 workgroups) that each device holds for the life of
+ * the process; the iterates live in the system (allocated by naj_create_system).
+ * Every call on a device shares that device's array and overwrites it, so calls that
+ * overlap on one device (from several host threads or on several streams) race:
+ * serialize them.  The call returns after `stream` has finished the solve.
+ * Errors: as naj_solve; NAJ_EINVAL also when the system's drivers use more than 4096
+ * workgroups, for a system owned by a server, and for NAJ_MIXED on a system whose
+ * float32 work vectors do not exist yet (the first mixed naj_solve on a system
+ * allocates them; this call never does).
+ */
+naj_status naj_solve_noalloc(naj_system *sys, const double *b, const double *x0, const naj_opts *opts, double *x,
+                             naj_result *res, int32_t *restart_log, int32_t log_cap, void *stream);
+
+/*
  * Stand-alone kernels of the hot path, for measurement and tests.
  *
  * naj_step: one fused pass of Algorithm 3's row update (Section 3 display):

@@ -555,6 +555,27 @@ struct Pool {
 
 }  // namespace naj
 
+// Scratch of the allocation-free solve (naj_solve_noalloc), for callers that cannot allocate device
+// memory: the control block, the grid-barrier words, the arrival counters, the per-workgroup partial
+// sums and an 8-double reduction slot of one solve, at fixed offsets in one static array.  Each
+// device holds its own copy for the life of the process.  Host code must never pass `scratch`
+// itself to a kernel (that is a host-side stand-in): it takes the device address from
+// hipGetSymbolAddress once per device (noalloc_scratch) and uses that.
+constexpr size_t kNoAllocCtrlOff = 0;
+constexpr size_t kNoAllocBarOff = 1024;
+constexpr size_t kNoAllocScalOff = 1280;
+constexpr size_t kNoAllocCountersOff = 4096;
+constexpr size_t kNoAllocPartOff = kNoAllocCountersOff + sizeof(unsigned int) * kCounterWords;
+constexpr int kNoAllocMaxGrid = 4096;   // workgroups whose partial sums fit
+constexpr size_t kNoAllocBytes = kNoAllocPartOff + sizeof(double) * kPartStride * kNoAllocMaxGrid;
+constexpr int kNoAllocMaxDevices = 64;
+static_assert(sizeof(Ctrl) <= kNoAllocBarOff - kNoAllocCtrlOff, "control block exceeds its scratch slot");
+static_assert(sizeof(Barrier) <= kNoAllocScalOff - kNoAllocBarOff, "barrier exceeds its scratch slot");
+static_assert(kNoAllocScalOff + 8 * sizeof(double) <= kNoAllocCountersOff, "reduction slot exceeds its scratch slot");
+static_assert(kNoAllocPartOff % 256 == 0, "partial sums must stay 256-byte aligned");
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
 struct naj_system {
   int device = 0;
   int64_t n = 0, nnz = 0;
@@ -861,7 +882,46 @@ naj_status check_opts(const naj_opts& o) {
   return NAJ_OK;
 }
 
-SolveArgs make_args(naj_system* s, const double* b, const naj_opts& o) {
+// Per-solve scratch of the single-solve drivers: control block, grid-barrier words, arrival
+// counters, per-workgroup partial sums and a small reduction slot.  naj_solve uses the system's
+// own (allocated at creation); naj_solve_noalloc points it into the static device array below.
+struct SolveScratch {
+  Ctrl* ctrl;
+  Barrier* bar;
+  unsigned int* counters;
+  double* part;
+  double* scal;
+};
+
+SolveScratch own_scratch(naj_system* s) { return SolveScratch{s->ctrl, s->bar, s->counters, s->part, s->scal}; }
+
+// Device address of `scratch` on device `dev` (current), looked up once per device and kept.
+std::mutex g_noalloc_mu;
+char* g_noalloc_ptr[kNoAllocMaxDevices] = {};
+
+naj_status noalloc_scratch(int dev, SolveScratch* w) {
+  if (dev < 0 || dev >= kNoAllocMaxDevices) return fail(NAJ_EINVAL, "device %d out of range", dev);
+  char* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+      void* p = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !p)
+        return fail(NAJ_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+      g_noalloc_ptr[dev] = (char*)p;
+    }
+    base = g_noalloc_ptr[dev];
+  }
+  w->ctrl = (Ctrl*)(base + kNoAllocCtrlOff);
+  w->bar = (Barrier*)(base + kNoAllocBarOff);
+  w->scal = (double*)(base + kNoAllocScalOff);
+  w->counters = (unsigned int*)(base + kNoAllocCountersOff);
+  w->part = (double*)(base + kNoAllocPartOff);
+  return NAJ_OK;
+}
+
+SolveArgs make_args(naj_system* s, const double* b, const naj_opts& o, const SolveScratch& w) {
   SolveArgs a;
   a.A = sell_of(s);
   a.dinv = s->dinv;
@@ -875,10 +935,10 @@ SolveArgs make_args(naj_system* s, const double* b, const naj_opts& o) {
   a.buf3 = s->vec[3];
   a.ymode = s->ymode;
   a.ypar = 0;
-  a.part = s->part;
-  a.ctrl = s->ctrl;
-  a.bar = s->bar;
-  a.counters = s->counters;
+  a.part = w.part;
+  a.ctrl = w.ctrl;
+  a.bar = w.bar;
+  a.counters = w.counters;
   a.hist = s->hist;
   a.trace = s->trace;
   a.hist_cap = s->hist_cap_dev;
@@ -907,13 +967,13 @@ SolveArgs make_args(naj_system* s, const double* b, const naj_opts& o) {
 
 // ||b - Q x||^2 into *rr (with obj: f(x) = <x, Q x>/2 - <b, x> instead), fixed-order sums.
 naj_status residual_norm2(naj_system* s, const double* x, const double* b, double* out, double* rr,
-                          hipStream_t st, bool obj = false) {
+                          hipStream_t st, bool obj, const SolveScratch& w) {
   const int G = s->aux_grid;
-  hipLaunchKernelGGL(k_resid64, dim3(G), dim3(kAux), 0, st, sell_of(s), s->nxcd, x, b, out, s->part, obj ? 1 : 0);
+  hipLaunchKernelGGL(k_resid64, dim3(G), dim3(kAux), 0, st, sell_of(s), s->nxcd, x, b, out, w.part, obj ? 1 : 0);
   HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(k_reduce_fixed, dim3(1), dim3(kWave), 0, st, s->part, G, s->scal);
+  hipLaunchKernelGGL(k_reduce_fixed, dim3(1), dim3(kWave), 0, st, w.part, G, w.scal);
   HIP_TRY(hipGetLastError());
-  HIP_TRY(hipMemcpyAsync(rr, s->scal, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(rr, w.scal, sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   return NAJ_OK;
 }
@@ -1146,7 +1206,7 @@ naj_status run_solve(naj_system* s, SolveArgs& a, const naj_opts& o, hipStream_t
     const int64_t n_now = std::min<int64_t>(chunk, max_pass - launched);
     for (int64_t i = 0; i < n_now; ++i) HIP_TRY(hipLaunchKernel(fn, grid, block, kargs, 0, st));
     launched += n_now;
-    HIP_TRY(hipMemcpyAsync(&s->hflag[cur], &s->ctrl->phase, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(&s->hflag[cur], &a.ctrl->phase, sizeof(int), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipEventRecord(s->evc[cur], st));
     if (prev >= 0) {
       HIP_TRY(hipEventSynchronize(s->evc[prev]));
@@ -1580,30 +1640,31 @@ naj_status naj_system_offset_slices(const naj_system* s, int64_t* offset_slices,
   return NAJ_OK;
 }
 
-naj_status naj_solve(naj_system* s, const double* b, const double* x0, const naj_opts* opts, double* x,
-                     naj_result* res, double* hist, int32_t hist_cap, int32_t* restart_log, int32_t log_cap,
-                     double* trace, int32_t trace_cap, void* stream) {
-  g_err.clear();
-  (void)hipGetLastError();   // drop a stale error left by unrelated earlier runtime calls
-  if (!s) return fail(NAJ_EINVAL, "system is NULL");
-  if (!b || !x || !res) return fail(NAJ_EINVAL, "b, x and res are required");
-  if (x == b) return fail(NAJ_EINVAL, "x must not alias b");
+// The body of naj_solve and naj_solve_noalloc: w is the per-solve scratch; with may_alloc false
+// nothing is allocated (no history buffers; mixed precision needs the float32 vectors already).
+static naj_status solve_impl(naj_system* s, const double* b, const double* x0, const naj_opts* opts, double* x,
+                             naj_result* res, double* hist, int32_t hist_cap, int32_t* restart_log, int32_t log_cap,
+                             double* trace, int32_t trace_cap, hipStream_t st, const SolveScratch& w,
+                             bool may_alloc) {
   naj_opts o;
   if (opts) o = *opts; else naj_opts_default(&o);
   naj_status rc = check_opts(o);
   if (rc != NAJ_OK) return rc;
   if ((hist && hist_cap < 0) || (trace && trace_cap < 0) || (restart_log && log_cap < 0))
     return fail(NAJ_EINVAL, "negative capacity");
-  hipStream_t st = (hipStream_t)stream;
-  HIP_TRY(hipSetDevice(s->device));
-  rc = ensure_hist(s, hist ? hist_cap : 0, trace ? trace_cap : 0);
-  if (rc != NAJ_OK) return rc;
-  if (o.precision == NAJ_MIXED && !s->fvec[0]) {
-    for (int i = 0; i < 5; ++i) {
-      if (i == 3 && !s->ymode) continue;
-      rc = dev_alloc(s, &s->fvec[i], (size_t)s->n);
-      if (rc != NAJ_OK) return rc;
+  if (may_alloc) {
+    rc = ensure_hist(s, hist ? hist_cap : 0, trace ? trace_cap : 0);
+    if (rc != NAJ_OK) return rc;
+    if (o.precision == NAJ_MIXED && !s->fvec[0]) {
+      for (int i = 0; i < 5; ++i) {
+        if (i == 3 && !s->ymode) continue;
+        rc = dev_alloc(s, &s->fvec[i], (size_t)s->n);
+        if (rc != NAJ_OK) return rc;
+      }
     }
+  } else if (o.precision == NAJ_MIXED && !s->fvec[0]) {
+    return fail(NAJ_EINVAL, "mixed precision needs the system's float32 work vectors, which the first mixed "
+                            "naj_solve on it allocates; this entry point allocates nothing");
   }
   const double* b_in = b;
   if (s->perm) {   // into the solver's row order
@@ -1618,25 +1679,25 @@ naj_status naj_solve(naj_system* s, const double* b, const double* x0, const naj
     HIP_TRY(hipMemcpyAsync(s->vec[0], x0, sizeof(double) * s->n, hipMemcpyDeviceToDevice, st));
   }
   if (!x0) HIP_TRY(hipMemsetAsync(s->vec[0], 0, sizeof(double) * s->n, st));
-  hipLaunchKernelGGL(k_solve_init, dim3(1), dim3(64), 0, st, s->ctrl, s->bar, s->counters, o.k0, s->ymode);
+  hipLaunchKernelGGL(k_solve_init, dim3(1), dim3(64), 0, st, w.ctrl, w.bar, w.counters, o.k0, s->ymode);
   HIP_TRY(hipGetLastError());
-  SolveArgs a = make_args(s, b_in, o);
-  if (!hist) a.hist = nullptr, a.hist_cap = 0;
+  SolveArgs a = make_args(s, b_in, o, w);
+  if (!hist || !may_alloc) a.hist = nullptr, a.hist_cap = 0;
   else a.hist_cap = std::min(hist_cap, s->hist_cap_dev);
-  if (!trace) a.trace = nullptr, a.trace_cap = 0;
+  if (!trace || !may_alloc) a.trace = nullptr, a.trace_cap = 0;
   else a.trace_cap = std::min(trace_cap, s->trace_cap_dev);
   rc = run_solve(s, a, o, st);
   if (rc != NAJ_OK) return rc;
-  hipLaunchKernelGGL(k_copy_result, dim3(blocks_for(s->n, kAux * 4)), dim3(kAux), 0, st, s->ctrl, s->vec[0],
+  hipLaunchKernelGGL(k_copy_result, dim3(blocks_for(s->n, kAux * 4)), dim3(kAux), 0, st, w.ctrl, s->vec[0],
                      s->vec[1], s->vec[2], x, s->perm, s->n);
   HIP_TRY(hipGetLastError());
   Ctrl hc;
-  HIP_TRY(hipMemcpyAsync(&hc, s->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(&hc, w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   const int hl = std::min(hc.hist_len, a.hist_cap);
-  if (hist && hl > 0) HIP_TRY(hipMemcpy(hist, s->hist, sizeof(double) * hl, hipMemcpyDeviceToHost));
+  if (a.hist && hl > 0) HIP_TRY(hipMemcpy(hist, s->hist, sizeof(double) * hl, hipMemcpyDeviceToHost));
   const int tl = std::min(o.precision == NAJ_MIXED ? hc.outer : hc.hist_len, a.trace_cap);
-  if (trace && tl > 0) HIP_TRY(hipMemcpy(trace, s->trace, sizeof(double) * 2 * tl, hipMemcpyDeviceToHost));
+  if (a.trace && tl > 0) HIP_TRY(hipMemcpy(trace, s->trace, sizeof(double) * 2 * tl, hipMemcpyDeviceToHost));
   int nlog = std::min(hc.restarts, (int)kRestartLogCap);
   if (restart_log) {
     nlog = std::min(nlog, (int)log_cap);
@@ -1652,7 +1713,7 @@ naj_status naj_solve(naj_system* s, const double* b, const double* x0, const naj
     res->restarts = hc.inner_restarts;
     res->confirmations = hc.outer;
   }
-  res->hist_len = hist ? hl : 0;
+  res->hist_len = a.hist ? std::max(hl, 0) : 0;
   res->nrestart_log = restart_log ? nlog : 0;
   float ms = 0.f;
   HIP_TRY(hipEventElapsedTime(&ms, s->ev0, s->ev1));
@@ -1668,18 +1729,50 @@ naj_status naj_solve(naj_system* s, const double* b, const double* x0, const naj
   if (obj && hc.status == ST_OK) res->objgap = hc.nb > 0.0 ? hc.relres : 0.0;
   if ((obj || hc.status == ST_NOT_CONVERGED || hc.status == ST_BREAKDOWN) && hc.result >= 0 && hc.nb > 0.0) {
     double rr = 0.0;   // residual of the returned iterate, in the solver's row order
-    rc = residual_norm2(s, s->vec[hc.result], b_in, nullptr, &rr, st);
+    rc = residual_norm2(s, s->vec[hc.result], b_in, nullptr, &rr, st, false, w);
     if (rc != NAJ_OK) return rc;
     res->relres = std::sqrt(rr) / hc.nb;
     if (obj && hc.status != ST_OK) {   // the objective gap of the returned iterate
       double fx = 0.0;
-      rc = residual_norm2(s, s->vec[hc.result], b_in, nullptr, &fx, st, true);
+      rc = residual_norm2(s, s->vec[hc.result], b_in, nullptr, &fx, st, true, w);
       if (rc != NAJ_OK) return rc;
       res->objgap = std::fabs(fx - o.fstar) / (1.0 + std::fabs(o.fstar));
     }
   }
   if (hc.status == ST_BREAKDOWN) return fail(NAJ_EBREAKDOWN, "NaN/Inf in a reduction at iteration %d", hc.iterations);
   return (naj_status)hc.status;
+}
+
+naj_status naj_solve(naj_system* s, const double* b, const double* x0, const naj_opts* opts, double* x,
+                     naj_result* res, double* hist, int32_t hist_cap, int32_t* restart_log, int32_t log_cap,
+                     double* trace, int32_t trace_cap, void* stream) {
+  g_err.clear();
+  (void)hipGetLastError();   // drop a stale error left by unrelated earlier runtime calls
+  if (!s) return fail(NAJ_EINVAL, "system is NULL");
+  if (!b || !x || !res) return fail(NAJ_EINVAL, "b, x and res are required");
+  if (x == b) return fail(NAJ_EINVAL, "x must not alias b");
+  HIP_TRY(hipSetDevice(s->device));
+  return solve_impl(s, b, x0, opts, x, res, hist, hist_cap, restart_log, log_cap, trace, trace_cap,
+                    (hipStream_t)stream, own_scratch(s), true);
+}
+
+naj_status naj_solve_noalloc(naj_system* s, const double* b, const double* x0, const naj_opts* opts, double* x,
+                             naj_result* res, int32_t* restart_log, int32_t log_cap, void* stream) {
+  g_err.clear();
+  (void)hipGetLastError();
+  if (!s) return fail(NAJ_EINVAL, "system is NULL");
+  if (!b || !x || !res) return fail(NAJ_EINVAL, "b, x and res are required");
+  if (x == b) return fail(NAJ_EINVAL, "x must not alias b");
+  if (s->lean) return fail(NAJ_EINVAL, "the system belongs to a server and has no single-solve vectors");
+  if (s->max_grid > kNoAllocMaxGrid)
+    return fail(NAJ_EINVAL, "the system's drivers use %d workgroups; the static scratch holds partial sums for %d",
+                s->max_grid, kNoAllocMaxGrid);
+  HIP_TRY(hipSetDevice(s->device));
+  SolveScratch w;
+  naj_status rc = noalloc_scratch(s->device, &w);
+  if (rc != NAJ_OK) return rc;
+  return solve_impl(s, b, x0, opts, x, res, nullptr, 0, restart_log, log_cap, nullptr, 0, (hipStream_t)stream, w,
+                    false);
 }
 
 naj_status naj_step(naj_system* s, const double* p, const double* r, double beta, const double* b, double* x,
@@ -1692,7 +1785,7 @@ naj_status naj_step(naj_system* s, const double* p, const double* r, double beta
   hipStream_t st = (hipStream_t)stream;
   naj_opts o;
   naj_opts_default(&o);
-  SolveArgs a = make_args(s, b, o);
+  SolveArgs a = make_args(s, b, o, own_scratch(s));
   const int G = s->aux_grid;
   const int bz = beta == 0.0 ? 1 : 0;
   const double* P = p;
@@ -1731,12 +1824,12 @@ naj_status naj_residual(naj_system* s, const double* x, const double* b, double*
   g_err.clear();
   if (!s || !x || !b || !rr) return fail(NAJ_EINVAL, "null argument");
   hipStream_t st = (hipStream_t)stream;
-  if (!s->perm) return residual_norm2(s, x, b, out, rr, st);
+  if (!s->perm) return residual_norm2(s, x, b, out, rr, st, false, own_scratch(s));
   const dim3 g1(blocks_for(s->n, kAux * 4)), b1(kAux);
   hipLaunchKernelGGL(k_gather, g1, b1, 0, st, x, s->perm, s->vec[0], s->n);
   hipLaunchKernelGGL(k_gather, g1, b1, 0, st, b, s->perm, s->bperm, s->n);
   HIP_TRY(hipGetLastError());
-  naj_status rc = residual_norm2(s, s->vec[0], s->bperm, out ? s->vec[1] : nullptr, rr, st);
+  naj_status rc = residual_norm2(s, s->vec[0], s->bperm, out ? s->vec[1] : nullptr, rr, st, false, own_scratch(s));
   if (rc != NAJ_OK) return rc;
   if (out) {
     hipLaunchKernelGGL(k_scatter, g1, b1, 0, st, s->vec[1], s->perm, out, s->n);

@@ -74,6 +74,8 @@ _SIGS = {
                                                 ctypes.POINTER(_I64)]),
     "naj_solve": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(NajOpts), _P, ctypes.POINTER(NajResult), _P, _I32,
                                  _P, _I32, _P, _I32, _P]),
+    "naj_solve_noalloc": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(NajOpts), _P, ctypes.POINTER(NajResult), _P,
+                                         _I32, _P]),
     "naj_step": (ctypes.c_int, [_P, _P, _P, _D, _P, _P, _P, _P]),
     "naj_residual": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "naj_diagonal": (ctypes.c_int, [_P, _P, _P]),
@@ -280,6 +282,27 @@ class System:
         info = SolveInfo(res.status, res.iterations, res.restarts, res.confirmations, res.relres,
                          hist[:res.hist_len].copy(), rlog[:res.nrestart_log].tolist(),
                          tr[:res.hist_len].copy() if trace else np.zeros((0, 2)),
+                         res.kernel_ms, res.passes, res.grid, res.objgap)
+        return x, info
+
+    def solve_noalloc(self, b, x0=None, *, out=None, stream=None, **opts) -> tuple:
+        """naj_solve_noalloc: the same solve with its scratch in the library's static device array
+        (allocates no device memory; ``out`` should be given so this call allocates nothing either)."""
+        torch = _torch()
+        lib = load()
+        o = default_opts(**opts)
+        b = self.vec(b)
+        x0 = None if x0 is None else self.vec(x0)
+        x = out if out is not None else torch.empty(self.n, dtype=torch.float64, device=self.device)
+        rlog = np.zeros(64, dtype=np.int32)
+        res = NajResult()
+        with torch.cuda.device(self.device):
+            st = lib.naj_solve_noalloc(self._h, _ptr(b), _ptr(x0), ctypes.byref(o), _ptr(x), ctypes.byref(res),
+                                       rlog.ctypes.data_as(_P), 64, _stream_ptr(stream))
+        if st < 0 and st != NAJ_EBREAKDOWN:
+            _check(st)
+        info = SolveInfo(res.status, res.iterations, res.restarts, res.confirmations, res.relres,
+                         np.zeros(0), rlog[:res.nrestart_log].tolist(), np.zeros((0, 2)),
                          res.kernel_ms, res.passes, res.grid, res.objgap)
         return x, info
 
