@@ -102,22 +102,108 @@ def make_workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(sysobj, iterations_needed: int, sample_iters: int, jblock=None, stop_kw=None) -> dict:
-    """Time the CPU oracle (as it is) on a bounded sample of the same solve and scale to solves/s."""
-    from threadpoolctl import threadpool_limits
+def host_cpu() -> dict:
+    """Host CPU facts for the baseline: logical CPUs this process may use, and the model name."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count()
+    return {"nproc": nproc, "cpu_model": model, "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
 
-    import oracle as O
-    with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        r = O.accelerated_jacobi(sysobj.rowptr, sysobj.colidx, sysobj.vals, sysobj.b, tol=1e-8,
-                                 max_iter=sample_iters, jblock=jblock, **(stop_kw or {}))
-        dt = time.perf_counter() - t0
-    per_iter = dt / max(1, len(r.hist))
-    solve_s = per_iter * iterations_needed
-    return {"value": 1.0 / solve_s, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {len(r.hist)} of {iterations_needed} iterations of the same float64 solve "
-                      f"({dt:.1f} s, {per_iter * 1e3:.1f} ms/iteration, numpy/scipy single thread), "
-                      f"scaled to one full solve"}
+
+def cpu_baseline(sysobj, iterations_needed: int, sample_iters: int, jblock=None, stop_kw=None,
+                 progress=None) -> dict:
+    """The CPU oracle (as it is) on the same solve.
+
+    Diagonal J with the residual stop: the multi-core C oracle (OpenMP over rows) runs the whole
+    float64 solve on every thread OpenMP gives it (OMP_NUM_THREADS), timed around the solve with
+    setup excluded, repeated while the repeats take under about 8 s (median reported); a one-thread
+    run over the first `sample_iters` iterations is scaled to one solve beside it.  Block J or the
+    objective stop: the numpy/scipy oracle on one thread over the first `sample_iters` iterations,
+    scaled to one solve."""
+    info = host_cpu()
+    if jblock or stop_kw:
+        from threadpoolctl import threadpool_limits
+
+        import oracle as O
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            r = O.accelerated_jacobi(sysobj.rowptr, sysobj.colidx, sysobj.vals, sysobj.b, tol=1e-8,
+                                     max_iter=sample_iters, jblock=jblock, **(stop_kw or {}))
+            dt = time.perf_counter() - t0
+        per_iter = dt / max(1, len(r.hist))
+        return {"value": 1.0 / (per_iter * iterations_needed), "unit": "solves/s", "cores": 1, "kind": "oracle",
+                "sample": f"first {len(r.hist)} of {iterations_needed} iterations of the same float64 solve "
+                          f"({dt:.1f} s, {per_iter * 1e3:.1f} ms/iteration, numpy/scipy single thread), "
+                          f"scaled to one full solve", **info}
+    from oracle import cpu_omp
+    times, r = [], None
+    t_all = time.perf_counter()
+    while len(times) < 5 and (len(times) < 1 or time.perf_counter() - t_all < 8.0):
+        r = cpu_omp.solve(sysobj.rowptr, sysobj.colidx, sysobj.vals, sysobj.b, tol=1e-8, max_iter=20000,
+                          threads=0, hist_cap=0)
+        times.append(r.seconds)
+        if progress:
+            progress(f"cpu oracle ({r.threads} threads): {r.seconds:.2f} s, {r.iterations} iterations")
+    med = float(np.median(times))
+    one = cpu_omp.solve(sysobj.rowptr, sysobj.colidx, sysobj.vals, sysobj.b, tol=1e-8,
+                        max_iter=min(sample_iters, max(1, r.iterations)), threads=1, hist_cap=0)
+    per_iter1 = one.seconds / max(1, one.iterations)
+    return {"value": 1.0 / med, "unit": "solves/s", "cores": r.threads, "kind": "oracle",
+            "sample": f"{len(times)} complete float64 solves of the same system by the C oracle "
+                      f"(OpenMP over rows, {r.threads} threads; {r.iterations} iterations, relres {r.relres:.3g}, "
+                      f"status {r.status}), median {med:.2f} s",
+            "iterations": r.iterations, "seconds_median": med,
+            "single_thread": {"value": 1.0 / (per_iter1 * r.iterations), "unit": "solves/s", "cores": 1,
+                              "sample": f"first {one.iterations} iterations on one thread "
+                                        f"({one.seconds:.2f} s, {per_iter1 * 1e3:.2f} ms/iteration), "
+                                        f"scaled to {r.iterations} iterations"},
+            **info}
+
+
+def attainable_bandwidth(progress=None) -> dict:
+    """The GPU's attainable streaming rates, measured by the library's probe kernel (naj_bandwidth_probe:
+    16-byte non-temporal accesses over 1 GiB, mean of 20 launches timed with HIP events on the launching
+    stream): read only, copy (read + write bytes) and write only, beside the 8 TB/s published peak."""
+    import torch
+    from paper_2407_03272_amd import naj
+    out = {}
+    for mode in (0, 1, 2):
+        r = naj.bandwidth_probe(mode, 1 << 30, 20)
+        out[r["mode"] + "_gbps"] = r["gbps"]
+        if mode == 1:
+            assert r["copy_exact"], "bandwidth probe copy mismatch"
+    torch.cuda.empty_cache()
+    out["best_gbps"] = max(out["read_gbps"], out["copy_gbps"], out["write_gbps"])
+    out["best_frac_of_peak"] = out["best_gbps"] / HBM_PEAK_GBS
+    out["kernel"] = "naj_bandwidth_probe (k_bw_probe), 1 GiB, 16-byte non-temporal accesses, mean of 20 launches"
+    if progress:
+        progress(f"attainable bandwidth: read {out['read_gbps']:.0f}, copy {out['copy_gbps']:.0f}, "
+                 f"write {out['write_gbps']:.0f} GB/s")
+    return out
+
+
+def component_mean_free(rowptr, colidx, vals, x: np.ndarray) -> np.ndarray:
+    """x minus its J-weighted mean on each connected component of the matrix graph (J = absolute row
+    sums, 1 on zero rows): the part of x outside the null space of a graph Laplacian, where the
+    method keeps the J-weighted sum of the starting point on every component."""
+    import scipy.sparse as sps
+    from scipy.sparse.csgraph import connected_components
+    n = len(rowptr) - 1
+    A = sps.csr_matrix((np.abs(vals), colidx, rowptr), shape=(n, n))
+    J = np.asarray(A.sum(axis=1)).ravel()
+    J[J == 0] = 1.0
+    nc, lab = connected_components(A, directed=False)
+    mean = np.bincount(lab, weights=J * x, minlength=nc) / np.bincount(lab, weights=J, minlength=nc)
+    return x - mean[lab]
 
 
 def bench_fe_batch(args, progress):
@@ -403,70 +489,23 @@ def bench_serve(args, progress):
     return out
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="laplace3d_128")
-    ap.add_argument("--cpu-sample-iters", type=int, default=200)
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
-    ap.add_argument("--no-compare", action="store_true", help="skip the second-precision comparison solves")
-    ap.add_argument("--nsys", type=int, default=512, help="systems in the fe_batch workload")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--stop", choices=["relres", "objective"], default="relres",
-                    help="single float64 solves: stop on the relative residual (tol 1e-8) or on the paper's "
-                         "relative objective gap (tol 1e-10, f* = -<b, x*>/2 from the generator's x*)")
-    ap.add_argument("--jblock", type=int, default=0,
-                    help="single-solve workloads: block-diagonal J of eq. (J-blkdiag) with blocks of this many rows")
-    ap.add_argument("--serve-requests", type=int, default=2200, help="requests in the serve workload trace")
-    ap.add_argument("--serve-budget-mb", type=int, default=8192, help="serve workload memory budget")
-    ap.add_argument("--serve-small-budget-mb", type=int, default=512, help="second serve run with this budget (0: none)")
-    ap.add_argument("--serve-slots", type=int, default=64)
-    ap.add_argument("--serve-fp64-sample", type=int, default=200)
-    ap.add_argument("--pmc-sample", action="store_true",
-                    help="run only a 1 GiB torch copy (counter calibration) and a 50-iteration solve, for rocprofv3 --pmc")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
-              "(a single system's solve runs on one device)", file=sys.stderr)
-        sys.exit(2)
-
+def bench_single(args, workload: str, progress, steps: int, warmup: int, precision: str, compare: bool,
+                 cpu: bool, sysobj=None) -> dict:
+    """One system solved `steps` times (after `warmup` untimed solves) in `precision`; optionally the
+    same system in the other precision for the mixed-vs-float64 comparison, and the CPU oracle."""
     import torch
     from paper_2407_03272_amd import naj
-
-    def progress(msg):
-        print(f"[bench] {msg}", file=sys.stderr, flush=True)
-
-    if args.workload == "serve":
-        print(json.dumps(bench_serve(args, progress)), flush=True)
-        return
-    if args.workload == "fe_batch":
-        if args.precision == "fp64" and "--precision" not in sys.argv:
-            args.precision = "mixed"
-        print(json.dumps(bench_fe_batch(args, progress)), flush=True)
-        return
-    sysobj = make_workload(args.workload)
+    if sysobj is None:
+        sysobj = make_workload(workload)
     n, nnz = sysobj.n, sysobj.nnz
     progress(f"workload {sysobj.name}: n={n} nnz={nnz}")
     dev = torch.device("cuda:0")
-    if args.pmc_sample:
-        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)     # 1 GiB
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        sysm = naj.System(sysobj.rowptr, sysobj.colidx, sysobj.vals, device="cuda:0")
-        b = torch.as_tensor(sysobj.b).to(dev)
-        _, info = sysm.solve(b, hist_cap=0, tol=1e-30, max_iter=50)
-        print(json.dumps({"pmc_sample": True, "copy_bytes_each_way": src.numel() * 8, "passes": info.passes}))
-        return
     jb = args.jblock
     obj = args.stop == "objective"
     if obj:
-        if args.precision != "fp64":
+        if precision != "fp64":
             raise SystemExit("the objective-gap stop is a float64 option")
-        args.no_compare = True
+        compare = False
         fstar = -0.5 * float(np.dot(sysobj.b, sysobj.xstar))
         stop_kw = dict(stop=naj.NAJ_STOP_OBJECTIVE, fstar=fstar)
         tol = 1e-10
@@ -475,8 +514,8 @@ def main():
     sysm = naj.System(sysobj.rowptr, sysobj.colidx, sysobj.vals, device="cuda:0", jblock=jb or None)
     b = torch.as_tensor(sysobj.b).to(dev)
     x = torch.empty(n, dtype=torch.float64, device=dev)
-    mixed = args.precision == "mixed"
-    singular = args.workload.startswith("chunglu")   # graph Laplacians: answers are defined up to the null space
+    mixed = precision == "mixed"
+    singular = workload.startswith("chunglu")   # graph Laplacians: answers are defined up to the null space
 
     def timed(mixed_: bool, steps: int, warmup: int):
         opts = dict(tol=tol, max_iter=20000, precision=naj.NAJ_MIXED if mixed_ else naj.NAJ_FP64,
@@ -499,9 +538,9 @@ def main():
         return total, lat, kms, infos
 
     progress("system created")
-    total, lat, kms, infos = timed(mixed, args.steps, args.warmup)
+    total, lat, kms, infos = timed(mixed, steps, warmup)
     x_main = x.clone()
-    progress(f"timed {args.steps} solves: {total / args.steps * 1e3:.2f} ms each")
+    progress(f"timed {steps} solves: {total / steps * 1e3:.2f} ms each")
     info = infos[-1]
     sinfo = sysm.info()
     nnz_off = sinfo["offset_nnz"]
@@ -509,7 +548,7 @@ def main():
     moved_bytes = solve_bytes(n, nnz, info, mixed, jb, nnz_off)      # what the layout reads and writes
     kernel_s = float(np.mean(kms)) / 1e3
     achieved = alg_bytes / kernel_s / 1e9
-    solves_s = args.steps / total
+    solves_s = steps / total
     if mixed:
         per_launch = bytes_per_iteration(n, nnz, s_v=4, s_x=4, jb=jb)
         moved_launch = bytes_per_iteration(n, nnz, s_v=4, s_x=4, jb=jb, nnz_off=nnz_off)
@@ -529,15 +568,15 @@ def main():
         "value": solves_s,
         "unit": "solves/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": total / args.steps * 1e3,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": total / steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32+f64" if mixed else "f64",
         "data": "synthetic",
-        "config": {"workload": wl, "n": n, "nnz": nnz, "precision": args.precision, "tol": tol,
+        "config": {"workload": wl, "n": n, "nnz": nnz, "precision": precision, "tol": tol,
                    "iterations": info.iterations, "restarts": info.restarts, "confirmations": info.confirmations,
                    "passes": info.passes, "grid": info.grid, "relres": info.relres,
                    "layout": sinfo["layout"], "offset_slices": sinfo["offset_slices"],
@@ -549,7 +588,7 @@ def main():
         "gbps_solve": achieved,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None if (mixed or jb) else measured_traffic(args.workload),
+                     "traffic": None if (mixed or jb) else measured_traffic(workload),
                      "kernel": "k_pass64 (fused iteration pass, one launch per pass)",
                      "launches_per_solve": info.passes,
                      "algorithmic_bytes_per_launch": per_launch,
@@ -558,29 +597,168 @@ def main():
                      "layout_frac": moved_bytes / kernel_s / 1e9 / HBM_PEAK_GBS,
                      "mean_launch_us": kernel_s / info.passes * 1e6},
     }
-    if not args.no_compare:
+    if compare:
         # the same system solved in the other precision, for the mixed-vs-FP64 comparison
-        ctot, clat, ckms, cinfos = timed(not mixed, max(3, args.steps // 2), 1)
+        ctot, clat, ckms, cinfos = timed(not mixed, max(3, steps // 2), 1)
         ci = cinfos[-1]
         # the mixed answer against the float64 one (which equals the oracle's in the parity tests); a singular
         # system's answers may differ by a null-space component, so none is stated there
         xm, xf = (x_main, x) if mixed else (x, x_main)
-        rel_err = None if singular else float(torch.linalg.vector_norm(xm - xf) / torch.linalg.vector_norm(xf))
+        if singular:
+            # answers of a graph Laplacian are defined up to its null space: compare them with the
+            # J-weighted mean of every connected component removed (both runs start from x^0 = 0,
+            # whose component means the method keeps, so this removes only rounding drift)
+            pm = component_mean_free(sysobj.rowptr, sysobj.colidx, sysobj.vals, xm.cpu().numpy())
+            pf = component_mean_free(sysobj.rowptr, sysobj.colidx, sysobj.vals, xf.cpu().numpy())
+            rel_err = float(np.linalg.norm(pm - pf) / np.linalg.norm(pf))
+        else:
+            rel_err = float(torch.linalg.vector_norm(xm - xf) / torch.linalg.vector_norm(xf))
         line["compare"] = {"precision": "fp64" if mixed else "mixed", "solves_per_s": len(clat) / ctot,
                            "p50_ms": float(np.percentile(clat, 50) * 1e3),
                            "p99_ms": float(np.percentile(clat, 99) * 1e3),
                            "iterations": ci.iterations, "confirmations": ci.confirmations, "relres": ci.relres,
                            "rel_err_mixed_vs_fp64": rel_err,
+                           "rel_err_definition": ("2-norm over 2-norm after removing each connected component's "
+                                                  "J-weighted mean" if singular else "2-norm over 2-norm"),
                            "gbps_solve": solve_bytes(n, nnz, ci, not mixed, jb) / (float(np.mean(ckms)) / 1e3) / 1e9}
     it = info.iterations
-    if not args.no_cpu_baseline:
+    if cpu:
         progress("cpu baseline")
         its_fp64 = info.iterations if not mixed else line.get("compare", {}).get("iterations", info.iterations)
         line["cpu_baseline"] = cpu_baseline(sysobj, its_fp64, args.cpu_sample_iters, jb or None,
-                                            dict(stop="objective", fstar=stop_kw["fstar"]) if obj else None)
+                                            dict(stop="objective", fstar=stop_kw["fstar"]) if obj else None,
+                                            progress)
     sysm.close()
-    print(json.dumps(line), flush=True)
+    return line
 
+
+
+def _sub(line: dict) -> dict:
+    """A workload's result as a sub-object of the default line (without the keys the top line carries)."""
+    return {k: v for k, v in line.items()
+            if k not in ("metric", "n_gpus", "higher_is_better", "scaling", "vs_baseline", "data")}
+
+
+def bench_default(args, progress) -> dict:
+    """The default run.  Top level: the 128^3 Laplacian in float64, one solve per step (value, latency,
+    the fused pass's roofline, the mixed-precision comparison, the CPU oracle), and the measured copy
+    bandwidth.  Sub-results, each with its own fixed step counts: 160^3 in float64 (the pass beyond the
+    256 MB MALL), the Chung-Lu graph Laplacian n = 2^22 in mixed precision against float64, the
+    512-system finite-element batch (mixed batch against float64 batch and float64 one system at a
+    time), and the serving loop (p50/p99 latency, offered and saturated solves/s, float64 one request
+    at a time)."""
+    import copy
+    t_start = time.perf_counter()
+    line = bench_single(args, "laplace3d_128", progress, args.steps, args.warmup, "fp64", not args.no_compare,
+                        not args.no_cpu_baseline)
+    ab = attainable_bandwidth(progress)
+    line["attainable_bandwidth"] = ab
+    rf = line["roofline"]
+    rf["attainable_gbps"] = ab["best_gbps"]
+    rf["frac_of_attainable"] = rf["achieved"] / ab["best_gbps"]
+    rf["layout_frac_of_attainable"] = rf["layout_gbps"] / ab["best_gbps"]
+    rf["residency"] = ("MALL-resident: the pass moves about 192 MB, under the 256 MB MALL, so part of its "
+                       "bytes may come from the MALL rather than HBM; workloads.laplace3d_160 is the pass "
+                       "beyond the MALL")
+    subs = {}
+    subs["laplace3d_160"] = _sub(bench_single(args, "laplace3d_160", progress, 3, 1, "fp64", True, False))
+    subs["laplace3d_160"]["roofline"]["residency"] = "beyond the MALL: about 376 MB moved per pass"
+    progress(f"160^3 done at {time.perf_counter() - t_start:.0f} s")
+    subs["chunglu_4m"] = _sub(bench_single(args, "chunglu_4m", progress, 3, 1, "mixed", True, False))
+    progress(f"Chung-Lu done at {time.perf_counter() - t_start:.0f} s")
+    a2 = copy.copy(args)
+    a2.steps, a2.warmup, a2.precision = 2, 1, "mixed"
+    fe = bench_fe_batch(a2, progress)
+    subs["fe_batch"] = _sub(fe)
+    progress(f"batch done at {time.perf_counter() - t_start:.0f} s")
+    sv = bench_serve(args, progress)
+    subs["serve"] = _sub(sv)
+    progress(f"serving done at {time.perf_counter() - t_start:.0f} s")
+    line["workloads"] = subs
+    one_fe = fe.get("compare_one_at_a_time", {}).get("solves_per_s_est")
+    one_sv = sv.get("compare_one_at_a_time", {}).get("solves_per_s")
+    line["comparisons"] = {
+        "batched_mixed_solves_per_s": fe["value"],
+        "batched_fp64_solves_per_s": fe.get("compare_batch", {}).get("solves_per_s"),
+        "fp64_one_at_a_time_solves_per_s_batch_systems": one_fe,
+        "batched_mixed_over_fp64_one_at_a_time": fe["value"] / one_fe if one_fe else None,
+        "served_mixed_solves_per_s_offered_200": sv["value"],
+        "served_mixed_solves_per_s_saturated": sv["closed_loop_solves_per_s"],
+        "served_p50_ms": sv["p50_ms"], "served_p99_ms": sv["p99_ms"],
+        "fp64_one_at_a_time_solves_per_s_trace": one_sv,
+        "served_saturated_over_fp64_one_at_a_time": sv["closed_loop_solves_per_s"] / one_sv if one_sv else None,
+    }
+    line["bench_seconds"] = time.perf_counter() - t_start
+    return line
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="laplace3d_128")
+    ap.add_argument("--cpu-sample-iters", type=int, default=200)
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--no-compare", action="store_true", help="skip the second-precision comparison solves")
+    ap.add_argument("--nsys", type=int, default=512, help="systems in the fe_batch workload")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--stop", choices=["relres", "objective"], default="relres",
+                    help="single float64 solves: stop on the relative residual (tol 1e-8) or on the paper's "
+                         "relative objective gap (tol 1e-10, f* = -<b, x*>/2 from the generator's x*)")
+    ap.add_argument("--jblock", type=int, default=0,
+                    help="single-solve workloads: block-diagonal J of eq. (J-blkdiag) with blocks of this many rows")
+    ap.add_argument("--serve-requests", type=int, default=2200, help="requests in the serve workload trace")
+    ap.add_argument("--serve-budget-mb", type=int, default=8192, help="serve workload memory budget")
+    ap.add_argument("--serve-small-budget-mb", type=int, default=512, help="second serve run with this budget (0: none)")
+    ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--serve-fp64-sample", type=int, default=200)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="default workload only: skip the beyond-MALL, Chung-Lu, batch and serving sub-results")
+    ap.add_argument("--pmc-sample", action="store_true",
+                    help="run only a 1 GiB torch copy (counter calibration) and a 50-iteration solve, for rocprofv3 --pmc")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(a single system's solve runs on one device)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2407_03272_amd import naj
+
+    def progress(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    if args.workload == "serve":
+        print(json.dumps(bench_serve(args, progress)), flush=True)
+        return
+    if args.workload == "fe_batch":
+        if args.precision == "fp64" and "--precision" not in sys.argv:
+            args.precision = "mixed"
+        print(json.dumps(bench_fe_batch(args, progress)), flush=True)
+        return
+    if args.pmc_sample:
+        # counter calibration: the library's probe kernel reads 1 GiB (mode 0) and copies 1 GiB (mode 1),
+        # two launches each (one untimed, one timed); then 50 iterations of the workload's solve
+        sysobj = make_workload(args.workload)
+        dev = torch.device("cuda:0")
+        cal = [naj.bandwidth_probe(m, 1 << 30, 1) for m in (0, 1)]
+        torch.cuda.synchronize()
+        sysm = naj.System(sysobj.rowptr, sysobj.colidx, sysobj.vals, device="cuda:0")
+        b = torch.as_tensor(sysobj.b).to(dev)
+        prec = naj.NAJ_MIXED if args.precision == "mixed" else naj.NAJ_FP64
+        _, info = sysm.solve(b, hist_cap=0, tol=1e-30, max_iter=50, precision=prec,
+                             **({"max_refine": 1} if prec == naj.NAJ_MIXED else {}))
+        print(json.dumps({"pmc_sample": True, "probe_read_bytes": 1 << 30, "probe_copy_bytes_each_way": 1 << 30,
+                          "probe": cal, "passes": info.passes, "info": sysm.info()}))
+        return
+    if args.workload == "laplace3d_128" and not args.no_extras and args.precision == "fp64" and not args.jblock \
+            and args.stop == "relres":
+        print(json.dumps(bench_default(args, progress)), flush=True)
+        return
+    line = bench_single(args, args.workload, progress, args.steps, args.warmup, args.precision,
+                        not args.no_compare, not args.no_cpu_baseline)
+    print(json.dumps(line), flush=True)
 
 if __name__ == "__main__":
     main()

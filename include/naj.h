@@ -47,6 +47,7 @@ typedef enum naj_status {
     NAJ_ENOMEM = -2,         /* device allocation failed                                  */
     NAJ_EDEVICE = -3,        /* HIP runtime error or device-side timeout                  */
     NAJ_EBREAKDOWN = -4,     /* a reduction became NaN/Inf (x holds the last finite x^{t-1}) */
+    NAJ_ECANCELLED = -5,     /* naj_cancel stopped the solve; x holds the iterate it had   */
     NAJ_EBUSY = -6           /* server: no slot or memory for the request now             */
 } naj_status;
 
@@ -199,7 +200,11 @@ naj_status naj_system_offset_slices(const naj_system *sys, int64_t *offset_slice
  *                     s_t = <Q y^t - b, x^t - x^{t-1}> at [2(t-1)] and
  *                     sum_i |(Q y^t - b)_i (x^t - x^{t-1})_i| at [2(t-1)+1]
  *   stream          : the call returns after the stream has finished the solve
- * Errors: NAJ_EINVAL (bad options), NAJ_ENOMEM, NAJ_EDEVICE, NAJ_EBREAKDOWN.
+ * Several right-hand sides of one system: a batch of that one system (naj_batch_create with
+ * nsys = 1 and nrhs = k, row-interleaved b and x) runs them together, each with its own
+ * restart schedule and stop.
+ * Errors: NAJ_EINVAL (bad options), NAJ_ENOMEM, NAJ_EDEVICE, NAJ_EBREAKDOWN, NAJ_ECANCELLED
+ * (naj_cancel; x, res->iterations and res->relres then describe the iterate the solve held).
  */
 naj_status naj_solve(naj_system *sys, const double *b, const double *x0, const naj_opts *opts, double *x,
                      naj_result *res, double *hist, int32_t hist_cap, int32_t *restart_log, int32_t log_cap,
@@ -213,7 +218,7 @@ naj_status naj_solve(naj_system *sys, const double *b, const double *x0, const n
  *   b, x0, opts, x, res, restart_log, log_cap, stream : as naj_solve
  * No residual history or trace is recorded (res->hist_len = 0).
  * Scratch: the solve's control block, barrier words, arrival counters and
- * per-workgroup partial sums live in one static device array of 172,032 bytes
+ * per-workgroup partial sums live in one static device array of 303,104 bytes
  * (partial sums for at most 4096 workgroups) that each device holds for the life of
  * the process; the iterates live in the system (allocated by naj_create_system).
  * Every call on a device shares that device's array and overwrites it, so calls that
@@ -226,6 +231,31 @@ naj_status naj_solve(naj_system *sys, const double *b, const double *x0, const n
  */
 naj_status naj_solve_noalloc(naj_system *sys, const double *b, const double *x0, const naj_opts *opts, double *x,
                              naj_result *res, int32_t *restart_log, int32_t log_cap, void *stream);
+
+/*
+ * Ask the solve running on `sys` (naj_solve or naj_solve_noalloc, called from another host
+ * thread) to stop.  This is the one call that may overlap another call on the same system.
+ * The solve's scalar control reads the request at a pass boundary, once every 64 passes (a
+ * read of host memory kept off the other passes), ends the solve after that pass's decision
+ * and returns NAJ_ECANCELLED with x = the float64 iterate it held (x^t as after the iteration
+ * cap; in mixed precision the refinement's current x), res->iterations and res->relres of
+ * that x.  A request that arrives while no solve runs is dropped when the next solve starts.
+ * Errors: NAJ_EINVAL for a NULL system or one owned by a server.
+ */
+naj_status naj_cancel(naj_system *sys);
+
+/*
+ * Attainable HBM rate of this GPU, for the measurement beside the published peak: a streaming
+ * kernel (16-byte non-temporal accesses, grid-stride, 8 workgroups of 256 threads per CU) over
+ * `bytes` bytes, launched once untimed and then `reps` times between HIP events on `stream`.
+ *   mode  : 0 reads src (dst must hold 16 bytes), 1 copies src to dst, 2 writes dst
+ *   src, dst : device buffers of `bytes` bytes (16-byte aligned; src unused in mode 2)
+ *   ms    : host, mean milliseconds per launch.  Bytes moved per launch: `bytes` (modes 0, 2) or
+ *           2 * `bytes` (mode 1).
+ * The call returns after the timed launches have finished.  Errors: NAJ_EINVAL, NAJ_EDEVICE.
+ */
+naj_status naj_bandwidth_probe(int32_t mode, const void *src, void *dst, int64_t bytes, int32_t reps,
+                               double *ms, void *stream);
 
 /*
  * Stand-alone kernels of the hot path, for measurement and tests.

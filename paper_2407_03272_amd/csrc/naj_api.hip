@@ -460,6 +460,74 @@ __global__ void k_reduce_fixed(const double* part, int G, double* out) {
   }
 }
 
+// Streaming probes of the attainable HBM rate (naj_bandwidth_probe): 16-byte accesses, a grid-stride
+// sweep with four independent accesses in flight per thread.  MODE 0 reads src (the xor of the words
+// is stored only if it equals a constant no real input produces, so the loads stay), 1 copies src to
+// dst, 2 writes dst.  NAJ_PROBE_NT selects non-temporal accesses, NAJ_PROBE_WG_PER_CU the grid.
+#ifndef NAJ_PROBE_NT
+#define NAJ_PROBE_NT 0
+#endif
+#ifndef NAJ_PROBE_WG_PER_CU
+#define NAJ_PROBE_WG_PER_CU 8
+#endif
+constexpr int kProbeBlock = 256;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ u32x4 probe_ld(const u32x4* p) {
+#if NAJ_PROBE_NT
+  return __builtin_nontemporal_load(p);
+#else
+  return *p;
+#endif
+}
+
+__device__ __forceinline__ void probe_st(u32x4* p, u32x4 v) {
+#if NAJ_PROBE_NT
+  __builtin_nontemporal_store(v, p);
+#else
+  *p = v;
+#endif
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(kProbeBlock) k_bw_probe(const u32x4* __restrict__ src, u32x4* __restrict__ dst,
+                                                          int64_t n16) {
+  const int64_t stride = (int64_t)gridDim.x * kProbeBlock;
+  int64_t i = (int64_t)blockIdx.x * kProbeBlock + threadIdx.x;
+  if constexpr (MODE == 0) {
+    uint32_t acc = 0;
+    for (; i + 3 * stride < n16; i += 4 * stride) {
+      const u32x4 a = probe_ld(src + i);
+      const u32x4 b = probe_ld(src + i + stride);
+      const u32x4 c = probe_ld(src + i + 2 * stride);
+      const u32x4 d = probe_ld(src + i + 3 * stride);
+      acc ^= (a.x ^ b.y ^ c.z ^ d.w) + (a.w ^ b.x ^ c.y ^ d.z);
+    }
+    for (; i < n16; i += stride) {
+      const u32x4 a = probe_ld(src + i);
+      acc ^= a.x ^ a.y ^ a.z ^ a.w;
+    }
+    if (acc == 0x9E3779B9u) dst[0] = u32x4{acc, acc, acc, acc};
+  } else if constexpr (MODE == 1) {
+    for (; i + 3 * stride < n16; i += 4 * stride) {
+      const u32x4 a = probe_ld(src + i);
+      const u32x4 b = probe_ld(src + i + stride);
+      const u32x4 c = probe_ld(src + i + 2 * stride);
+      const u32x4 d = probe_ld(src + i + 3 * stride);
+      probe_st(dst + i, a);
+      probe_st(dst + i + stride, b);
+      probe_st(dst + i + 2 * stride, c);
+      probe_st(dst + i + 3 * stride, d);
+    }
+    for (; i < n16; i += stride) probe_st(dst + i, probe_ld(src + i));
+  } else {
+    for (; i < n16; i += stride) {
+      const uint32_t v = (uint32_t)i;
+      probe_st(dst + i, u32x4{v, v + 1u, v + 2u, v + 3u});
+    }
+  }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------- system object
@@ -561,15 +629,15 @@ struct Pool {
 // device holds its own copy for the life of the process.  Host code must never pass `scratch`
 // itself to a kernel (that is a host-side stand-in): it takes the device address from
 // hipGetSymbolAddress once per device (noalloc_scratch) and uses that.
-constexpr size_t kNoAllocCtrlOff = 0;
+constexpr size_t kNoAllocCtrlOff = 0;       // two control blocks
 constexpr size_t kNoAllocBarOff = 1024;
 constexpr size_t kNoAllocScalOff = 1280;
 constexpr size_t kNoAllocCountersOff = 4096;
 constexpr size_t kNoAllocPartOff = kNoAllocCountersOff + sizeof(unsigned int) * kCounterWords;
 constexpr int kNoAllocMaxGrid = 4096;   // workgroups whose partial sums fit
-constexpr size_t kNoAllocBytes = kNoAllocPartOff + sizeof(double) * kPartStride * kNoAllocMaxGrid;
+constexpr size_t kNoAllocBytes = kNoAllocPartOff + 2 * sizeof(double) * kPartStride * kNoAllocMaxGrid;
 constexpr int kNoAllocMaxDevices = 64;
-static_assert(sizeof(Ctrl) <= kNoAllocBarOff - kNoAllocCtrlOff, "control block exceeds its scratch slot");
+static_assert(2 * sizeof(Ctrl) <= kNoAllocBarOff - kNoAllocCtrlOff, "control blocks exceed their scratch slot");
 static_assert(sizeof(Barrier) <= kNoAllocScalOff - kNoAllocBarOff, "barrier exceeds its scratch slot");
 static_assert(kNoAllocScalOff + 8 * sizeof(double) <= kNoAllocCountersOff, "reduction slot exceeds its scratch slot");
 static_assert(kNoAllocPartOff % 256 == 0, "partial sums must stay 256-byte aligned");
@@ -629,7 +697,8 @@ struct naj_system {
   int64_t bytes = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hipEvent_t evc[2] = {nullptr, nullptr};
-  int* hflag = nullptr;            // pinned host slots for the phase word
+  int* hflag = nullptr;            // pinned host words: [0], [1] the phase word of the chunks in flight,
+                                   // [2] the cancel word (naj_cancel), read by the solve's scalar control
   Pool* pool = nullptr;            // device memory source (null: the runtime allocator)
   bool lean = false;               // matrix only: no single-solve workspace (batch and server members)
 };
@@ -694,27 +763,37 @@ constexpr int kSmallBlock = 1024;
 // J of a system: its stored block inverse, the caller's D, or the row sums.
 int jm_of(const naj_system* s) { return s->jblock > 0 ? kJBlock : (s->dinv ? kJUser : kJRowSum); }
 
-template <bool YM>
+// Per-pass kernel instances: J mode, block size, momentum form, non-temporal matrix loads and the phases
+// of float64 (PS = kPhasesFp64) or mixed-precision (kPhasesMixed) solves.
+template <bool YM, int PS>
 const void* pass_kernel_ym(int jm, int bs) {
-  if (bs == 1024) return jm ? (const void*)k_pass64<kJUser, 1024, YM> : (const void*)k_pass64<kJRowSum, 1024, YM>;
-  if (bs == 512) return jm ? (const void*)k_pass64<kJUser, 512, YM> : (const void*)k_pass64<kJRowSum, 512, YM>;
-  return jm ? (const void*)k_pass64<kJUser, 256, YM> : (const void*)k_pass64<kJRowSum, 256, YM>;
+  if (bs == 1024)
+    return jm ? (const void*)k_pass64<kJUser, 1024, YM, false, PS> : (const void*)k_pass64<kJRowSum, 1024, YM, false, PS>;
+  if (bs == 512)
+    return jm ? (const void*)k_pass64<kJUser, 512, YM, false, PS> : (const void*)k_pass64<kJRowSum, 512, YM, false, PS>;
+  return jm ? (const void*)k_pass64<kJUser, 256, YM, false, PS> : (const void*)k_pass64<kJRowSum, 256, YM, false, PS>;
 }
 
-// A block-J system always uses the regular layout in the two-iterate form.  nt: the float64 iteration
-// passes load matrix entries non-temporally (instances for the 256-thread pass only).
-const void* pass_kernel(int jm, int bs, bool ym, bool nt = false) {
+template <int PS>
+const void* pass_kernel_ps(int jm, int bs, bool ym, bool nt) {
   if (nt && bs == 256) {
-    if (jm == kJBlock) return (const void*)k_pass64<kJBlock, 256, false, true>;
-    if (ym) return jm ? (const void*)k_pass64<kJUser, 256, true, true> : (const void*)k_pass64<kJRowSum, 256, true, true>;
-    return jm ? (const void*)k_pass64<kJUser, 256, false, true> : (const void*)k_pass64<kJRowSum, 256, false, true>;
+    if (jm == kJBlock) return (const void*)k_pass64<kJBlock, 256, false, true, PS>;
+    if (ym)
+      return jm ? (const void*)k_pass64<kJUser, 256, true, true, PS> : (const void*)k_pass64<kJRowSum, 256, true, true, PS>;
+    return jm ? (const void*)k_pass64<kJUser, 256, false, true, PS> : (const void*)k_pass64<kJRowSum, 256, false, true, PS>;
   }
   if (jm == kJBlock) {
-    if (bs == 1024) return (const void*)k_pass64<kJBlock, 1024, false>;
-    if (bs == 512) return (const void*)k_pass64<kJBlock, 512, false>;
-    return (const void*)k_pass64<kJBlock, 256, false>;
+    if (bs == 1024) return (const void*)k_pass64<kJBlock, 1024, false, false, PS>;
+    if (bs == 512) return (const void*)k_pass64<kJBlock, 512, false, false, PS>;
+    return (const void*)k_pass64<kJBlock, 256, false, false, PS>;
   }
-  return ym ? pass_kernel_ym<true>(jm, bs) : pass_kernel_ym<false>(jm, bs);
+  return ym ? pass_kernel_ym<true, PS>(jm, bs) : pass_kernel_ym<false, PS>(jm, bs);
+}
+
+// A block-J system always uses the regular layout in the two-iterate form.  nt: the iteration passes
+// load matrix entries non-temporally (instances for the 256-thread pass only).
+const void* pass_kernel(int jm, int bs, bool ym, bool nt, bool mixed) {
+  return mixed ? pass_kernel_ps<kPhasesMixed>(jm, bs, ym, nt) : pass_kernel_ps<kPhasesFp64>(jm, bs, ym, nt);
 }
 
 // LDS-resident single-workgroup solve: 32 n bytes of vectors must fit beside the kernel's own LDS.
@@ -962,6 +1041,7 @@ SolveArgs make_args(naj_system* s, const double* b, const naj_opts& o, const Sol
   a.r32 = s->fvec[4];
   a.nxcd = s->nxcd;
   a.spin_ticks = s->spin_ticks;
+  a.cancel = s->hflag ? s->hflag + 2 : nullptr;
   return a;
 }
 
@@ -1165,10 +1245,12 @@ naj_status build_layout(naj_system* s, const int32_t* rowptr, const int32_t* col
   return NAJ_OK;   // the temporaries are released by tmp's destructor
 }
 
-// Runs the solve kernels on `st` for the prepared control block; ev0/ev1 bracket them.
-naj_status run_solve(naj_system* s, SolveArgs& a, const naj_opts& o, hipStream_t st) {
+// Runs the solve kernels on `st` for the prepared control blocks; ev0/ev1 bracket them.  *final
+// receives the control block that holds the finished solve's state.
+naj_status run_solve(naj_system* s, SolveArgs& a, const naj_opts& o, hipStream_t st, Ctrl** final) {
   const int ud = jm_of(s);
   void* kargs[] = {&a};
+  *final = a.ctrl;
   if (s->mode == kModeSmall && !s->ymode && s->n <= kLdsMaxN && env_int("NAJ_LDS", 1)) {
     const void* fn = solve_lds_kernel(ud);
     const size_t bytes = (size_t)32 * s->n;
@@ -1191,22 +1273,31 @@ naj_status run_solve(naj_system* s, SolveArgs& a, const naj_opts& o, hipStream_t
     return NAJ_OK;
   }
   // one launch per pass, enqueued in chunks; the host checks the phase word of
-  // the previous chunk while the current one runs, so the device never waits
+  // the previous chunk while the current one runs, so the device never waits.  Launch k takes its
+  // index as an argument: it publishes its control state in ctrl[k & 1] (see k_pass64).
   const bool mx = o.precision == NAJ_MIXED;
-  const void* fn = pass_kernel(ud, mx ? s->pass_bs_mx : s->pass_bs, s->ymode != 0, mx ? s->nt_mx != 0 : s->nt != 0);
+  const void* fn = pass_kernel(ud, mx ? s->pass_bs_mx : s->pass_bs, s->ymode != 0, mx ? s->nt_mx != 0 : s->nt != 0, mx);
   const dim3 grid(mx ? s->grid_mx : s->grid), block(mx ? s->pass_bs_mx : s->pass_bs);
-  // passes: norm of b + iterations + confirmations (at most one per confirm_gap iterations, plus one)
+  // passes: norm of b + iterations + confirmations (at most one per confirm_gap iterations, plus one),
+  // and the launch that takes the last decision
   const int64_t max_pass = o.precision == NAJ_MIXED
-                               ? 2 + (int64_t)(o.max_refine + 1) * (1 + (int64_t)o.max_iter)
-                               : 2 + (int64_t)o.max_iter + (int64_t)o.max_iter / std::max(1, o.confirm_gap) + 1;
+                               ? 3 + (int64_t)(o.max_refine + 1) * (1 + (int64_t)o.max_iter)
+                               : 3 + (int64_t)o.max_iter + (int64_t)o.max_iter / std::max(1, o.confirm_gap) + 1;
   int64_t launched = 0;
   int chunk = 4, cur = 0, prev = -1;
+  int kidx = 0;
+  void* pargs[] = {&a, &kidx};
   HIP_TRY(hipEventRecord(s->ev0, st));
   for (;;) {
     const int64_t n_now = std::min<int64_t>(chunk, max_pass - launched);
-    for (int64_t i = 0; i < n_now; ++i) HIP_TRY(hipLaunchKernel(fn, grid, block, kargs, 0, st));
+    for (int64_t i = 0; i < n_now; ++i) {
+      const int64_t k = launched + i;
+      kidx = k == 0 ? 0 : 2 - (int)(k & 1);   // the kernel needs only k > 0 and the parity of k
+      HIP_TRY(hipLaunchKernel(fn, grid, block, pargs, 0, st));
+    }
     launched += n_now;
-    HIP_TRY(hipMemcpyAsync(&s->hflag[cur], &a.ctrl->phase, sizeof(int), hipMemcpyDeviceToHost, st));
+    *final = a.ctrl + ((launched - 1) & 1);
+    HIP_TRY(hipMemcpyAsync(&s->hflag[cur], &(*final)->phase, sizeof(int), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipEventRecord(s->evc[cur], st));
     if (prev >= 0) {
       HIP_TRY(hipEventSynchronize(s->evc[prev]));
@@ -1563,8 +1654,8 @@ static naj_status create_system_impl(int64_t n, int64_t nnz, const int32_t* rowp
   }
   if (!lean) {   // workspace of the single-solve drivers
     for (int i = 0; i < 3 + s->ymode; ++i) STEP(dev_alloc(s, &s->vec[i], (size_t)n));
-    STEP(dev_alloc(s, &s->part, (size_t)kPartStride * s->max_grid));
-    STEP(dev_alloc(s, &s->ctrl, 1));
+    STEP(dev_alloc(s, &s->part, (size_t)2 * kPartStride * s->max_grid));
+    STEP(dev_alloc(s, &s->ctrl, 2));
     STEP(dev_alloc(s, &s->bar, 1));
     STEP(dev_alloc(s, &s->counters, (size_t)kCounterWords));
     HSTEP(hipMemsetAsync(s->counters, 0, sizeof(unsigned int) * kCounterWords, st));
@@ -1573,7 +1664,8 @@ static naj_status create_system_impl(int64_t n, int64_t nnz, const int32_t* rowp
     HSTEP(hipEventCreate(&s->ev1));
     HSTEP(hipEventCreateWithFlags(&s->evc[0], hipEventDisableTiming));
     HSTEP(hipEventCreateWithFlags(&s->evc[1], hipEventDisableTiming));
-    HSTEP(hipHostMalloc((void**)&s->hflag, 2 * sizeof(int), hipHostMallocDefault));
+    HSTEP(hipHostMalloc((void**)&s->hflag, 4 * sizeof(int), hipHostMallocDefault));
+    for (int i = 0; i < 4; ++i) s->hflag[i] = 0;
   }
   HSTEP(hipStreamSynchronize(st));
   sys_free(s, flag);
@@ -1681,18 +1773,22 @@ static naj_status solve_impl(naj_system* s, const double* b, const double* x0, c
   if (!x0) HIP_TRY(hipMemsetAsync(s->vec[0], 0, sizeof(double) * s->n, st));
   hipLaunchKernelGGL(k_solve_init, dim3(1), dim3(64), 0, st, w.ctrl, w.bar, w.counters, o.k0, s->ymode);
   HIP_TRY(hipGetLastError());
+  // a cancel request applies to the solve that is running: one left from before this solve is dropped
+  // (the stream is idle here for this system's work: every entry point returns after its stream work)
+  __atomic_store_n(&s->hflag[2], 0, __ATOMIC_RELEASE);
   SolveArgs a = make_args(s, b_in, o, w);
   if (!hist || !may_alloc) a.hist = nullptr, a.hist_cap = 0;
   else a.hist_cap = std::min(hist_cap, s->hist_cap_dev);
   if (!trace || !may_alloc) a.trace = nullptr, a.trace_cap = 0;
   else a.trace_cap = std::min(trace_cap, s->trace_cap_dev);
-  rc = run_solve(s, a, o, st);
+  Ctrl* fin = nullptr;
+  rc = run_solve(s, a, o, st, &fin);
   if (rc != NAJ_OK) return rc;
-  hipLaunchKernelGGL(k_copy_result, dim3(blocks_for(s->n, kAux * 4)), dim3(kAux), 0, st, w.ctrl, s->vec[0],
+  hipLaunchKernelGGL(k_copy_result, dim3(blocks_for(s->n, kAux * 4)), dim3(kAux), 0, st, fin, s->vec[0],
                      s->vec[1], s->vec[2], x, s->perm, s->n);
   HIP_TRY(hipGetLastError());
   Ctrl hc;
-  HIP_TRY(hipMemcpyAsync(&hc, w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(&hc, fin, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   const int hl = std::min(hc.hist_len, a.hist_cap);
   if (a.hist && hl > 0) HIP_TRY(hipMemcpy(hist, s->hist, sizeof(double) * hl, hipMemcpyDeviceToHost));
@@ -1727,7 +1823,8 @@ static naj_status solve_impl(naj_system* s, const double* b, const double* x0, c
   res->objgap = __builtin_nan("");
   const bool obj = o.stop == NAJ_STOP_OBJECTIVE;
   if (obj && hc.status == ST_OK) res->objgap = hc.nb > 0.0 ? hc.relres : 0.0;
-  if ((obj || hc.status == ST_NOT_CONVERGED || hc.status == ST_BREAKDOWN) && hc.result >= 0 && hc.nb > 0.0) {
+  if ((obj || hc.status == ST_NOT_CONVERGED || hc.status == ST_BREAKDOWN || hc.status == ST_CANCELLED) &&
+      hc.result >= 0 && hc.nb > 0.0) {
     double rr = 0.0;   // residual of the returned iterate, in the solver's row order
     rc = residual_norm2(s, s->vec[hc.result], b_in, nullptr, &rr, st, false, w);
     if (rc != NAJ_OK) return rc;
@@ -1740,7 +1837,56 @@ static naj_status solve_impl(naj_system* s, const double* b, const double* x0, c
     }
   }
   if (hc.status == ST_BREAKDOWN) return fail(NAJ_EBREAKDOWN, "NaN/Inf in a reduction at iteration %d", hc.iterations);
+  if (hc.status == ST_CANCELLED) return fail(NAJ_ECANCELLED, "cancelled after %d passes", hc.passes);
   return (naj_status)hc.status;
+}
+
+naj_status naj_bandwidth_probe(int32_t mode, const void* src, void* dst, int64_t bytes, int32_t reps,
+                               double* ms, void* stream) {
+  g_err.clear();
+  (void)hipGetLastError();
+  if (mode < 0 || mode > 2) return fail(NAJ_EINVAL, "mode must be 0 (read), 1 (copy) or 2 (write)");
+  if (bytes < 16 || bytes % 16 != 0) return fail(NAJ_EINVAL, "bytes must be a positive multiple of 16");
+  if (reps < 1 || !ms) return fail(NAJ_EINVAL, "reps >= 1 and ms are required");
+  if ((mode != 2 && !src) || !dst) return fail(NAJ_EINVAL, "src (modes 0, 1) and dst are required");
+  if (((uintptr_t)src | (uintptr_t)dst) % 16 != 0) return fail(NAJ_EINVAL, "src and dst must be 16-byte aligned");
+  hipStream_t st = (hipStream_t)stream;
+  int dev = 0, cus = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const int64_t n16 = bytes / 16;
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * NAJ_PROBE_WG_PER_CU,
+                                                                 (n16 + kProbeBlock - 1) / kProbeBlock));
+  const u32x4* s4 = (const u32x4*)src;
+  u32x4* d4 = (u32x4*)dst;
+  auto launch = [&]() {
+    if (mode == 0) hipLaunchKernelGGL(k_bw_probe<0>, dim3(grid), dim3(kProbeBlock), 0, st, s4, d4, n16);
+    else if (mode == 1) hipLaunchKernelGGL(k_bw_probe<1>, dim3(grid), dim3(kProbeBlock), 0, st, s4, d4, n16);
+    else hipLaunchKernelGGL(k_bw_probe<2>, dim3(grid), dim3(kProbeBlock), 0, st, s4, d4, n16);
+  };
+  launch();   // warm-up
+  HIP_TRY(hipGetLastError());
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  HIP_TRY(hipEventRecord(e0, st));
+  for (int r = 0; r < reps; ++r) launch();
+  HIP_TRY(hipEventRecord(e1, st));
+  HIP_TRY(hipEventSynchronize(e1));
+  float t = 0.f;
+  const hipError_t e = hipEventElapsedTime(&t, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  HIP_TRY(e);
+  *ms = (double)t / reps;
+  return NAJ_OK;
+}
+
+naj_status naj_cancel(naj_system* s) {
+  if (!s) return fail(NAJ_EINVAL, "system is NULL");
+  if (!s->hflag) return fail(NAJ_EINVAL, "the system belongs to a server and has no single-solve state");
+  __atomic_store_n(&s->hflag[2], 1, __ATOMIC_RELEASE);
+  return NAJ_OK;
 }
 
 naj_status naj_solve(naj_system* s, const double* b, const double* x0, const naj_opts* opts, double* x,

@@ -56,7 +56,11 @@ __device__ __forceinline__ T mat_ld(const T* p) {
 // PH_RESID64 and PH_INNER32 belong to the mixed-precision refinement loop.
 enum Phase : int { PH_NORMB = 0, PH_ITER = 1, PH_CONFIRM = 2, PH_DONE = 3, PH_RESID64 = 4, PH_INNER32 = 5 };
 
-enum : int { ST_OK = 0, ST_NOT_CONVERGED = 1, ST_EDEVICE = -3, ST_BREAKDOWN = -4 };
+enum : int { ST_OK = 0, ST_NOT_CONVERGED = 1, ST_EDEVICE = -3, ST_BREAKDOWN = -4, ST_CANCELLED = -5 };
+
+// The scalar control reads the caller's cancel word once every this many passes (a read of host
+// memory, kept off all other passes).
+constexpr int kCancelEvery = 64;
 
 constexpr int kRestartLogCap = 64;
 
@@ -182,8 +186,8 @@ struct SolveArgs {
   double* buf1;
   double* buf2;
   double* buf3;               // materialized form: the second y buffer
-  double* part;               // [3 * G]
-  Ctrl* ctrl;
+  double* part;               // [2][G][kPartStride] (the single-launch drivers use the first half)
+  Ctrl* ctrl;                 // [2]: the per-pass driver's states after even / odd launches
   Barrier* bar;
   unsigned int* counters;     // [kCounterWords], zero between passes
   double* hist;
@@ -211,6 +215,7 @@ struct SolveArgs {
   int ypar;                   // materialized form in the float32 inner phase: the two y buffers alternate
                               // with the pass count (batches: every right-hand side of a system reads y
                               // from the same buffer in a pass)
+  const int* cancel;          // host-visible cancel word of the solve (nonzero: stop), or null
 };
 
 // How a pass forms y^t and whether it writes y^{t+1}.
@@ -708,11 +713,8 @@ __device__ __forceinline__ void block_sum3(double& a, double& b, double& c, doub
   }
 }
 
-// s_waitcnt vmcnt(0): every vector memory operation this wave issued, stores
-// included, has completed (gfx9-family encoding: expcnt and lgkmcnt left at max).
-__device__ __forceinline__ void wait_stores_complete() { __builtin_amdgcn_s_waitcnt(0x0F70); }
-
-// Per-workgroup partial sums live at part[4*w + k], k = 0, 1, 2 (32 B per workgroup).
+// Per-workgroup partial sums live at part[4*w + k], k = 0, 1, 2 (32 B per workgroup); the per-pass
+// driver keeps two such arrays, for launches of even and odd index.
 constexpr int kPartStride = 4;
 
 // Sums of the G workgroups' partials in a fixed order (lane l adds slots l, l+64, ...

@@ -102,7 +102,7 @@ __device__ inline void apply_step(const SolveArgs& a, Ctrl* c, bool restart) {
 
 // Mixed precision, after a float64 residual pass (refinement step k = c->outer):
 // accept x, give up, or start a float32 inner solve of Q d = fl32(r) from d = 0.
-__device__ inline void mixed_after_residual(const SolveArgs& a, Ctrl* c, double rr, double r32sq) {
+__device__ inline void mixed_after_residual(const SolveArgs& a, Ctrl* c, double rr, double r32sq, bool side) {
   if (c->update) {               // the pass wrote x + d into iXn: it is the current iterate now
     const int t = c->iX;
     c->iX = c->iXn;
@@ -112,7 +112,7 @@ __device__ inline void mixed_after_residual(const SolveArgs& a, Ctrl* c, double 
   const int k = c->outer;
   const double rho = sqrt(rr) / c->nb;
   c->outer = k + 1;
-  if (a.hist && k < a.hist_cap) a.hist[k] = rho;
+  if (side && a.hist && k < a.hist_cap) a.hist[k] = rho;
   c->hist_len = k + 1;
   c->relres = rho;
   c->result = c->iX;
@@ -155,9 +155,9 @@ __device__ inline void mixed_after_residual(const SolveArgs& a, Ctrl* c, double 
   c->phase = PH_INNER32;
 }
 
-__device__ inline void mixed_finish_inner(const SolveArgs& a, Ctrl* c, int d_buf, int its) {
+__device__ inline void mixed_finish_inner(const SolveArgs& a, Ctrl* c, int d_buf, int its, bool side) {
   const int k = c->outer - 1;
-  if (a.trace && k < a.trace_cap) {
+  if (side && a.trace && k < a.trace_cap) {
     a.trace[2 * k] = (double)its;
     a.trace[2 * k + 1] = (double)c->ell;
   }
@@ -170,7 +170,7 @@ __device__ inline void mixed_finish_inner(const SolveArgs& a, Ctrl* c, int d_buf
 
 // Mixed precision, after a float32 inner pass: the inner solve's stop test, then
 // the restart test and the restart/momentum branches of Algorithm 2.
-__device__ inline void mixed_after_inner(const SolveArgs& a, Ctrl* c, double s, double gg, double sabs) {
+__device__ inline void mixed_after_inner(const SolveArgs& a, Ctrl* c, double s, double gg, double sabs, bool side) {
   (void)sabs;
   const int t = c->t;
   const double mon = sqrt(gg) / c->nr;
@@ -181,7 +181,7 @@ __device__ inline void mixed_after_inner(const SolveArgs& a, Ctrl* c, double s, 
     return;
   }
   if (mon <= a.inner_tol) {
-    mixed_finish_inner(a, c, c->iW, t);     // d = x^t
+    mixed_finish_inner(a, c, c->iW, t, side);     // d = x^t
     return;
   }
   if (mon <= 0.9 * c->best_mon) {
@@ -191,7 +191,7 @@ __device__ inline void mixed_after_inner(const SolveArgs& a, Ctrl* c, double s, 
   // the stall test applies once the monitor has halved (before that a plateau is the slow
   // start on a smooth right-hand side, not the float32 rounding level)
   if (a.inner_stall > 0 && c->best_mon <= kStallArm && t - c->best_t >= a.inner_stall) {
-    mixed_finish_inner(a, c, c->iW, t);     // stalled at the float32 rounding level: d = x^t
+    mixed_finish_inner(a, c, c->iW, t, side);     // stalled at the float32 rounding level: d = x^t
     return;
   }
   const bool restart = a.restart && (t > c->K_re + c->K) && (s >= 0.0);
@@ -224,14 +224,42 @@ __device__ inline void mixed_after_inner(const SolveArgs& a, Ctrl* c, double s, 
     else ymode_plan_next(c);
   }
   if (t >= a.max_iter) {
-    mixed_finish_inner(a, c, c->iP, a.max_iter);   // d = the last iterate
+    mixed_finish_inner(a, c, c->iP, a.max_iter, side);   // d = the last iterate
     return;
   }
   c->t = t + 1;
 }
 
-// The decision after a pass, from its three reduced sums.  One thread runs it.
-__device__ inline void control_update(const SolveArgs& a, Ctrl* c, double r0, double r1, double r2) {
+// A cancel request (a nonzero word in host-visible memory, written by the caller's host thread) ends the
+// solve at the pass boundary where it is seen, after that pass's decision: the result is the float64
+// iterate the solve holds (x^{t-1} role, or the refinement's current x), as for the iteration cap.
+__device__ inline void check_cancel(const SolveArgs& a, Ctrl* c) {
+  if (!a.cancel || c->phase == PH_DONE || (c->passes % kCancelEvery) != 0) return;
+  if (__hip_atomic_load(a.cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) == 0) return;
+  c->status = ST_CANCELLED;
+  if (a.precision) {
+    c->result = c->iX;
+  } else {
+    c->result = c->iP;
+    c->iterations = c->t - 1;
+  }
+  c->relres = __builtin_nan("");
+  c->phase = PH_DONE;
+}
+
+__device__ inline void control_update_pass(const SolveArgs& a, Ctrl* c, double r0, double r1, double r2, bool side);
+
+// The decision after a pass, from its three reduced sums, then the cancel check.  One thread runs
+// it.  With side false only the control state is updated: the residual history, the trace and the
+// cancel word are left to the one copy of the decision whose state is published (see k_pass64).
+__device__ inline void control_update(const SolveArgs& a, Ctrl* c, double r0, double r1, double r2,
+                                      bool side = true) {
+  control_update_pass(a, c, r0, r1, r2, side);
+  if (side) check_cancel(a, c);
+}
+
+// The decision after a pass, from its three reduced sums.
+__device__ inline void control_update_pass(const SolveArgs& a, Ctrl* c, double r0, double r1, double r2, bool side) {
   const int phase = c->phase;
   c->passes += 1;
   if (phase == PH_NORMB) {
@@ -254,11 +282,11 @@ __device__ inline void control_update(const SolveArgs& a, Ctrl* c, double r0, do
     return;
   }
   if (phase == PH_RESID64) {
-    mixed_after_residual(a, c, r0, r1);
+    mixed_after_residual(a, c, r0, r1, side);
     return;
   }
   if (phase == PH_INNER32) {
-    mixed_after_inner(a, c, r0, r1, r2);
+    mixed_after_inner(a, c, r0, r1, r2, side);
     return;
   }
   if (phase == PH_ITER) {
@@ -266,8 +294,8 @@ __device__ inline void control_update(const SolveArgs& a, Ctrl* c, double r0, do
     const double s = r0, gg = r1, sabs = r2;
     // monitor at y^t: relative residual, or relative objective gap (gg then holds f(y^t))
     const double mon = a.stop_obj ? fabs(gg - a.fstar) / a.fscale : sqrt(gg) / c->nb;
-    if (a.hist && t - 1 < a.hist_cap) a.hist[t - 1] = mon;
-    if (a.trace && t - 1 < a.trace_cap) {
+    if (side && a.hist && t - 1 < a.hist_cap) a.hist[t - 1] = mon;
+    if (side && a.trace && t - 1 < a.trace_cap) {
       a.trace[2 * (t - 1)] = s;
       a.trace[2 * (t - 1) + 1] = sabs;
     }
@@ -359,12 +387,19 @@ __device__ __forceinline__ void pass_resid64(const Sell& A, int nxcd, const doub
   for (int64_t s = wr.first; s < wr.end; s += wr.step) resid_slice(A, s, lane, X, b, out, p0, obj);
 }
 
+// Phases a kernel instance carries (template parameter PS of run_pass and k_pass64): every phase, or
+// those of float64 solves only (norm of b, iteration, confirmation), or those of mixed-precision solves
+// only (norm of b, float64 residual, float32 inner pass).  An instance's register budget is that of
+// the heaviest phase it carries.
+constexpr int kPhasesAll = 0, kPhasesFp64 = 1, kPhasesMixed = 2;
+
 // The workgroup's share of one pass; partial sums in p0..p2 (per thread).
-template <int JM, int BS, bool YM, bool NT = false>
+template <int JM, int BS, bool YM, bool NT = false, int PS = kPhasesAll>
 __device__ __forceinline__ void run_pass(const SolveArgs& a, const PassView& v, double& p0, double& p1,
                                          double& p2) {
   const int lane = threadIdx.x % kWave;
-  if (v.phase == PH_ITER) {
+  constexpr bool F64 = PS != kPhasesMixed, MX = PS != kPhasesFp64;
+  if (F64 && v.phase == PH_ITER) {
     Momentum<double> m;
     m.R = pick(a, v.iR);
     m.Yn = (YM && v.iYn >= 0) ? pick(a, v.iYn) : nullptr;
@@ -373,9 +408,9 @@ __device__ __forceinline__ void run_pass(const SolveArgs& a, const PassView& v, 
     m.bz = v.bz != 0;
     m.ym = YM;
     pass_iter64<JM, BS, YM, NT>(a, pick(a, v.iP), m, pick(a, v.iW), p0, p1, p2);
-  } else if (v.phase == PH_CONFIRM) {
+  } else if (F64 && v.phase == PH_CONFIRM) {
     pass_resid64<BS>(a.A, a.nxcd, pick(a, v.iW), a.b, nullptr, p0, a.stop_obj != 0);
-  } else if (v.phase == PH_INNER32) {
+  } else if (MX && v.phase == PH_INNER32) {
     const float* P = pickf(a, v.iP);
     float* W = pickf(a, v.iW);
     Momentum<float> m;
@@ -391,7 +426,7 @@ __device__ __forceinline__ void run_pass(const SolveArgs& a, const PassView& v, 
       for (int64_t r = lr.first; r < a.A.n_long; r += lr.step) inner_long<JM, YM, NT>(a, r, lane, P, m, W, zp, p0, p1, p2);
     const WaveRange wr = wave_range<BS>(a.A, a.nxcd);
     for (int64_t s = wr.first; s < wr.end; s += wr.step) inner_slice<JM, YM, NT>(a, s, lane, P, m, W, zp, p0, p1, p2);
-  } else if (v.phase == PH_RESID64) {
+  } else if (MX && v.phase == PH_RESID64) {
     const double* X = pick(a, v.iX);
     const float* D = v.update ? pickf(a, v.iD) : nullptr;
     double* Xn = v.update ? pick(a, v.iXn) : nullptr;
@@ -399,7 +434,7 @@ __device__ __forceinline__ void run_pass(const SolveArgs& a, const PassView& v, 
     for (int64_t r = lr.first; r < a.A.n_long; r += lr.step) resid_mixed_long(a, r, lane, X, D, Xn, p0, p1);
     const WaveRange wr = wave_range<BS>(a.A, a.nxcd);
     for (int64_t s = wr.first; s < wr.end; s += wr.step) resid_mixed_slice(a, s, lane, X, D, Xn, p0, p1);
-  } else {  // PH_NORMB: every row, flat
+  } else if (v.phase == PH_NORMB) {  // every row, flat
     for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < a.A.n; i += (int64_t)gridDim.x * BS) {
       const double x = a.b[i];
       p0 = p0 + x * x;
@@ -407,58 +442,87 @@ __device__ __forceinline__ void run_pass(const SolveArgs& a, const PassView& v, 
   }
 }
 
-// One pass per launch.  The last workgroup to finish reduces the partials and
-// updates the control block for the next launch; launches after the solve has
-// finished return at once.
-template <int JM, int BS, bool YM, bool NT = false>
-__global__ void __launch_bounds__(BS) k_pass64(SolveArgs a) {
+// Sums of the G per-workgroup partial sums of a pass, in a fixed order: thread i adds slots i, i + BS,
+// i + 2 BS, ... in turn (four slots' loads issued together), then the workgroup's threads are combined
+// by block_sum3.  Every workgroup that runs it gets the same three values (in thread 0).
+template <int BS>
+__device__ __forceinline__ void block_part_sum(const double* __restrict__ part, int G, double& r0, double& r1,
+                                               double& r2, double (*sh)[BS / kWave]) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  int i = threadIdx.x;
+  for (; i + 3 * BS < G; i += 4 * BS) {
+    double v[4][3];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) v[q][k] = part[(size_t)(i + q * BS) * kPartStride + k];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      s0 = s0 + v[q][0];
+      s1 = s1 + v[q][1];
+      s2 = s2 + v[q][2];
+    }
+  }
+  for (; i < G; i += BS) {
+    const double* p = part + (size_t)i * kPartStride;
+    const double a0 = p[0], a1 = p[1], a2 = p[2];
+    s0 = s0 + a0;
+    s1 = s1 + a1;
+    s2 = s2 + a2;
+  }
+  r0 = s0;
+  r1 = s1;
+  r2 = s2;
+  block_sum3<BS>(r0, r1, r2, sh);
+}
+
+// One pass per launch; launch k of a solve (k = 0, 1, ...) runs pass k.  The scalar decision after
+// pass k-1 is taken at the start of launch k by every workgroup, each from the same two inputs: the
+// control state C_{k-1} (in ctrl[(k-1) & 1]; launch 0 reads the initial state from ctrl[1]) and the
+// per-workgroup partial sums of pass k-1 (in the half (k-1) & 1 of part), added in one fixed order.
+// So every workgroup reaches the same state C_k without waiting for any other workgroup of its own
+// launch: the kernel boundary between launches k-1 and k is the only synchronization.  Workgroup 0
+// alone publishes C_k into ctrl[k & 1] (read by launch k+1 and by the host) and writes the residual
+// history, the trace and the cancel decision.  A cancel therefore reaches only workgroup 0's copy
+// of C_k; the other workgroups may still run pass k, into buffers that are not the result, and
+// launch k+1 reads the published state.  Launches after the solve has finished copy the finished
+// state forward and return.
+// The launch passes k itself for k < 3 and any value of the same parity above 0 beyond (only k > 0
+// and k & 1 matter).
+template <int JM, int BS, bool YM, bool NT = false, int PS = kPhasesAll>
+__global__ void __launch_bounds__(BS) k_pass64(SolveArgs a, int k) {
   __shared__ double sh[3][BS / kWave];
   __shared__ PassView v;
-  __shared__ int s_last;
-  if (threadIdx.x == 0) load_view(a.ctrl, &v);
-  __syncthreads();
-  if (v.phase == PH_DONE) return;
-  double p0 = 0.0, p1 = 0.0, p2 = 0.0;
-  run_pass<JM, BS, YM, NT>(a, v, p0, p1, p2);
-  block_sum3<BS>(p0, p1, p2, sh);
+  __shared__ Ctrl c;
   const int G = gridDim.x;
+  const int prev = (k + 1) & 1;
+  {
+    const uint32_t* src = (const uint32_t*)(a.ctrl + prev);
+    uint32_t* dst = (uint32_t*)&c;
+    for (int i = threadIdx.x; i < (int)(sizeof(Ctrl) / 4); i += BS) dst[i] = src[i];
+  }
+  double r0 = 0.0, r1 = 0.0, r2 = 0.0;
+  if (k > 0) block_part_sum<BS>(a.part + (size_t)prev * G * kPartStride, G, r0, r1, r2, sh);
+  __syncthreads();
   if (threadIdx.x == 0) {
-    // Partials are written through to the agent coherence point (agent-scope
-    // atomic stores) and must have completed before the arrival is counted;
-    // the last arriver reads them back with agent-scope atomic loads.  No L2
-    // writeback/invalidate is needed for them; the vector writes reach the
-    // next pass through the kernel boundary.
-    double* slot = a.part + (size_t)blockIdx.x * kPartStride;
-    __hip_atomic_store(slot + 0, p0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(slot + 1, p1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(slot + 2, p2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    wait_stores_complete();
-    // two-level arrival count: workgroups of one L2 domain count on their own
-    // counter; the domain's last arriver counts on the top counter
-    const int nd = effective_domains(G, a.nxcd);
-    const int dom = blockIdx.x % nd;
-    unsigned int* dc = a.counters + (size_t)dom * kCounterStride;
-    unsigned int* tc = a.counters + (size_t)kMaxDomains * kCounterStride;
-    int last = 0;
-    const unsigned int o1 = __hip_atomic_fetch_add(dc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (o1 == (unsigned int)(G / nd - 1)) {
-      __hip_atomic_store(dc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const unsigned int o2 = __hip_atomic_fetch_add(tc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (o2 == (unsigned int)(nd - 1)) {
-        __hip_atomic_store(tc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        last = 1;
-      }
-    }
-    s_last = last;
+    if (k > 0 && c.phase != PH_DONE) control_update(a, &c, r0, r1, r2, blockIdx.x == 0);
+    load_view(&c, &v);
   }
   __syncthreads();
-  if (s_last && threadIdx.x < kWave) {
-    const int lane = threadIdx.x;
-    // drop stale L2 copies of the partials (written through by other domains), then read them in bulk
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    double r0, r1, r2;
-    grid_sum3(a.part, G, lane, r0, r1, r2);
-    if (lane == 0) control_update(a, a.ctrl, r0, r1, r2);
+  if (blockIdx.x == 0) {
+    const uint32_t* src = (const uint32_t*)&c;
+    uint32_t* dst = (uint32_t*)(a.ctrl + (k & 1));
+    for (int i = threadIdx.x; i < (int)(sizeof(Ctrl) / 4); i += BS) dst[i] = src[i];
+  }
+  if (v.phase == PH_DONE) return;
+  double p0 = 0.0, p1 = 0.0, p2 = 0.0;
+  run_pass<JM, BS, YM, NT, PS>(a, v, p0, p1, p2);
+  block_sum3<BS>(p0, p1, p2, sh);
+  if (threadIdx.x == 0) {
+    double* slot = a.part + ((size_t)(k & 1) * G + blockIdx.x) * kPartStride;
+    slot[0] = p0;
+    slot[1] = p1;
+    slot[2] = p2;
   }
 }
 
@@ -544,10 +608,13 @@ __global__ void __launch_bounds__(BS) k_solve64(SolveArgs a) {
   }
 }
 
-// Clears the control block, the barrier and the arrival counters before a solve.
-__global__ void k_solve_init(Ctrl* c, Barrier* bar, unsigned int* counters, int k0, int ymode) {
+// Clears the control blocks, the barrier and the arrival counters before a solve.  ctrl[0] and
+// ctrl[1] both receive the initial state: the single-launch drivers use ctrl[0]; the per-pass driver
+// reads the state before its first launch from ctrl[1].
+__global__ void k_solve_init(Ctrl* ctrl, Barrier* bar, unsigned int* counters, int k0, int ymode) {
   for (int i = threadIdx.x; i <= kMaxDomains; i += blockDim.x) counters[(size_t)i * kCounterStride] = 0u;
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
+  if (threadIdx.x < 2 && blockIdx.x == 0) {
+    Ctrl* c = ctrl + threadIdx.x;
     c->alpha = 1.0;
     c->beta = 0.0;
     c->nb = 0.0;
@@ -589,9 +656,11 @@ __global__ void k_solve_init(Ctrl* c, Barrier* bar, unsigned int* counters, int 
       ymode_plan_next(c);
     }
     for (int i = 0; i < kRestartLogCap; ++i) c->restart_log[i] = 0;
-    bar->count = 0ULL;
-    bar->epoch_done = 0u;
-    bar->pad = 0u;
+    if (threadIdx.x == 0) {
+      bar->count = 0ULL;
+      bar->epoch_done = 0u;
+      bar->pad = 0u;
+    }
   }
 }
 

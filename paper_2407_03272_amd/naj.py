@@ -27,6 +27,7 @@ NAJ_EINVAL = -1
 NAJ_ENOMEM = -2
 NAJ_EDEVICE = -3
 NAJ_EBREAKDOWN = -4
+NAJ_ECANCELLED = -5
 NAJ_EBUSY = -6
 NAJ_FP64 = 0
 NAJ_MIXED = 1
@@ -76,6 +77,8 @@ _SIGS = {
                                  _P, _I32, _P, _I32, _P]),
     "naj_solve_noalloc": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(NajOpts), _P, ctypes.POINTER(NajResult), _P,
                                          _I32, _P]),
+    "naj_cancel": (ctypes.c_int, [_P]),
+    "naj_bandwidth_probe": (ctypes.c_int, [_I32, _P, _P, _I64, _I32, ctypes.POINTER(_D), _P]),
     "naj_step": (ctypes.c_int, [_P, _P, _P, _D, _P, _P, _P, _P]),
     "naj_residual": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "naj_diagonal": (ctypes.c_int, [_P, _P, _P]),
@@ -132,6 +135,7 @@ def load(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build the HIP library first (python -m paper_2407_03272_amd.build "
                            "or __graft_entry__.build())")
+    _torch()   # torch's HIP runtime is set up first: the library shares it (device memory, streams)
     lib = ctypes.CDLL(path)
     for name, (res, args) in _SIGS.items():
         fn = getattr(lib, name)
@@ -277,13 +281,17 @@ class System:
                                rlog.ctypes.data_as(_P), 64,
                                tr.ctypes.data_as(_P) if trace else None, cap if trace else 0,
                                _stream_ptr(stream))
-        if st < 0 and st != NAJ_EBREAKDOWN:
+        if st < 0 and st not in (NAJ_EBREAKDOWN, NAJ_ECANCELLED):
             _check(st)
         info = SolveInfo(res.status, res.iterations, res.restarts, res.confirmations, res.relres,
                          hist[:res.hist_len].copy(), rlog[:res.nrestart_log].tolist(),
                          tr[:res.hist_len].copy() if trace else np.zeros((0, 2)),
                          res.kernel_ms, res.passes, res.grid, res.objgap)
         return x, info
+
+    def cancel(self):
+        """naj_cancel: ask the solve running on this system (in another thread) to stop."""
+        _check(load().naj_cancel(self._h))
 
     def solve_noalloc(self, b, x0=None, *, out=None, stream=None, **opts) -> tuple:
         """naj_solve_noalloc: the same solve with its scratch in the library's static device array
@@ -299,7 +307,7 @@ class System:
         with torch.cuda.device(self.device):
             st = lib.naj_solve_noalloc(self._h, _ptr(b), _ptr(x0), ctypes.byref(o), _ptr(x), ctypes.byref(res),
                                        rlog.ctypes.data_as(_P), 64, _stream_ptr(stream))
-        if st < 0 and st != NAJ_EBREAKDOWN:
+        if st < 0 and st not in (NAJ_EBREAKDOWN, NAJ_ECANCELLED):
             _check(st)
         info = SolveInfo(res.status, res.iterations, res.restarts, res.confirmations, res.relres,
                          np.zeros(0), rlog[:res.nrestart_log].tolist(), np.zeros((0, 2)),
@@ -420,6 +428,25 @@ def autotune_tiles(system: System, nrhs: int, passes: int = 20, stream=None, **o
         _check(load().naj_autotune_tiles(system._h, int(nrhs), ctypes.byref(o), int(passes), _stream_ptr(stream),
                                          ctypes.byref(best)))
     return best.value
+
+
+def bandwidth_probe(mode: int, nbytes: int = 1 << 30, reps: int = 20, device="cuda:0", stream=None) -> dict:
+    """naj_bandwidth_probe on fresh buffers of `nbytes`: mode 0 read, 1 copy, 2 write.  Returns the mean
+    milliseconds per launch and the rate in GB/s (bytes moved per launch / time)."""
+    torch = _torch()
+    dev = torch.device(device)
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev) if mode != 2 else None
+    dst = torch.empty(nbytes // 8 if mode != 0 else 2, dtype=torch.float64, device=dev)
+    ms = _D()
+    with torch.cuda.device(dev):
+        _check(load().naj_bandwidth_probe(int(mode), _ptr(src), _ptr(dst), int(nbytes), int(reps), ctypes.byref(ms),
+                                          _stream_ptr(stream)))
+    moved = nbytes * (2 if mode == 1 else 1)
+    out = {"mode": ("read", "copy", "write")[mode], "bytes_per_launch": moved, "ms": ms.value,
+           "gbps": moved / (ms.value / 1e3) / 1e9}
+    if mode == 1:
+        out["copy_exact"] = bool(torch.equal(src, dst))
+    return out
 
 
 def tune_save(path: str):

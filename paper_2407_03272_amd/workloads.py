@@ -396,20 +396,26 @@ def fe_batch(nsys: int = 512, n_lo: float = 1e3, n_hi: float = 2e5, seed: int = 
         return list(ex.map(_fe_from_spec, specs, chunksize=4))
 
 
-def serve_trace(nreq: int, seed: int = 1005, rate: float = 200.0, fe_pool: int = 128, workers: int = 8):
+def serve_trace(nreq: int, seed: int = 1005, rate: float = 200.0, fe_pool: int | None = None, workers: int = 8):
     """Request trace of the serving workload: Poisson arrivals at `rate` per second; 70% P1
-    finite-element systems drawn from the first `fe_pool` members of the batch generator
-    (seed 1004), 30% 3D 7-point Dirichlet Laplacians with m ~ U{16..100} per side; one
-    right-hand side each, N(0,1); tolerance 1e-6 or 1e-8 with probability 1/2 each."""
+    finite-element systems drawn from the batch generator's distribution (sizes log-uniform in
+    [1e3, 2e5], 2D or 3D, lognormal coefficients), each request its own independent draw (seed
+    derived from `seed`; with `fe_pool` set, draws from the first `fe_pool` members of the batch
+    instead); 30% 3D 7-point Dirichlet Laplacians with m ~ U{16..100} per side; one right-hand side
+    each, N(0,1); tolerance 1e-6 or 1e-8 with probability 1/2 each."""
     from concurrent.futures import ProcessPoolExecutor
     rng = np.random.default_rng(seed)
     arr = np.cumsum(rng.exponential(1.0 / rate, nreq))
     kind = rng.random(nreq) < 0.7
-    fe_idx = rng.integers(0, fe_pool, nreq)
     ms = rng.integers(16, 101, nreq)
     tols = np.where(rng.random(nreq) < 0.5, 1e-6, 1e-8)
     bseeds = rng.integers(0, 2 ** 31 - 1, nreq)
-    specs = fe_batch_specs(512, 1e3, 2e5, 1004)
+    if fe_pool is None:
+        specs = fe_batch_specs(nreq, 1e3, 2e5, seed + 1)    # one independent system per request index
+        fe_idx = np.arange(nreq)
+    else:
+        fe_idx = rng.integers(0, fe_pool, nreq)
+        specs = fe_batch_specs(512, 1e3, 2e5, 1004)
     need = sorted(set(int(k) for k, f in zip(fe_idx, kind) if f))
     with ProcessPoolExecutor(max_workers=max(1, workers)) as ex:
         fe_sys = dict(zip(need, ex.map(_fe_from_spec, [(*specs[k], 1) for k in need], chunksize=2)))

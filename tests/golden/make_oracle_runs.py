@@ -1,9 +1,12 @@
 """Writes oracle_runs.json: the CPU oracle's complete runs on the two Laplacian
 workloads (2D 64x64 Poisson, 3D 128^3 Laplacian), so GPU tests at full size can
-compare without re-running the slow oracle.  Calls only oracle/ and the seeded
+compare without re-running the slow oracle: iterations, restarts, confirmations,
+the monitor history, sampled entries of x and the SHA-256 of the whole x (its
+float64 values, little-endian, in row order).  Calls only oracle/ and the seeded
 input generators.  Run from the repository root (takes about a minute):
     python tests/golden/make_oracle_runs.py
 """
+import hashlib
 import json
 import os
 import sys
@@ -26,7 +29,8 @@ def run(name, sysobj, **kw):
     idx = np.sort(rng.choice(sysobj.n, size=min(NSAMPLE, sysobj.n), replace=False))
     return {"name": name, "opts": kw, "n": sysobj.n, "nnz": sysobj.nnz, "iterations": r.iterations,
             "status": r.status, "restarts": r.restarts, "confirms": r.confirms, "relres": r.relres,
-            "hist": r.hist, "sample_idx": idx.tolist(), "sample_x": r.x[idx].tolist()}
+            "hist": r.hist, "sample_idx": idx.tolist(), "sample_x": r.x[idx].tolist(),
+            "x_sha256": hashlib.sha256(np.ascontiguousarray(r.x, dtype="<f8").tobytes()).hexdigest()}
 
 
 def main():

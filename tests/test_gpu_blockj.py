@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+import tie_rule as TR
 from paper_2407_03272_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -92,13 +93,10 @@ def test_block_step_matches_oracle(naj, case, beta):
     sysm.close()
 
 
-def _near_tie_ok(orc, gpu_info, n):
-    eps = np.finfo(float).eps
-    diff = sorted(set(orc.restarts) ^ set(gpu_info.restart_log))
-    if not diff:
-        return True
-    t = diff[0]
-    return abs(orc.s_log[t - 1]) <= 64 * n * eps * orc.sabs_log[t - 1]
+# The GPU applies the inverse blocks from its own Cholesky factor, the oracle an LU solve of each block,
+# so the iterates agree to rounding only: the restart inner products must agree to 1e-6 of sum|g_i d_i|
+# (tie_rule), and a decision that differs must be a tie.
+AGREE_BLOCK = 1e-6
 
 
 def _compare_block_solve(naj, rowptr, colidx, vals, b, nb, *, rtol=1e-10, **kw):
@@ -106,9 +104,11 @@ def _compare_block_solve(naj, rowptr, colidx, vals, b, nb, *, rtol=1e-10, **kw):
     orc = O.accelerated_jacobi(rowptr, colidx, vals, b, jblock=nb, **kw)
     sysm = naj.System(rowptr, colidx, vals, jblock=nb)
     x, info = sysm.solve(b, trace=True, **kw)
-    if info.restart_log != orc.restarts[:64]:
-        assert _near_tie_ok(orc, info, n), (info.restart_log, orc.restarts)
+    if info.restart_log != orc.restarts[:64] or info.iterations != orc.iterations:
         orc = O.accelerated_jacobi(rowptr, colidx, vals, b, jblock=nb, forced_restarts=info.restart_log, **kw)
+    ties = TR.check_decisions(orc, info.restart_log, info.trace, n, k0=kw.get("k0", 2), agree=AGREE_BLOCK)
+    _say(f"  decisions checked over {len(orc.s_log)} iterations, ties {ties}, largest |s_gpu - s|/sum|gd| "
+         f"{TR.max_sum_difference(orc, info.trace):.2e}")
     assert info.status == orc.status == O.STATUS_OK
     assert info.iterations == orc.iterations, (info.iterations, orc.iterations)
     xg = x.cpu().numpy()

@@ -1,8 +1,11 @@
 """Parity at the benchmark workloads' full sizes, in the configuration bench.py times.
 
 * Chung-Lu graph Laplacian, n = 2^22 (sorted layout, long rows): the complete float64 solve against the
-  oracle (the same restart schedule unless a restart test is a numerical tie, iterates within 1e-10), and the
-  mixed solve to relres 1e-8 by the oracle's product.
+  oracle (every restart decision checked along the GPU's trajectory by the near-tie rule of tie_rule.py,
+  iterates within 1e-10), and the mixed solve to relres 1e-8 by the oracle's product, its error against the
+  float64 oracle's answer stated and bounded after removing each connected component's J-weighted mean
+  (the method keeps that mean at its starting value on every component, so answers of the singular system
+  are compared modulo its null space).
 * The 512-system finite-element batch, 8 right-hand sides each, with autotuned work items: every one of the
   4096 instances reaches relres 1e-8 by an independent float64 product, and sampled regular-layout
   instances equal the mixed oracle bit for bit (the oracle computes them one by one).
@@ -15,6 +18,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+import tie_rule as TR
 from paper_2407_03272_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -33,6 +37,19 @@ def _say(*a):
     print("[gpu-case]", *a, flush=True)
 
 
+def _component_mean_free(rowptr, colidx, vals, x):
+    """x minus its J-weighted mean (J = absolute row sums, 1 on zero rows) on each connected component."""
+    import scipy.sparse as sps
+    from scipy.sparse.csgraph import connected_components
+    n = len(rowptr) - 1
+    A = sps.csr_matrix((np.abs(vals), colidx, rowptr), shape=(n, n))
+    J = np.asarray(A.sum(axis=1)).ravel()
+    J[J == 0] = 1.0
+    nc, lab = connected_components(A, directed=False)
+    mean = np.bincount(lab, weights=J * x, minlength=nc) / np.bincount(lab, weights=J, minlength=nc)
+    return x - mean[lab]
+
+
 def test_chunglu_4m_full_size(naj):
     _say("full size: Chung-Lu n=2^22")
     s = W.chung_lu_laplacian()
@@ -40,12 +57,15 @@ def test_chunglu_4m_full_size(naj):
     assert sysm.info()["layout"] == 1
     x, info = sysm.solve(s.b, tol=1e-8, max_iter=20000, trace=True)
     orc = O.accelerated_jacobi(s.rowptr, s.colidx, s.vals, s.b, tol=1e-8, max_iter=20000)
-    if info.restart_log != orc.restarts:
-        eps = np.finfo(float).eps
-        t = sorted(set(orc.restarts) ^ set(info.restart_log))[0]
-        assert abs(orc.s_log[t - 1]) <= 64 * s.n * eps * orc.sabs_log[t - 1]
+    if info.restart_log != orc.restarts or info.iterations != orc.iterations:
         orc = O.accelerated_jacobi(s.rowptr, s.colidx, s.vals, s.b, tol=1e-8, max_iter=20000,
                                    forced_restarts=info.restart_log)
+    # long rows sum in another order, so the iterates are not bit-identical: the GPU's restart inner
+    # products must agree with the oracle's to 1e-6 of sum|g_i d_i|, and any decision that differs must be
+    # a tie (|s_t| <= 4 n eps sum|g_i d_i| + the measured difference)
+    ties = TR.check_decisions(orc, info.restart_log, info.trace, s.n, agree=1e-6)
+    _say(f"  decisions checked over {len(orc.s_log)} iterations, ties {ties}, largest |s_gpu - s|/sum|gd| "
+         f"{TR.max_sum_difference(orc, info.trace):.2e}")
     assert info.status == orc.status == O.STATUS_OK
     assert info.iterations == orc.iterations
     xg = x.cpu().numpy()
@@ -54,8 +74,15 @@ def test_chunglu_4m_full_size(naj):
     assert np.linalg.norm(s.b - Q @ xg) / np.linalg.norm(s.b) <= 1e-8
     xm, im = sysm.solve(s.b, tol=1e-8, precision=naj.NAJ_MIXED)
     assert im.status == 0
-    assert np.linalg.norm(s.b - Q @ xm.cpu().numpy()) / np.linalg.norm(s.b) <= 1e-8
-    _say(f"  iterations {info.iterations}, restarts {info.restart_log}; mixed inner {im.iterations}")
+    xmh = xm.cpu().numpy()
+    assert np.linalg.norm(s.b - Q @ xmh) / np.linalg.norm(s.b) <= 1e-8
+    # the mixed answer against the float64 oracle's, modulo the null space
+    pm = _component_mean_free(s.rowptr, s.colidx, s.vals, xmh)
+    po = _component_mean_free(s.rowptr, s.colidx, s.vals, orc.x)
+    err = float(np.linalg.norm(pm - po) / np.linalg.norm(po))
+    _say(f"  iterations {info.iterations}, restarts {info.restart_log}; mixed inner {im.iterations}, "
+         f"error of the mixed answer against the float64 oracle (modulo the null space) {err:.2e}")
+    assert err <= 1e-5
     sysm.close()
 
 

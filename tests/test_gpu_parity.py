@@ -8,6 +8,7 @@ bit, and the tests check that where the matrix makes it certain.  Reductions
 decision may differ only at a numerical tie; the near-tie rule replays the
 oracle with the GPU's schedule in that case.
 """
+import hashlib
 import json
 import os
 
@@ -15,6 +16,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+import tie_rule as TR
 from paper_2407_03272_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -35,26 +37,27 @@ def _say(*a):
     print("[gpu-case]", *a, flush=True)
 
 
-def _near_tie_ok(orc, gpu_info, n):
-    """Decisions may differ only where |s_t| <= 4 n eps sum|g_i d_i| (restart) at the first divergence."""
-    eps = np.finfo(float).eps
-    o_set, g_set = set(orc.restarts), set(gpu_info.restart_log)
-    diff = sorted(o_set ^ g_set)
-    if not diff:
-        return True
-    t = diff[0]
-    s, sabs = orc.s_log[t - 1], orc.sabs_log[t - 1]
-    return abs(s) <= 4 * n * eps * sabs
+# Agreement of the GPU's restart inner products with the oracle's on paths whose iterates are not
+# bit-identical (long rows of the sorted layout sum in another order): |s^GPU - s| <= AGREE_LONG * sum|g d|.
+AGREE_LONG = 1e-6
 
 
-def _compare_solve(naj, sysm, rowptr, colidx, vals, b, *, x0=None, D=None, rtol=1e-10, bitwise=False, **kw):
+def _compare_solve(naj, sysm, rowptr, colidx, vals, b, *, x0=None, D=None, rtol=1e-10, bitwise=False,
+                   agree=None, **kw):
+    """The GPU solve against the oracle.  Every restart decision is checked along the GPU's trajectory
+    (tie_rule): the oracle replayed with the GPU's schedule must make the same decision at every
+    iteration unless the restart inner product is a numerical tie, and the GPU's inner products must
+    agree with the oracle's to within `agree` (default 4 n eps: the rounding of the sum alone)."""
     orc = O.accelerated_jacobi(rowptr, colidx, vals, b, x0=x0, D=D, **kw)
     x, info = sysm.solve(b, x0=x0, trace=True, **kw)
     xg = x.cpu().numpy()
     n = len(rowptr) - 1
     if info.restart_log != orc.restarts or info.iterations != orc.iterations:
-        assert _near_tie_ok(orc, info, n), (info.restart_log, orc.restarts, info.iterations, orc.iterations)
         orc = O.accelerated_jacobi(rowptr, colidx, vals, b, x0=x0, D=D, forced_restarts=info.restart_log, **kw)
+    ties = TR.check_decisions(orc, info.restart_log, info.trace, n, k0=kw.get("k0", 2),
+                              restart=kw.get("restart", True), agree=agree)
+    _say(f"  decisions checked over {len(orc.s_log)} iterations, ties {ties}, largest |s_gpu - s|/sum|gd| "
+         f"{TR.max_sum_difference(orc, info.trace):.2e}")
     assert info.status == orc.status
     assert info.iterations == orc.iterations
     assert info.restart_log == orc.restarts[:64]
@@ -223,6 +226,35 @@ def test_edge_cases(naj):
     _compare_solve(naj, s65, rp, ci, va, b, tol=1e-10, max_iter=5000, bitwise=True)
 
 
+def test_zero_row_gpu_matches_oracle(naj):
+    """A zero row (an isolated vertex) gets J_kk = 1.  With b_k = 0 the component stays at x^0_k and the
+    run converges; with b_k != 0 the system is inconsistent (b outside range(Q), excluded by Section 1)
+    and the run ends NOT_CONVERGED at the cap.  Both runs equal the oracle's bit for bit."""
+    _say("zero row: consistent and inconsistent right-hand sides")
+    rowptr, colidx, vals, u, v = W.random_laplacian(40, 0.1, 8)
+    Q = O.csr(rowptr, colidx, vals)
+    A = Q.tolil()
+    for j in A.rows[0][:]:          # isolate vertex 0
+        if j != 0:
+            A[0, j] = 0; A[j, 0] = 0; A[j, j] -= 1
+    A[0, 0] = 0
+    A = A.tocsr(); A.eliminate_zeros(); A.sort_indices()
+    rp, ci, va = A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data
+    assert rp[1] - rp[0] == 0
+    b = W.rhs_in_range(rp, ci, va, 3)
+    x0 = np.full(40, 0.25)
+    sysm = naj.System(rp, ci, va)
+    orc, info, xg = _compare_solve(naj, sysm, rp, ci, va, b, x0=x0, tol=1e-9, max_iter=20000, bitwise=True)
+    assert info.status == 0 and xg[0] == 0.25
+    b2 = b.copy(); b2[0] = 1.0
+    orc2, info2, xg2 = _compare_solve(naj, sysm, rp, ci, va, b2, x0=x0, tol=1e-9, max_iter=500, bitwise=True)
+    assert info2.status == orc2.status == naj.NAJ_NOT_CONVERGED and info2.iterations == 500
+    rel = np.linalg.norm(b2 - O.csr(rp, ci, va) @ xg2) / np.linalg.norm(b2)
+    assert rel >= 1.0 / np.linalg.norm(b2) * (1 - 1e-12)      # row 0 keeps its residual b_0
+    assert info2.relres == pytest.approx(rel, rel=1e-10)
+    sysm.close()
+
+
 def test_invalid_csr_rejected(naj):
     _say("invalid csr")
     rp, ci, va = W.poisson_dirichlet((8, 8))
@@ -285,8 +317,9 @@ def test_full_size_first_iterations_elementwise(naj, c2):
 
 
 def test_full_size_solve_matches_stored_oracle_run(naj, c2):
-    """Full 128^3 solve against the oracle's stored complete run: same iteration count and restarts, sampled
-    entries of x within 1e-10, and the residual of the returned x recomputed by the oracle's product."""
+    """Full 128^3 solve against the oracle's stored complete run: same iteration count and restarts, the whole
+    x bit-identical (its SHA-256 against the stored one; sampled entries within 1e-10 as well), and the
+    residual of the returned x recomputed by the oracle's product."""
     _say("128^3 full solve")
     ref = [r for r in json.load(open(os.path.join(GOLD, "oracle_runs.json")))["runs"] if r["name"] == "laplace3d_128"][0]
     sysm = naj.System(c2.rowptr, c2.colidx, c2.vals)
@@ -297,6 +330,8 @@ def test_full_size_solve_matches_stored_oracle_run(naj, c2):
     idx = np.asarray(ref["sample_idx"])
     sx = np.asarray(ref["sample_x"])
     assert np.abs(xg[idx] - sx).max() <= 1e-10 * np.abs(sx).max()
+    # the whole vector, bit for bit: same restart schedule and the same IEEE operations per row
+    assert hashlib.sha256(np.ascontiguousarray(xg, dtype="<f8").tobytes()).hexdigest() == ref["x_sha256"]
     np.testing.assert_allclose(info.hist, ref["hist"], rtol=1e-9)
     Q = O.csr(c2.rowptr, c2.colidx, c2.vals)
     rel = np.linalg.norm(c2.b - Q @ xg) / np.linalg.norm(c2.b)
@@ -315,7 +350,7 @@ def test_irregular_layout_chung_lu(naj):
     info = sysm.info()
     assert info["layout"] == 1
     assert info["stored_entries"] <= 1.05 * s.nnz
-    _compare_solve(naj, sysm, s.rowptr, s.colidx, s.vals, s.b, tol=1e-8, max_iter=20000)
+    _compare_solve(naj, sysm, s.rowptr, s.colidx, s.vals, s.b, tol=1e-8, max_iter=20000, agree=AGREE_LONG)
     rng = np.random.default_rng(5)
     p, r = rng.standard_normal(s.n), rng.standard_normal(s.n)
     x, (s_, gg, sabs) = sysm.step(p, r, 0.3, s.b)
@@ -360,7 +395,8 @@ def test_irregular_user_diagonal_and_mixed(naj):
     s = W.chung_lu_laplacian(1 << 14, 16, 2.5, seed=91, b_seed=92)
     J = O.jacobi_diagonal(O.csr(s.rowptr, s.colidx, s.vals))
     sysd = naj.System(s.rowptr, s.colidx, s.vals, D=1.2 * J)
-    _compare_solve(naj, sysd, s.rowptr, s.colidx, s.vals, s.b, D=1.2 * J, tol=1e-8, max_iter=20000)
+    _compare_solve(naj, sysd, s.rowptr, s.colidx, s.vals, s.b, D=1.2 * J, tol=1e-8, max_iter=20000,
+                   agree=AGREE_LONG)
     sysm = naj.System(s.rowptr, s.colidx, s.vals)
     x, info = sysm.solve(s.b, precision=naj.NAJ_MIXED, trace=True, hist_cap=64)
     m = O.accelerated_jacobi_mixed(s.rowptr, s.colidx, s.vals, s.b, tol=1e-8)
@@ -394,30 +430,42 @@ def test_materialized_momentum_form_is_bitwise(naj, mode, monkeypatch):
 
 def test_nontemporal_pass_is_bitwise(naj, monkeypatch):
     """Systems whose float64 pass exceeds the 256 MB MALL load matrix entries non-temporally (a separate
-    kernel instance); forced at creation on a 40^3 Poisson system, the solve and block-J solve equal the
-    ordinary pass's bit for bit and the float64 solve equals the oracle's; forced on a Chung-Lu Laplacian
-    (sorted layout, long rows), the float64 and mixed solves equal the ordinary passes' bit for bit."""
+    kernel instance), and so do mixed solves whose float32 inner pass exceeds it (256-thread launch shape).
+    Forced at creation on a 40^3 Poisson system with the 256-thread mixed launch shape, the float64, block-J,
+    mixed and block-J mixed solves equal the ordinary instances' bit for bit, the float64 solve equals the
+    oracle's and the mixed solve the mixed oracle's; forced on a Chung-Lu Laplacian (sorted layout, long
+    rows), the float64 and mixed solves equal the ordinary passes' bit for bit."""
     _say("non-temporal pass, poisson 40^3")
     s = W.poisson_system((40, 40, 40), 12)
     out = []
     for flag in ("1", "0"):
         monkeypatch.setenv("NAJ_NT", flag)
+        monkeypatch.setenv("NAJ_NT_MIXED", flag)
+        monkeypatch.setenv("NAJ_BS_MIXED", "256")     # the launch shape that has the non-temporal instances
         sysm = naj.System(s.rowptr, s.colidx, s.vals)
         sysb = naj.System(s.rowptr, s.colidx, s.vals, jblock=4)
-        monkeypatch.delenv("NAJ_NT")
+        for v in ("NAJ_NT", "NAJ_NT_MIXED", "NAJ_BS_MIXED"):
+            monkeypatch.delenv(v)
         x, info = sysm.solve(s.b, tol=1e-8, max_iter=20000)
         xb, ib = sysb.solve(s.b, tol=1e-8, max_iter=20000)
-        assert info.grid > 1 and info.status == 0 and ib.status == 0
-        out.append((x.cpu().numpy(), info.iterations, info.restart_log, xb.cpu().numpy(), ib.iterations))
+        xm, im = sysm.solve(s.b, tol=1e-8, precision=naj.NAJ_MIXED)
+        xbm, ibm = sysb.solve(s.b, tol=1e-8, precision=naj.NAJ_MIXED)
+        assert info.grid > 1 and info.status == 0 and ib.status == 0 and im.status == 0 and ibm.status == 0
+        out.append((x.cpu().numpy(), info.iterations, info.restart_log, xb.cpu().numpy(), ib.iterations,
+                    xm.cpu().numpy(), im.iterations, xbm.cpu().numpy(), ibm.iterations))
         sysm.close()
         sysb.close()
     assert np.array_equal(out[0][0], out[1][0]) and out[0][1:3] == out[1][1:3]
     assert np.array_equal(out[0][3], out[1][3]) and out[0][4] == out[1][4]
+    assert np.array_equal(out[0][5], out[1][5]) and out[0][6] == out[1][6]
+    assert np.array_equal(out[0][7], out[1][7]) and out[0][8] == out[1][8]
     orc = O.accelerated_jacobi(s.rowptr, s.colidx, s.vals, s.b, tol=1e-8, max_iter=20000)
     if out[0][2] == orc.restarts:
         assert out[0][1] == orc.iterations and np.array_equal(out[0][0], orc.x)
     else:
         assert np.abs(out[0][0] - orc.x).max() <= 1e-10 * np.abs(orc.x).max()
+    m = O.accelerated_jacobi_mixed(s.rowptr, s.colidx, s.vals, s.b, tol=1e-8)
+    assert out[0][6] == m.inner_total and np.array_equal(out[0][5], m.x)
     # the sorted layout (materialized form, long rows one wavefront each) with and without the loads
     c = W.chung_lu_laplacian(1 << 15, 16, 2.5, seed=81, b_seed=82)
     res = []
