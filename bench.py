@@ -32,24 +32,31 @@ CSRC = os.path.join(ROOT, "paper_2407_03272_amd", "csrc")
 PROFILES = os.path.join(ROOT, "profiles")
 
 
+# The files that define the fused pass kernel k_pass64 (its code, the layout it reads and its partition of
+# slices over workgroups).  Host-side files only choose its instance and grid, which the traffic record
+# names itself.
+PASS_KERNEL_SOURCES = ("naj_device.h", "naj_solve.h", "naj_partition.h")
+
+
 def kernel_source_hash() -> str:
-    import glob
     import hashlib
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(CSRC, "*.h")) + glob.glob(os.path.join(CSRC, "*.hip"))):
-        h.update(os.path.basename(p).encode())
-        h.update(open(p, "rb").read())
+    for name in PASS_KERNEL_SOURCES:
+        h.update(name.encode())
+        h.update(open(os.path.join(CSRC, name), "rb").read())
     return h.hexdigest()
 
 
-def measured_traffic(workload: str):
+def measured_traffic(workload: str, grid: int | None = None):
     """HBM bytes per pass from the committed rocprofv3 counter runs, or None when none exist for this
-    workload or the kernel sources changed since they were taken."""
+    workload, the pass kernel's sources changed since they were taken, or the pass ran on another grid."""
     path = os.path.join(PROFILES, f"k_pass64_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
     if rec.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    if grid is not None and rec.get("grid") not in (None, grid):
         return None
     return rec["traffic_bytes_per_pass"]
 
@@ -588,7 +595,7 @@ def bench_single(args, workload: str, progress, steps: int, warmup: int, precisi
         "gbps_solve": achieved,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None if (mixed or jb) else measured_traffic(workload),
+                     "traffic": None if (mixed or jb) else measured_traffic(workload, info.grid),
                      "kernel": "k_pass64 (fused iteration pass, one launch per pass)",
                      "launches_per_solve": info.passes,
                      "algorithmic_bytes_per_launch": per_launch,
