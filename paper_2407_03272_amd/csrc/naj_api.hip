@@ -465,7 +465,7 @@ __global__ void k_reduce_fixed(const double* part, int G, double* out) {
 // is stored only if it equals a constant no real input produces, so the loads stay), 1 copies src to
 // dst, 2 writes dst.  NAJ_PROBE_NT selects non-temporal accesses, NAJ_PROBE_WG_PER_CU the grid.
 #ifndef NAJ_PROBE_NT
-#define NAJ_PROBE_NT 0
+#define NAJ_PROBE_NT 1
 #endif
 #ifndef NAJ_PROBE_WG_PER_CU
 #define NAJ_PROBE_WG_PER_CU 8

@@ -244,9 +244,9 @@ class System:
             self._h = None
 
     def __del__(self):
-        if _finalizing():   # the exit hook has released every handle; the runtime may be gone now
-            return
         try:
+            if _finalizing():   # the exit hook has released every handle; the runtime may be gone now
+                return
             self.close()
         except Exception:
             pass
@@ -391,9 +391,9 @@ class Batch:
             self._h = None
 
     def __del__(self):
-        if _finalizing():   # the exit hook has released every handle; the runtime may be gone now
-            return
         try:
+            if _finalizing():   # the exit hook has released every handle; the runtime may be gone now
+                return
             self.close()
         except Exception:
             pass
@@ -552,9 +552,9 @@ class Server:
             self._h = None
 
     def __del__(self):
-        if _finalizing():   # the exit hook has released every handle; the runtime may be gone now
-            return
         try:
+            if _finalizing():   # the exit hook has released every handle; the runtime may be gone now
+                return
             self.close()
         except Exception:
             pass

@@ -226,6 +226,31 @@ def test_edge_cases(naj):
     _compare_solve(naj, s65, rp, ci, va, b, tol=1e-10, max_iter=5000, bitwise=True)
 
 
+@pytest.mark.parametrize("mode", ["0", "2"])
+def test_edge_cases_launch_drivers(naj, mode, monkeypatch):
+    """The edge cases on the one-launch-per-pass driver (whose decision after a pass is taken at the start of
+    the next launch) and on the cooperative persistent driver: a zero right-hand side (decided after the
+    norm pass), a converged start, NaN in b, an iteration cap of 1 and of 2."""
+    _say("edge cases, driver", mode)
+    monkeypatch.setenv("NAJ_MODE", mode)
+    s = W.poisson2d_64()
+    sysm = naj.System(s.rowptr, s.colidx, s.vals)
+    monkeypatch.delenv("NAJ_MODE")
+    x, info = sysm.solve(np.zeros(s.n))
+    assert info.status == 0 and info.iterations == 0 and not x.cpu().numpy().any()
+    x, info = sysm.solve(s.b, x0=s.xstar)
+    assert info.iterations == 0 and np.array_equal(x.cpu().numpy(), s.xstar)
+    bad = s.b.copy(); bad[17] = np.nan
+    x, info = sysm.solve(bad)
+    assert info.status == naj.NAJ_EBREAKDOWN
+    for cap in (1, 2):
+        x, info = sysm.solve(s.b, tol=1e-8, max_iter=cap)
+        orc = O.accelerated_jacobi(s.rowptr, s.colidx, s.vals, s.b, tol=1e-8, max_iter=cap)
+        assert info.status == naj.NAJ_NOT_CONVERGED and info.iterations == cap
+        assert np.array_equal(x.cpu().numpy(), orc.x)
+    sysm.close()
+
+
 def test_zero_row_gpu_matches_oracle(naj):
     """A zero row (an isolated vertex) gets J_kk = 1.  With b_k = 0 the component stays at x^0_k and the
     run converges; with b_k != 0 the system is inconsistent (b outside range(Q), excluded by Section 1)
