@@ -365,26 +365,58 @@ __device__ __forceinline__ void load_view(const Ctrl* c, PassView* v) {
 // The workgroup's share of one float64 iteration pass (long rows, then slices).  YM: the
 // materialized momentum form (a compile-time choice, so the two-iterate kernel carries none
 // of the materialized form's code).
+// The rows one wave takes in a pass.  With a balanced item list (A.witem, built for this launch shape
+// on the sorted layout) the wave sweeps its own list of long rows and slices; otherwise the long rows
+// are strided over every wave of the grid, then the wave takes its slice range.  `longs` is false
+// where the kernel instance has no long-row path (block J, whose layout has no long rows).  LISTS:
+// the instance carries the list path; only the materialized-momentum instances do, which are the
+// ones the sorted layout runs (the others keep their register budget and ignore the lists).
+template <int BS, bool LISTS, class LongFn, class SliceFn>
+__device__ __forceinline__ void for_wave_items(const Sell& A, int nxcd, bool longs, LongFn&& fl, SliceFn&& fs) {
+  if (LISTS && A.witem) {
+    const NAJ_CONST int32_t* off = (const NAJ_CONST int32_t*)A.woff;
+    const NAJ_CONST int32_t* item = (const NAJ_CONST int32_t*)A.witem;
+    const int w = (int)blockIdx.x * (BS / kWave) + wave_id();
+    const int e = off[w + 1];
+    for (int i = off[w]; i < e; ++i) {
+      const int64_t it = item[i];
+      if (it < A.n_long) {
+        if (longs) fl(it);
+      } else {
+        fs(it - A.n_long);
+      }
+    }
+    return;
+  }
+  if (longs) {
+    const LongRange<BS> lr;
+    for (int64_t r = lr.first; r < A.n_long; r += lr.step) fl(r);
+  }
+  const WaveRange wr = wave_range<BS>(A, nxcd);
+  for (int64_t s = wr.first; s < wr.end; s += wr.step) fs(s);
+}
+
 template <int JM, int BS, bool YM, bool NT = false>
 __device__ __forceinline__ void pass_iter64(const SolveArgs& a, const double* P, const Momentum<double>& m, double* W,
                                             double& p0, double& p1, double& p2) {
   const int lane = threadIdx.x % kWave;
-  const LongRange<BS> lr;
-  if constexpr (JM != kJBlock)   // a block J uses the regular layout: no long rows
-    for (int64_t r = lr.first; r < a.A.n_long; r += lr.step) iter_long<JM, YM, NT>(a, r, lane, P, m, W, p0, p1, p2);
-  const WaveRange wr = wave_range<BS>(a.A, a.nxcd);
-  for (int64_t s = wr.first; s < wr.end; s += wr.step) iter_slice<JM, YM, NT>(a, s, lane, P, m, W, p0, p1, p2);
+  // a block J uses the regular layout: no long rows
+  for_wave_items<BS, YM>(
+      a.A, a.nxcd, JM != kJBlock,
+      [&](int64_t r) {
+        if constexpr (JM != kJBlock) iter_long<JM, YM, NT>(a, r, lane, P, m, W, p0, p1, p2);
+      },
+      [&](int64_t s) { iter_slice<JM, YM, NT>(a, s, lane, P, m, W, p0, p1, p2); });
 }
 
 // The workgroup's share of r = b - Q X (float64); ||r||^2 in p0 (with obj: f(X)).
-template <int BS>
+template <int BS, bool LISTS = false>
 __device__ __forceinline__ void pass_resid64(const Sell& A, int nxcd, const double* X, const double* b, double* out,
                                              double& p0, bool obj = false) {
   const int lane = threadIdx.x % kWave;
-  const LongRange<BS> lr;
-  for (int64_t r = lr.first; r < A.n_long; r += lr.step) resid_long(A, r, lane, X, b, out, p0, obj);
-  const WaveRange wr = wave_range<BS>(A, nxcd);
-  for (int64_t s = wr.first; s < wr.end; s += wr.step) resid_slice(A, s, lane, X, b, out, p0, obj);
+  for_wave_items<BS, LISTS>(
+      A, nxcd, true, [&](int64_t r) { resid_long(A, r, lane, X, b, out, p0, obj); },
+      [&](int64_t s) { resid_slice(A, s, lane, X, b, out, p0, obj); });
 }
 
 // Phases a kernel instance carries (template parameter PS of run_pass and k_pass64): every phase, or
@@ -409,7 +441,7 @@ __device__ __forceinline__ void run_pass(const SolveArgs& a, const PassView& v, 
     m.ym = YM;
     pass_iter64<JM, BS, YM, NT>(a, pick(a, v.iP), m, pick(a, v.iW), p0, p1, p2);
   } else if (F64 && v.phase == PH_CONFIRM) {
-    pass_resid64<BS>(a.A, a.nxcd, pick(a, v.iW), a.b, nullptr, p0, a.stop_obj != 0);
+    pass_resid64<BS, YM>(a.A, a.nxcd, pick(a, v.iW), a.b, nullptr, p0, a.stop_obj != 0);
   } else if (MX && v.phase == PH_INNER32) {
     const float* P = pickf(a, v.iP);
     float* W = pickf(a, v.iW);
@@ -421,19 +453,19 @@ __device__ __forceinline__ void run_pass(const SolveArgs& a, const PassView& v, 
     m.bz = v.bz != 0;
     m.ym = YM;
     const bool zp = v.zp != 0;
-    const LongRange<BS> lr;
-    if constexpr (JM != kJBlock)
-      for (int64_t r = lr.first; r < a.A.n_long; r += lr.step) inner_long<JM, YM, NT>(a, r, lane, P, m, W, zp, p0, p1, p2);
-    const WaveRange wr = wave_range<BS>(a.A, a.nxcd);
-    for (int64_t s = wr.first; s < wr.end; s += wr.step) inner_slice<JM, YM, NT>(a, s, lane, P, m, W, zp, p0, p1, p2);
+    for_wave_items<BS, YM>(
+        a.A, a.nxcd, JM != kJBlock,
+        [&](int64_t r) {
+          if constexpr (JM != kJBlock) inner_long<JM, YM, NT>(a, r, lane, P, m, W, zp, p0, p1, p2);
+        },
+        [&](int64_t s) { inner_slice<JM, YM, NT>(a, s, lane, P, m, W, zp, p0, p1, p2); });
   } else if (MX && v.phase == PH_RESID64) {
     const double* X = pick(a, v.iX);
     const float* D = v.update ? pickf(a, v.iD) : nullptr;
     double* Xn = v.update ? pick(a, v.iXn) : nullptr;
-    const LongRange<BS> lr;
-    for (int64_t r = lr.first; r < a.A.n_long; r += lr.step) resid_mixed_long(a, r, lane, X, D, Xn, p0, p1);
-    const WaveRange wr = wave_range<BS>(a.A, a.nxcd);
-    for (int64_t s = wr.first; s < wr.end; s += wr.step) resid_mixed_slice(a, s, lane, X, D, Xn, p0, p1);
+    for_wave_items<BS, YM>(
+        a.A, a.nxcd, true, [&](int64_t r) { resid_mixed_long(a, r, lane, X, D, Xn, p0, p1); },
+        [&](int64_t s) { resid_mixed_slice(a, s, lane, X, D, Xn, p0, p1); });
   } else if (v.phase == PH_NORMB) {  // every row, flat
     for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < a.A.n; i += (int64_t)gridDim.x * BS) {
       const double x = a.b[i];
@@ -443,38 +475,64 @@ __device__ __forceinline__ void run_pass(const SolveArgs& a, const PassView& v, 
 }
 
 // Sums of the G per-workgroup partial sums of a pass, in a fixed order: thread i adds slots i, i + BS,
-// i + 2 BS, ... in turn (four slots' loads issued together), then the workgroup's threads are combined
-// by block_sum3.  Every workgroup that runs it gets the same three values (in thread 0).
+// i + 2 BS, ... in turn, then the workgroup's threads are combined by block_sum3.  Every workgroup that
+// runs it gets the same three values (in thread 0).  issue() starts the loads of up to four slots per
+// thread, so that they travel together with the other loads at the start of a launch; combine() adds
+// them (and, for G > 4 BS, loads and adds the slots in groups of four itself).
 template <int BS>
-__device__ __forceinline__ void block_part_sum(const double* __restrict__ part, int G, double& r0, double& r1,
-                                               double& r2, double (*sh)[BS / kWave]) {
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-  int i = threadIdx.x;
-  for (; i + 3 * BS < G; i += 4 * BS) {
-    double v[4][3];
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-      for (int k = 0; k < 3; ++k) v[q][k] = part[(size_t)(i + q * BS) * kPartStride + k];
+struct PartSums {
+  double v[4][3];
+
+  __device__ __forceinline__ void issue(const double* __restrict__ part, int G) {
+    if (G > 4 * BS) return;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      s0 = s0 + v[q][0];
-      s1 = s1 + v[q][1];
-      s2 = s2 + v[q][2];
+      const int j = threadIdx.x + q * BS;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) v[q][k] = j < G ? part[(size_t)j * kPartStride + k] : 0.0;
     }
   }
-  for (; i < G; i += BS) {
-    const double* p = part + (size_t)i * kPartStride;
-    const double a0 = p[0], a1 = p[1], a2 = p[2];
-    s0 = s0 + a0;
-    s1 = s1 + a1;
-    s2 = s2 + a2;
+
+  __device__ __forceinline__ void combine(const double* __restrict__ part, int G, double& r0, double& r1,
+                                          double& r2, double (*sh)[BS / kWave]) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    if (G <= 4 * BS) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if ((int)threadIdx.x + q * BS < G) {
+          s0 = s0 + v[q][0];
+          s1 = s1 + v[q][1];
+          s2 = s2 + v[q][2];
+        }
+    } else {
+      int i = threadIdx.x;
+      for (; i + 3 * BS < G; i += 4 * BS) {
+        double w[4][3];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int k = 0; k < 3; ++k) w[q][k] = part[(size_t)(i + q * BS) * kPartStride + k];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          s0 = s0 + w[q][0];
+          s1 = s1 + w[q][1];
+          s2 = s2 + w[q][2];
+        }
+      }
+      for (; i < G; i += BS) {
+        const double* p = part + (size_t)i * kPartStride;
+        const double a0 = p[0], a1 = p[1], a2 = p[2];
+        s0 = s0 + a0;
+        s1 = s1 + a1;
+        s2 = s2 + a2;
+      }
+    }
+    r0 = s0;
+    r1 = s1;
+    r2 = s2;
+    block_sum3<BS>(r0, r1, r2, sh);
   }
-  r0 = s0;
-  r1 = s1;
-  r2 = s2;
-  block_sum3<BS>(r0, r1, r2, sh);
-}
+};
 
 // One pass per launch; launch k of a solve (k = 0, 1, ...) runs pass k.  The scalar decision after
 // pass k-1 is taken at the start of launch k by every workgroup, each from the same two inputs: the
@@ -488,21 +546,26 @@ __device__ __forceinline__ void block_part_sum(const double* __restrict__ part, 
 // launch k+1 reads the published state.  Launches after the solve has finished copy the finished
 // state forward and return.
 // The launch passes k itself for k < 3 and any value of the same parity above 0 beyond (only k > 0
-// and k & 1 matter).
+// and k & 1 matter).  With `flag` set, workgroup 0 also stores the phase of C_k there (a host-visible
+// word the host polls instead of copying the control block back).
 template <int JM, int BS, bool YM, bool NT = false, int PS = kPhasesAll>
-__global__ void __launch_bounds__(BS) k_pass64(SolveArgs a, int k) {
+__global__ void __launch_bounds__(BS) k_pass64(SolveArgs a, int k, int* flag) {
   __shared__ double sh[3][BS / kWave];
   __shared__ PassView v;
   __shared__ Ctrl c;
   const int G = gridDim.x;
   const int prev = (k + 1) & 1;
+  // the partial sums' loads and the control block's go out together: one memory round trip
+  const double* __restrict__ part_prev = a.part + (size_t)prev * G * kPartStride;
+  PartSums<BS> ps;
+  if (k > 0) ps.issue(part_prev, G);
   {
     const uint32_t* src = (const uint32_t*)(a.ctrl + prev);
     uint32_t* dst = (uint32_t*)&c;
     for (int i = threadIdx.x; i < (int)(sizeof(Ctrl) / 4); i += BS) dst[i] = src[i];
   }
   double r0 = 0.0, r1 = 0.0, r2 = 0.0;
-  if (k > 0) block_part_sum<BS>(a.part + (size_t)prev * G * kPartStride, G, r0, r1, r2, sh);
+  if (k > 0) ps.combine(part_prev, G, r0, r1, r2, sh);
   __syncthreads();
   if (threadIdx.x == 0) {
     if (k > 0 && c.phase != PH_DONE) control_update(a, &c, r0, r1, r2, blockIdx.x == 0);
@@ -513,6 +576,7 @@ __global__ void __launch_bounds__(BS) k_pass64(SolveArgs a, int k) {
     const uint32_t* src = (const uint32_t*)&c;
     uint32_t* dst = (uint32_t*)(a.ctrl + (k & 1));
     for (int i = threadIdx.x; i < (int)(sizeof(Ctrl) / 4); i += BS) dst[i] = src[i];
+    if (flag && threadIdx.x == 0) __hip_atomic_store(flag, v.phase, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   }
   if (v.phase == PH_DONE) return;
   double p0 = 0.0, p1 = 0.0, p2 = 0.0;
