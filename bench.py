@@ -178,8 +178,9 @@ def cpu_baseline(sysobj, iterations_needed: int, sample_iters: int, jblock=None,
 
 def attainable_bandwidth(progress=None) -> dict:
     """The GPU's attainable streaming rates, measured by the library's probe kernel (naj_bandwidth_probe:
-    16-byte non-temporal accesses over 1 GiB, mean of 20 launches timed with HIP events on the launching
-    stream): read only, copy (read + write bytes) and write only, beside the 8 TB/s published peak."""
+    16 KB blocks taken by the workgroups in turn, 16-byte accesses, over 1 GiB, mean of 20 launches timed
+    with HIP events on the launching stream): read only, copy (read + write bytes) and write only, beside
+    the 8 TB/s published peak."""
     import torch
     from paper_2407_03272_amd import naj
     out = {}
@@ -191,7 +192,8 @@ def attainable_bandwidth(progress=None) -> dict:
     torch.cuda.empty_cache()
     out["best_gbps"] = max(out["read_gbps"], out["copy_gbps"], out["write_gbps"])
     out["best_frac_of_peak"] = out["best_gbps"] / HBM_PEAK_GBS
-    out["kernel"] = "naj_bandwidth_probe (k_bw_probe), 1 GiB, 16-byte non-temporal accesses, mean of 20 launches"
+    out["kernel"] = ("naj_bandwidth_probe (k_bw_probe), 1 GiB in 16 KB blocks taken by the workgroups in turn, "
+                     "16-byte accesses (non-temporal loads; copy: non-temporal stores), mean of 20 launches")
     if progress:
         progress(f"attainable bandwidth: read {out['read_gbps']:.0f}, copy {out['copy_gbps']:.0f}, "
                  f"write {out['write_gbps']:.0f} GB/s")

@@ -246,8 +246,9 @@ naj_status naj_cancel(naj_system *sys);
 
 /*
  * Attainable HBM rate of this GPU, for the measurement beside the published peak: a streaming
- * kernel (16-byte non-temporal accesses, grid-stride, 8 workgroups of 256 threads per CU) over
- * `bytes` bytes, launched once untimed and then `reps` times between HIP events on `stream`.
+ * kernel over `bytes` bytes (16 KB blocks taken by the workgroups in turn, four 16-byte accesses in
+ * flight per thread; non-temporal loads, and stores when copying; 3 workgroups of 256 threads per CU),
+ * launched once untimed and then `reps` times between HIP events on `stream`.
  *   mode  : 0 reads src (dst must hold 16 bytes), 1 copies src to dst, 2 writes dst
  *   src, dst : device buffers of `bytes` bytes (16-byte aligned; src unused in mode 2)
  *   ms    : host, mean milliseconds per launch.  Bytes moved per launch: `bytes` (modes 0, 2) or

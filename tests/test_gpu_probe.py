@@ -37,6 +37,21 @@ def test_probe_copy_of_a_ragged_size(naj):
     assert st == 0 and torch.equal(src, dst)
 
 
+def test_probe_write_of_a_ragged_size(naj):
+    """Mode 2 writes word i of 16 bytes as (i, i+1, i+2, i+3) over every full block and the partial one."""
+    import torch
+    n16 = 3 * 1024 + 5                      # three full 16 KB blocks and a partial one
+    dst = torch.zeros(4 * n16, dtype=torch.int32, device="cuda:0")
+    ms = ctypes.c_double()
+    st = naj.load().naj_bandwidth_probe(2, None, ctypes.c_void_p(dst.data_ptr()), n16 * 16, 1, ctypes.byref(ms),
+                                        None)
+    torch.cuda.synchronize()
+    assert st == 0
+    i = torch.arange(n16, dtype=torch.int64, device="cuda:0")
+    want = torch.stack([i, i + 1, i + 2, i + 3], dim=1).reshape(-1).to(torch.int32)
+    assert torch.equal(dst, want)
+
+
 def test_probe_rejects_bad_arguments(naj):
     ms = ctypes.c_double()
     lib = naj.load()
