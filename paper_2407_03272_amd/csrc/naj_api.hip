@@ -830,9 +830,14 @@ naj_status choose_grid(naj_system* s, hipStream_t st) {
   int64_t want = (s->nslices + s->n_long + wpb - 1) / wpb;
   want = ((want + nxcd - 1) / nxcd) * nxcd;
   s->max_grid = (int)std::max<int64_t>(nxcd, std::min<int64_t>(g, want));
-  const int small_slices = env_int("NAJ_SMALL_SLICES", 256);
+  // One workgroup only for small systems.  A single-workgroup pass costs about 3.8 us plus 0.15 us per
+  // slice (its waves take the slices in turn); a pass of the per-pass driver costs about 7.3 us up to a
+  // few thousand slices (the launch and the decision at the start of every workgroup).  Measured on 2D
+  // and 3D Poisson systems (float64 solves/s, one workgroup against one launch per pass): 16x16 1539 /
+  // 935, 32x32 586 / 467, 64x64 167 / 291, 16^3 454 / 863, 128x128 31 / 176; the cooperative
+  // persistent driver was slower than one of the two at every size.
+  const int small_slices = env_int("NAJ_SMALL_SLICES", 24);
   const int force = env_int("NAJ_MODE", -1);
-  // one workgroup only for small systems (few slices and little stored work)
   s->mode = (s->nslices + s->n_long / 4 <= small_slices && s->nnz <= (1 << 21)) ? kModeSmall : kModePass;
   if (force >= 0 && force <= 2) s->mode = force;
   s->grid = s->max_grid;

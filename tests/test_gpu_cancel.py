@@ -49,7 +49,7 @@ def _cancelled_solve(sysm, b, delay, **opts):
     return x, info, out["t"]
 
 
-@pytest.mark.parametrize("shape", [(64, 64, 64), (64, 64)])
+@pytest.mark.parametrize("shape", [(64, 64, 64), (24, 24)])   # the per-pass and the single-workgroup driver
 def test_cancel_float64(naj, shape):
     s = W.poisson_system(shape, 21)
     sysm = naj.System(s.rowptr, s.colidx, s.vals)

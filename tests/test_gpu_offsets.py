@@ -66,7 +66,9 @@ def test_poisson2d_offset_slices_bitwise(naj, monkeypatch):
     single-workgroup drivers (vectors in LDS, and in global memory) run it."""
     _say("offset form, poisson 2d")
     s = W.poisson2d_64()
+    monkeypatch.setenv("NAJ_MODE", "1")     # the single-workgroup driver (the default takes it up to 24 slices)
     on, off = _pair(naj, monkeypatch, s.rowptr, s.colidx, s.vals)
+    monkeypatch.delenv("NAJ_MODE")
     assert on.info()["offset_slices"] == 62 and on.info()["nslices"] == 64
     orc = O.accelerated_jacobi(s.rowptr, s.colidx, s.vals, s.b, tol=1e-8, max_iter=20000)
     for lds in ("1", "0"):

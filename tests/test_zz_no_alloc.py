@@ -45,14 +45,14 @@ def _same(naj, sysm, s, **opts):
 
 def test_noalloc_float64_large_then_small(naj):
     big = W.poisson_system((40, 40, 40), 12)
-    small = W.poisson2d_64()
+    small = W.poisson_system((24, 24), 5)    # 9 slices: the single-workgroup driver
     sb = naj.System(big.rowptr, big.colidx, big.vals)
     ss = naj.System(small.rowptr, small.colidx, small.vals)
     for rep in range(2):
         _say(f"noalloc float64 40^3 (per-pass driver), round {rep}")
         ib = _same(naj, sb, big, tol=1e-8, max_iter=20000)
         assert ib.status == 0 and ib.relres <= 1e-8
-        _say(f"noalloc float64 64x64 (single workgroup), round {rep}")
+        _say(f"noalloc float64 24x24 (single workgroup), round {rep}")
         i2 = _same(naj, ss, small, tol=1e-8, max_iter=20000)
         assert i2.status == 0 and i2.relres <= 1e-8
     _say("noalloc float64 capped (not converged: residual of the last iterate from the static scratch)")
