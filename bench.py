@@ -651,7 +651,8 @@ def _sub(line: dict) -> dict:
 def bench_default(args, progress) -> dict:
     """The default run.  Top level: the 128^3 Laplacian in float64, one solve per step (value, latency,
     the fused pass's roofline, the mixed-precision comparison, the CPU oracle), and the measured copy
-    bandwidth.  Sub-results, each with its own fixed step counts: 160^3 in float64 (the pass beyond the
+    bandwidth.  Sub-results, each with its own fixed step counts: the 64x64 Poisson system in float64
+    (against mixed and the CPU oracle), 160^3 in float64 (the pass beyond the
     256 MB MALL), the Chung-Lu graph Laplacian n = 2^22 in mixed precision against float64, the
     512-system finite-element batch (mixed batch against float64 batch and float64 one system at a
     time), and the serving loop (p50/p99 latency, offered and saturated solves/s, float64 one request
@@ -670,6 +671,10 @@ def bench_default(args, progress) -> dict:
                        "bytes may come from the MALL rather than HBM; workloads.laplace3d_160 is the pass "
                        "beyond the MALL")
     subs = {}
+    # the small configuration: 64x64 Poisson in float64 beside the CPU oracle (all host threads), and mixed
+    subs["poisson2d_64"] = _sub(bench_single(args, "poisson2d_64", progress, 50, 5, "fp64", True,
+                                             not args.no_cpu_baseline))
+    progress(f"64x64 done at {time.perf_counter() - t_start:.0f} s")
     subs["laplace3d_160"] = _sub(bench_single(args, "laplace3d_160", progress, 3, 1, "fp64", True, False))
     subs["laplace3d_160"]["roofline"]["residency"] = "beyond the MALL: about 376 MB moved per pass"
     progress(f"160^3 done at {time.perf_counter() - t_start:.0f} s")
