@@ -64,9 +64,9 @@ constexpr int kCancelEvery = 64;
 
 constexpr int kRestartLogCap = 64;
 
-// Control block of one solve: written only by the workgroup that finishes a
-// pass last (or by the single workgroup of the small-system kernel), read by
-// every workgroup before the next pass.
+// Control block of one solve.  The per-pass driver keeps two (by launch parity): workgroup 0 of a
+// launch publishes the state it decided, which every workgroup of the next launch reads.  The
+// single-workgroup and persistent drivers keep one, updated by one thread between passes.
 struct Ctrl {
   double alpha;          // alpha_t of the pass about to run
   double beta;           // y = P + beta (P - R) for the pass about to run

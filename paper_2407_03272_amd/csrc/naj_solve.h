@@ -2,19 +2,19 @@
 // matrix (product, Jacobi-type step and the partial sums of the restart
 // inner product and the residual monitor) followed by one scalar decision:
 // the restart test and the restart/momentum branches of Algorithm 2, or the
-// stopping test.  The decision is taken by the workgroup that finishes the
-// pass last, from the per-workgroup partial sums added in a fixed order, so
-// every run of the same system takes the same decisions.  Restarts never
-// move data: they only change which of three vector buffers plays x^{t-1},
-// x^{t-2} and x^t in the next pass.
+// stopping test.  The decision is taken from the per-workgroup partial sums
+// added in a fixed order, so every run of the same system takes the same
+// decisions.  Restarts never move data: they only change which of three
+// vector buffers plays x^{t-1}, x^{t-2} and x^t in the next pass.
 //
 // Two drivers share the pass:
-//  * k_pass64: one launch per pass.  Kernel boundaries order the passes
-//    (the next launch sees the previous one's vector writes and control
-//    block); large systems use it.
+//  * k_pass64: one launch per pass (every system above about 24 slices).
+//    Kernel boundaries order the passes; every workgroup of launch k takes
+//    the decision after pass k-1 itself, at its start.
 //  * k_solve64: one persistent launch per solve.  With a single workgroup
-//    the passes are separated by workgroup barriers only (small systems);
-//    with several co-resident workgroups by a counting grid barrier.
+//    the passes are separated by workgroup barriers only (tiny systems);
+//    with several co-resident workgroups by a counting grid barrier (an
+//    option, NAJ_MODE=2).
 #pragma once
 
 #include "naj_device.h"
