@@ -23,6 +23,7 @@
 #include <map>
 #include <mutex>
 #include <queue>
+#include <thread>
 #include <unordered_map>
 
 using namespace naj;
@@ -692,7 +693,6 @@ struct naj_system {
   long long spin_ticks = 0;
   int64_t bytes = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  hipEvent_t evc[2] = {nullptr, nullptr};
   int* hflag = nullptr;            // pinned host words: [0], [1] the phase word of the chunks in flight,
                                    // [2] the cancel word (naj_cancel), read by the solve's scalar control
   Pool* pool = nullptr;            // device memory source (null: the runtime allocator)
@@ -740,8 +740,6 @@ void free_system(naj_system* s) {
   for (auto& v : s->fvec) sys_free(s, v);
   if (s->ev0) (void)hipEventDestroy(s->ev0);
   if (s->ev1) (void)hipEventDestroy(s->ev1);
-  for (auto& e : s->evc)
-    if (e) (void)hipEventDestroy(e);
   if (s->hflag) (void)hipHostFree(s->hflag);
   delete s;
 }
@@ -1329,9 +1327,12 @@ naj_status run_solve(naj_system* s, SolveArgs& a, const naj_opts& o, hipStream_t
     HIP_TRY(hipEventRecord(s->ev1, st));
     return NAJ_OK;
   }
-  // one launch per pass, enqueued in chunks; the host checks the phase word of
-  // the previous chunk while the current one runs, so the device never waits.  Launch k takes its
-  // index as an argument: it publishes its control state in ctrl[k & 1] (see k_pass64).
+  // One launch per pass, enqueued in chunks of 4-8.  The chunk's last launch stores the phase it
+  // published in a pinned host word (workgroup 0, after its decision); the host marks the word pending
+  // before enqueuing the chunk and, while the next chunk runs, waits for the word of the previous one.
+  // No event or copy sits between the launches, and a finished solve leaves at most two chunks of
+  // launches behind it (each copies the finished state forward in a few microseconds).  Launch k takes
+  // its index parity as an argument: it publishes its control state in ctrl[k & 1] (see k_pass64).
   const bool mx = o.precision == NAJ_MIXED;
   const void* fn = pass_kernel(ud, mx ? s->pass_bs_mx : s->pass_bs, s->ymode != 0, mx ? s->nt_mx != 0 : s->nt != 0, mx);
   const dim3 grid(mx ? s->grid_mx : s->grid), block(mx ? s->pass_bs_mx : s->pass_bs);
@@ -1340,6 +1341,31 @@ naj_status run_solve(naj_system* s, SolveArgs& a, const naj_opts& o, hipStream_t
   const int64_t max_pass = o.precision == NAJ_MIXED
                                ? 3 + (int64_t)(o.max_refine + 1) * (1 + (int64_t)o.max_iter)
                                : 3 + (int64_t)o.max_iter + (int64_t)o.max_iter / std::max(1, o.confirm_gap) + 1;
+  constexpr int kPending = -1;   // no phase has this value
+  // Waits for chunk slot `slot`'s phase word.  The stream is asked now and then: an error it reports,
+  // or a drained stream with the word still pending, ends the solve with NAJ_EDEVICE.
+  auto wait_word = [&](int slot, int* phase) -> naj_status {
+    for (int64_t spin = 1;; ++spin) {
+      const int v = __atomic_load_n(&s->hflag[slot], __ATOMIC_ACQUIRE);
+      if (v != kPending) {
+        *phase = v;
+        return NAJ_OK;
+      }
+      if (spin % 1024 == 0) {
+        const hipError_t e = hipStreamQuery(st);
+        if (e == hipSuccess) {
+          const int w = __atomic_load_n(&s->hflag[slot], __ATOMIC_ACQUIRE);
+          if (w != kPending) {
+            *phase = w;
+            return NAJ_OK;
+          }
+          return fail(NAJ_EDEVICE, "the pass launches finished without publishing their phase");
+        }
+        if (e != hipErrorNotReady) return fail(NAJ_EDEVICE, "solve stream: %s", hipGetErrorString(e));
+        std::this_thread::yield();
+      }
+    }
+  };
   int64_t launched = 0;
   int chunk = 4, cur = 0, prev = -1;
   int kidx = 0;
@@ -1355,28 +1381,30 @@ naj_status run_solve(naj_system* s, SolveArgs& a, const naj_opts& o, hipStream_t
   HIP_TRY(hipEventRecord(s->ev0, st));
   for (;;) {
     const int64_t n_now = std::min<int64_t>(chunk, max_pass - launched);
+    __atomic_store_n(&s->hflag[cur], kPending, __ATOMIC_RELEASE);
     for (int64_t i = 0; i < n_now; ++i) {
       const int64_t k = launched + i;
       kidx = k == 0 ? 0 : 2 - (int)(k & 1);   // the kernel needs only k > 0 and the parity of k
-      // the chunk's last launch stores its published phase in the pinned word the host polls
       flag = i + 1 == n_now ? &s->hflag[cur] : nullptr;
       HIP_TRY(hipLaunchKernel(fn, grid, block, pargs, 0, st));
     }
     launched += n_now;
     *final = a.ctrl + ((launched - 1) & 1);
-    HIP_TRY(hipEventRecord(s->evc[cur], st));
+    int phase = 0;
     if (prev >= 0) {
-      HIP_TRY(hipEventSynchronize(s->evc[prev]));
-      if (s->hflag[prev] == PH_DONE) break;
+      const naj_status rc = wait_word(prev, &phase);
+      if (rc != NAJ_OK) return rc;
+      if (phase == PH_DONE) break;
     }
     if (launched >= max_pass) {
-      HIP_TRY(hipEventSynchronize(s->evc[cur]));
-      if (s->hflag[cur] == PH_DONE) break;
+      const naj_status rc = wait_word(cur, &phase);
+      if (rc != NAJ_OK) return rc;
+      if (phase == PH_DONE) break;
       return fail(NAJ_EDEVICE, "solve did not finish within %lld passes", (long long)launched);
     }
     prev = cur;
     cur ^= 1;
-    chunk = std::min(chunk * 2, 16);
+    chunk = std::min(chunk * 2, 8);
   }
   HIP_TRY(hipEventRecord(s->ev1, st));
   return NAJ_OK;
@@ -1733,8 +1761,6 @@ static naj_status create_system_impl(int64_t n, int64_t nnz, const int32_t* rowp
     STEP(dev_alloc(s, &s->scal, 8));
     HSTEP(hipEventCreate(&s->ev0));
     HSTEP(hipEventCreate(&s->ev1));
-    HSTEP(hipEventCreateWithFlags(&s->evc[0], hipEventDisableTiming));
-    HSTEP(hipEventCreateWithFlags(&s->evc[1], hipEventDisableTiming));
     HSTEP(hipHostMalloc((void**)&s->hflag, 4 * sizeof(int), hipHostMallocDefault));
     for (int i = 0; i < 4; ++i) s->hflag[i] = 0;
   }
