@@ -389,25 +389,33 @@ def test_irregular_layout_chung_lu(naj):
     np.testing.assert_allclose(res.cpu().numpy(), ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_balanced_wave_lists_are_bitwise(naj, monkeypatch, precision):
+@pytest.mark.parametrize("precision,bs_mixed", [(0, None), (1, None), (1, "512")])
+def test_balanced_wave_lists_are_bitwise(naj, monkeypatch, precision, bs_mixed):
     """The sorted layout's per-pass kernel takes its long rows and slices from per-wave lists balanced on the
     host (longest first to the least-loaded wave).  Every row is computed as with the strided assignment,
     so the iterates are bit-identical; only the grouping of the partial sums differs (the same schedule
-    here).  Float64 and mixed precision, against the same system built without the lists."""
-    _say("balanced wave lists on/off, chung-lu 2^15, precision", precision)
+    here).  Float64 and mixed precision, against the same system built without the lists; with 512-thread
+    mixed launches the mixed solve uses a second list built for that launch shape."""
+    _say("balanced wave lists on/off, chung-lu 2^15, precision", precision, "mixed block", bs_mixed)
     s = W.chung_lu_laplacian(1 << 15, 16, 2.5, seed=81, b_seed=82)
     out = []
     for lists in ("0", "1"):
         monkeypatch.setenv("NAJ_WAVE_LISTS", lists)
+        if bs_mixed:
+            monkeypatch.setenv("NAJ_BS_MIXED", bs_mixed)
         sysm = naj.System(s.rowptr, s.colidx, s.vals)
         monkeypatch.delenv("NAJ_WAVE_LISTS")
+        if bs_mixed:
+            monkeypatch.delenv("NAJ_BS_MIXED")
         assert sysm.info()["layout"] == 1
         x, info = sysm.solve(s.b, tol=1e-8, max_iter=20000, precision=precision)
         assert info.status == 0
-        out.append((x.cpu().numpy(), info))
+        out.append((x.cpu().numpy(), info, sysm.info()))
         sysm.close()
-    (x0, i0), (x1, i1) = out
+    (x0, i0, d0), (x1, i1, d1) = out
+    # the lists exist: 4 bytes per item (long rows and slices) per launch shape, plus the offsets
+    tables = 2 if bs_mixed else 1
+    assert d1["device_bytes"] - d0["device_bytes"] >= 4 * tables * d1["nslices"]
     assert i0.iterations == i1.iterations and i0.restart_log == i1.restart_log
     assert np.array_equal(x0, x1)
 
