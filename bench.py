@@ -38,12 +38,24 @@ PROFILES = os.path.join(ROOT, "profiles")
 PASS_KERNEL_SOURCES = ("naj_device.h", "naj_solve.h", "naj_partition.h")
 
 
-def kernel_source_hash() -> str:
+def strip_comments(text: str) -> str:
+    """C++ source without its comments and trailing blanks (the pass kernel's sources hold no string
+    literal with a comment marker), so a comment edit leaves the key of the counter records unchanged."""
+    import re
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+
+
+def kernel_source_hash(read=None) -> str:
+    """SHA-256 of the pass kernel's sources without comments; `read(name)` supplies a source's text
+    (default: the file in the package)."""
     import hashlib
     h = hashlib.sha256()
     for name in PASS_KERNEL_SOURCES:
+        text = read(name) if read else open(os.path.join(CSRC, name), encoding="utf-8").read()
         h.update(name.encode())
-        h.update(open(os.path.join(CSRC, name), "rb").read())
+        h.update(strip_comments(text).encode())
     return h.hexdigest()
 
 
