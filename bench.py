@@ -59,9 +59,10 @@ def kernel_source_hash(read=None) -> str:
     return h.hexdigest()
 
 
-def measured_traffic(workload: str, grid: int | None = None):
+def measured_traffic(workload: str, grid: int | None = None, value_bytes: int | None = None):
     """HBM bytes per pass from the committed rocprofv3 counter runs, or None when none exist for this
-    workload, the pass kernel's sources changed since they were taken, or the pass ran on another grid."""
+    workload, the pass kernel's sources changed since they were taken, or the pass ran on another grid or
+    read values of another size."""
     path = os.path.join(PROFILES, f"k_pass64_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
@@ -69,6 +70,8 @@ def measured_traffic(workload: str, grid: int | None = None):
     if rec.get("kernel_source_sha256") != kernel_source_hash():
         return None
     if grid is not None and rec.get("grid") not in (None, grid):
+        return None
+    if value_bytes is not None and rec.get("value_bytes", 8) != value_bytes:
         return None
     return rec["traffic_bytes_per_pass"]
 
@@ -83,27 +86,29 @@ def bytes_per_iteration(n: int, nnz: int, s_v: int = 8, s_x: int = 8, k: int = 1
     return s_v * nnz + 4 * (nnz - nnz_off) + 4 * (n + 1) + 4 * k * s_x * n + jb * s_x * n
 
 
-def bytes_per_residual(n: int, nnz: int, nnz_off: int = 0) -> int:
-    """Algorithmic bytes of one float64 residual pass r = b - Q x: matrix, row pointers, read x and b."""
-    return 8 * nnz + 4 * (nnz - nnz_off) + 4 * (n + 1) + 2 * 8 * n
+def bytes_per_residual(n: int, nnz: int, nnz_off: int = 0, s_v: int = 8) -> int:
+    """Algorithmic bytes of one float64 residual pass r = b - Q x: matrix, row pointers, read x and b
+    (s_v bytes per value: 4 where the layout reads the exact float32 copy)."""
+    return s_v * nnz + 4 * (nnz - nnz_off) + 4 * (n + 1) + 2 * 8 * n
 
 
-def bytes_per_refinement_residual(n: int, nnz: int, nnz_off: int = 0) -> int:
+def bytes_per_refinement_residual(n: int, nnz: int, nnz_off: int = 0, s_v: int = 8) -> int:
     """Float64 residual pass of the mixed loop with the update fused: matrix, row pointers, read x (f64), d (f32)
     and b, write x + d (f64) and fl32(r) (f32)."""
-    return 8 * nnz + 4 * (nnz - nnz_off) + 4 * (n + 1) + 8 * n + 4 * n + 8 * n + 8 * n + 4 * n
+    return s_v * nnz + 4 * (nnz - nnz_off) + 4 * (n + 1) + 8 * n + 4 * n + 8 * n + 8 * n + 4 * n
 
 
-def solve_bytes(n: int, nnz: int, info, mixed: bool, jb: int = 0, nnz_off: int = 0) -> int:
-    """Bytes of a whole solve from its pass counts (norm of b = 8n bytes): the CSR yardstick, or with
-    nnz_off the bytes the layout moves."""
+def solve_bytes(n: int, nnz: int, info, mixed: bool, jb: int = 0, nnz_off: int = 0, vb: int = 8) -> int:
+    """Bytes of a whole solve from its pass counts (norm of b = 8n bytes), with vb bytes per matrix value
+    read by the float64 passes (the element size s_v of the yardstick): the CSR yardstick, or with nnz_off
+    the bytes the layout moves."""
     if not mixed:
         it = info.iterations
         conf = info.passes - it - 1
-        return (8 * n + it * bytes_per_iteration(n, nnz, jb=jb, nnz_off=nnz_off)
-                + conf * bytes_per_residual(n, nnz, nnz_off))
+        return (8 * n + it * bytes_per_iteration(n, nnz, s_v=vb, jb=jb, nnz_off=nnz_off)
+                + conf * bytes_per_residual(n, nnz, nnz_off, s_v=vb))
     return (8 * n + info.iterations * bytes_per_iteration(n, nnz, s_v=4, s_x=4, jb=jb, nnz_off=nnz_off)
-            + info.confirmations * bytes_per_refinement_residual(n, nnz, nnz_off))
+            + info.confirmations * bytes_per_refinement_residual(n, nnz, nnz_off, s_v=vb))
 
 
 def make_workload(name: str):
@@ -565,8 +570,9 @@ def bench_single(args, workload: str, progress, steps: int, warmup: int, precisi
     info = infos[-1]
     sinfo = sysm.info()
     nnz_off = sinfo["offset_nnz"]
-    alg_bytes = solve_bytes(n, nnz, info, mixed, jb)                  # CSR int32 yardstick
-    moved_bytes = solve_bytes(n, nnz, info, mixed, jb, nnz_off)      # what the layout reads and writes
+    vb = sinfo["value_bytes"]          # 4: the float64 passes read the exact float32 copy of the values
+    alg_bytes = solve_bytes(n, nnz, info, mixed, jb, vb=vb)           # CSR int32 yardstick, s_v = vb
+    moved_bytes = solve_bytes(n, nnz, info, mixed, jb, nnz_off, vb)  # what the layout reads and writes
     kernel_s = float(np.mean(kms)) / 1e3
     achieved = alg_bytes / kernel_s / 1e9
     solves_s = steps / total
@@ -576,10 +582,13 @@ def bench_single(args, workload: str, progress, steps: int, warmup: int, precisi
         wl = (f"{sysobj.name}: n={n}, nnz={nnz}; float32 inner accelerated Jacobi with float64 reductions inside "
               f"float64 iterative refinement, x0=0, restart on, K0=2, inner tol 1e-4, final relres <= 1e-8, single solve")
     else:
-        per_launch = bytes_per_iteration(n, nnz, jb=jb)
-        moved_launch = bytes_per_iteration(n, nnz, jb=jb, nnz_off=nnz_off)
+        per_launch = bytes_per_iteration(n, nnz, s_v=vb, jb=jb)
+        moved_launch = bytes_per_iteration(n, nnz, s_v=vb, jb=jb, nnz_off=nnz_off)
         wl = (f"{sysobj.name}: n={n}, nnz={nnz}, float64, x0=0, restart on, K0=2, tol 1e-8, single solve "
               f"(plain FP64 one system at a time)")
+        if vb == 4:
+            wl += ("; float64 arithmetic and vectors, matrix values read from their float32 copy (every value is "
+                   "exact in float32: results bit-identical to 8-byte values)")
     if jb:
         wl += f"; block-diagonal J of eq. (J-blkdiag), blocks of {jb} rows"
     if obj:
@@ -601,7 +610,8 @@ def bench_single(args, workload: str, progress, steps: int, warmup: int, precisi
                    "iterations": info.iterations, "restarts": info.restarts, "confirmations": info.confirmations,
                    "passes": info.passes, "grid": info.grid, "relres": info.relres,
                    "layout": sinfo["layout"], "offset_slices": sinfo["offset_slices"],
-                   "nslices": sinfo["nslices"], "offset_nnz": nnz_off, "jblock": jb, "stop": args.stop,
+                   "nslices": sinfo["nslices"], "offset_nnz": nnz_off, "value_bytes": vb, "jblock": jb,
+                   "stop": args.stop,
                    "objgap": info.objgap if obj else None},
         "p50_ms": float(np.percentile(lat, 50) * 1e3),
         "p99_ms": float(np.percentile(lat, 99) * 1e3),
@@ -609,14 +619,20 @@ def bench_single(args, workload: str, progress, steps: int, warmup: int, precisi
         "gbps_solve": achieved,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None if (mixed or jb) else measured_traffic(workload, info.grid),
+                     "traffic": None if (mixed or jb) else measured_traffic(workload, info.grid, vb),
                      "kernel": "k_pass64 (fused iteration pass, one launch per pass)",
                      "launches_per_solve": info.passes,
                      "algorithmic_bytes_per_launch": per_launch,
                      "layout_bytes_per_launch": moved_launch,
                      "layout_gbps": moved_bytes / kernel_s / 1e9,
                      "layout_frac": moved_bytes / kernel_s / 1e9 / HBM_PEAK_GBS,
-                     "mean_launch_us": kernel_s / info.passes * 1e6},
+                     "mean_launch_us": kernel_s / info.passes * 1e6,
+                     "yardstick_note": ("achieved counts the CSR yardstick's bytes: (s_v + 4) per nonzero (int32 "
+                                        "columns), int32 row pointers, four vector streams, with s_v the bytes "
+                                        f"of a stored value ({4 if mixed else vb}"
+                                        + ("; the float64 passes read the values' exact float32 copy" if vb == 4 and not mixed else "")
+                                        + "); the layout moves layout_bytes_per_launch (no column indices in "
+                                        "column-offset slices); layout_frac is the pass against peak by those bytes")},
     }
     if compare:
         # the same system solved in the other precision, for the mixed-vs-FP64 comparison
@@ -673,6 +689,20 @@ def bench_default(args, progress) -> dict:
     t_start = time.perf_counter()
     line = bench_single(args, "laplace3d_128", progress, args.steps, args.warmup, "fp64", not args.no_compare,
                         not args.no_cpu_baseline)
+    if line["config"].get("value_bytes") == 4:
+        # the same solve with the 8-byte values (NAJ_VALUES32=0, its own 256 x 3 launch): the same answer
+        # bit for bit, for the comparison with the 4-byte reads the value above uses
+        os.environ["NAJ_VALUES32"] = "0"
+        try:
+            v8 = bench_single(args, "laplace3d_128", progress, max(3, args.steps // 2), 1, "fp64", False, False)
+        finally:
+            del os.environ["NAJ_VALUES32"]
+        line["values8"] = {"solves_per_s": v8["value"], "ms_per_step": v8["ms_per_step"],
+                           "mean_launch_us": v8["roofline"]["mean_launch_us"], "grid": v8["config"]["grid"],
+                           "layout_bytes_per_launch": v8["roofline"]["layout_bytes_per_launch"],
+                           "layout_frac": v8["roofline"]["layout_frac"], "frac": v8["roofline"]["frac"],
+                           "iterations": v8["config"]["iterations"],
+                           "note": "8-byte matrix values (NAJ_VALUES32=0); every other setting as in the value"}
     ab = attainable_bandwidth(progress)
     line["attainable_bandwidth"] = ab
     rf = line["roofline"]

@@ -165,6 +165,20 @@ naj_status naj_system_info(const naj_system *sys, int64_t *n, int64_t *nnz, int6
                            int32_t *layout, int64_t *stored_entries);
 
 /*
+ * Bytes per stored matrix value read by the float64 passes of the single-solve drivers: 4 when every
+ * value converts to float32 and back unchanged (checked when the system is created, e.g. a graph
+ * Laplacian with integer weights or a stencil), else 8.  With 4, those passes read the float32 copy of
+ * the values that mixed precision keeps anyway and widen each value to float64 where it is used, so
+ * they compute exactly what they compute from the 8-byte values (every result is the same bit for
+ * bit) on half the value bytes; J of eq. (J-diag), the absolute row sum, comes from the same values.
+ * NAJ_VALUES32=0 in the environment at creation keeps 8 bytes.  A block-J system (eq. (J-blkdiag))
+ * always reads 8.
+ *   bytes : host, 4 or 8
+ * Errors: NAJ_EINVAL for a NULL argument.
+ */
+naj_status naj_system_value_bytes(const naj_system *sys, int32_t *bytes);
+
+/*
  * Slices of the sliced layout (layout 0) stored in the column-offset form.  When all 64 rows of a
  * slice store their entries at columns row + S[0] < row + S[1] < ... of one increasing offset list
  * S common to the slice (a stencil pattern; at most 15 offsets, every row + S[k] inside [0, n)),

@@ -80,6 +80,14 @@ __global__ void k_check_vals(const double* vals, int64_t nnz, int* flag) {
   }
 }
 
+// Flags (64) a stored value that its float32 copy does not hold exactly (widening the copy back, as the
+// passes that read it do, must give the value itself).
+__global__ void k_check_exact32(const double* v, const float* v32, int64_t count, int* flag) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
+    if ((double)v32[i] != v[i]) atomicOr(flag, 64);
+  }
+}
+
 __global__ void k_check_D(const double* D, int64_t n, double* dinv, int* flag) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const double d = D[i];
@@ -672,6 +680,8 @@ struct naj_system {
   int ymode = 0;                   // materialized momentum form (irregular layout: one gathered vector)
   int nt = 0;                      // float64 iteration passes load matrix entries non-temporally
   int nt_mx = 0;                   // the same for the float32 inner passes of mixed solves
+  int val_exact32 = 0;             // every stored value is exact in float32: the float64 per-pass kernels
+                                   // read the float32 copy (4 bytes per entry) and widen it where used
   double* part = nullptr;          // 3 * max_grid
   Ctrl* ctrl = nullptr;
   Barrier* bar = nullptr;
@@ -760,35 +770,42 @@ int jm_of(const naj_system* s) { return s->jblock > 0 ? kJBlock : (s->dinv ? kJU
 
 // Per-pass kernel instances: J mode, block size, momentum form, non-temporal matrix loads and the phases
 // of float64 (PS = kPhasesFp64) or mixed-precision (kPhasesMixed) solves.
-template <bool YM, int PS>
+template <bool YM, int PS, bool V32>
 const void* pass_kernel_ym(int jm, int bs) {
   if (bs == 1024)
-    return jm ? (const void*)k_pass64<kJUser, 1024, YM, false, PS> : (const void*)k_pass64<kJRowSum, 1024, YM, false, PS>;
+    return jm ? (const void*)k_pass64<kJUser, 1024, YM, false, PS, V32>
+              : (const void*)k_pass64<kJRowSum, 1024, YM, false, PS, V32>;
   if (bs == 512)
-    return jm ? (const void*)k_pass64<kJUser, 512, YM, false, PS> : (const void*)k_pass64<kJRowSum, 512, YM, false, PS>;
-  return jm ? (const void*)k_pass64<kJUser, 256, YM, false, PS> : (const void*)k_pass64<kJRowSum, 256, YM, false, PS>;
+    return jm ? (const void*)k_pass64<kJUser, 512, YM, false, PS, V32>
+              : (const void*)k_pass64<kJRowSum, 512, YM, false, PS, V32>;
+  return jm ? (const void*)k_pass64<kJUser, 256, YM, false, PS, V32> : (const void*)k_pass64<kJRowSum, 256, YM, false, PS, V32>;
 }
 
-template <int PS>
+template <int PS, bool V32>
 const void* pass_kernel_ps(int jm, int bs, bool ym, bool nt) {
   if (nt && bs == 256) {
     if (jm == kJBlock) return (const void*)k_pass64<kJBlock, 256, false, true, PS>;
     if (ym)
-      return jm ? (const void*)k_pass64<kJUser, 256, true, true, PS> : (const void*)k_pass64<kJRowSum, 256, true, true, PS>;
-    return jm ? (const void*)k_pass64<kJUser, 256, false, true, PS> : (const void*)k_pass64<kJRowSum, 256, false, true, PS>;
+      return jm ? (const void*)k_pass64<kJUser, 256, true, true, PS, V32>
+                : (const void*)k_pass64<kJRowSum, 256, true, true, PS, V32>;
+    return jm ? (const void*)k_pass64<kJUser, 256, false, true, PS, V32>
+              : (const void*)k_pass64<kJRowSum, 256, false, true, PS, V32>;
   }
   if (jm == kJBlock) {
     if (bs == 1024) return (const void*)k_pass64<kJBlock, 1024, false, false, PS>;
     if (bs == 512) return (const void*)k_pass64<kJBlock, 512, false, false, PS>;
     return (const void*)k_pass64<kJBlock, 256, false, false, PS>;
   }
-  return ym ? pass_kernel_ym<true, PS>(jm, bs) : pass_kernel_ym<false, PS>(jm, bs);
+  return ym ? pass_kernel_ym<true, PS, V32>(jm, bs) : pass_kernel_ym<false, PS, V32>(jm, bs);
 }
 
-// A block-J system always uses the regular layout in the two-iterate form.  nt: the iteration passes
-// load matrix entries non-temporally (instances for the 256-thread pass only).
-const void* pass_kernel(int jm, int bs, bool ym, bool nt, bool mixed) {
-  return mixed ? pass_kernel_ps<kPhasesMixed>(jm, bs, ym, nt) : pass_kernel_ps<kPhasesFp64>(jm, bs, ym, nt);
+// A block-J system always uses the regular layout in the two-iterate form, with its 8-byte values.
+// nt: the iteration passes load matrix entries non-temporally (instances for the 256-thread pass only).
+// v32: the float64 passes read the float32 copy of the values, which holds every value exactly.
+const void* pass_kernel(int jm, int bs, bool ym, bool nt, bool mixed, bool v32) {
+  if (v32 && jm != kJBlock)
+    return mixed ? pass_kernel_ps<kPhasesMixed, true>(jm, bs, ym, nt) : pass_kernel_ps<kPhasesFp64, true>(jm, bs, ym, nt);
+  return mixed ? pass_kernel_ps<kPhasesMixed, false>(jm, bs, ym, nt) : pass_kernel_ps<kPhasesFp64, false>(jm, bs, ym, nt);
 }
 
 // LDS-resident single-workgroup solve: 32 n bytes of vectors must fit beside the kernel's own LDS.
@@ -816,10 +833,17 @@ naj_status choose_grid(naj_system* s, hipStream_t st) {
   if (nxcd < 1) nxcd = 1;
   if (nxcd > kMaxDomains) nxcd = kMaxDomains;
   s->nxcd = nxcd;
-  int bs = env_int("NAJ_BS", 256);   // 256 threads x 3 per CU measured best on the 128^3 Laplacian
-  if (bs != 256 && bs != 512 && bs != 1024) bs = 256;
+  // 256 threads x 3 per CU measured best for 8-byte values on the 128^3 Laplacian; with 4-byte values
+  // (exact in float32) 512 x 3 on regular layouts: 128^3 31.4 against 33.2 us per pass, 160^3 54.0
+  // against 72.1 (more waves in flight for the smaller loads, as for the float32 inner pass)
+  const int bs_default = (s->val_exact32 && s->layout == 0) ? 512 : 256;
+  int bs = env_int("NAJ_BS", bs_default);
+  if (bs != 256 && bs != 512 && bs != 1024) bs = bs_default;
   s->pass_bs = bs;
-  const int per_cu = std::max(1, env_int("NAJ_WG_PER_CU", bs == 256 ? 3 : 2 * 256 / bs));
+  // three workgroups per CU for 256 threads, and for 512 threads with 4-byte values (the measured
+  // shapes above); otherwise 512 x 1 or 1024 x 1
+  const int per_cu_default = (bs == 256 || (bs == 512 && s->val_exact32 && s->layout == 0)) ? 3 : 2 * 256 / bs;
+  const int per_cu = std::max(1, env_int("NAJ_WG_PER_CU", per_cu_default));
   int g = per_cu * s->cus;
   g -= g % nxcd;
   if (g < nxcd) g = nxcd;
@@ -1334,7 +1358,8 @@ naj_status run_solve(naj_system* s, SolveArgs& a, const naj_opts& o, hipStream_t
   // launches behind it (each copies the finished state forward in a few microseconds).  Launch k takes
   // its index parity as an argument: it publishes its control state in ctrl[k & 1] (see k_pass64).
   const bool mx = o.precision == NAJ_MIXED;
-  const void* fn = pass_kernel(ud, mx ? s->pass_bs_mx : s->pass_bs, s->ymode != 0, mx ? s->nt_mx != 0 : s->nt != 0, mx);
+  const void* fn = pass_kernel(ud, mx ? s->pass_bs_mx : s->pass_bs, s->ymode != 0, mx ? s->nt_mx != 0 : s->nt != 0, mx,
+                               s->val_exact32 != 0);
   const dim3 grid(mx ? s->grid_mx : s->grid), block(mx ? s->pass_bs_mx : s->pass_bs);
   // passes: norm of b + iterations + confirmations (at most one per confirm_gap iterations, plus one),
   // and the launch that takes the last decision
@@ -1714,6 +1739,27 @@ static naj_status create_system_impl(int64_t n, int64_t nnz, const int32_t* rowp
     goto bad;
   }
   STEP(build_layout(s, rowptr, colidx, vals, st));
+  // 4-byte values for the float64 passes when every stored value is exact in float32 (graph Laplacians
+  // with integer weights, stencils, the Section 4.1 matrix): the same products and sums on half the
+  // value bytes.  NAJ_VALUES32=0 keeps the 8-byte values.
+  if (env_int("NAJ_VALUES32", 1) && !jblock) {
+    HSTEP(hipMemsetAsync(flag, 0, sizeof(int), st));
+    const int64_t ns = s->nslices > 0 ? (int64_t)s->hslice[s->nslices] : 0;
+    if (ns > 0) {
+      hipLaunchKernelGGL(k_check_exact32, dim3(blocks_for(ns, kAux)), dim3(kAux), 0, st, s->val, s->val32, ns, flag);
+      HSTEP(hipGetLastError());
+    }
+    const int64_t nl = s->n_long > 0 ? (int64_t)s->hlong[s->n_long] : 0;
+    if (nl > 0) {
+      hipLaunchKernelGGL(k_check_exact32, dim3(blocks_for(nl, kAux)), dim3(kAux), 0, st, s->lval, s->lval32, nl, flag);
+      HSTEP(hipGetLastError());
+    }
+    HSTEP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    HSTEP(hipStreamSynchronize(st));
+    s->val_exact32 = hflag == 0 ? 1 : 0;
+    hflag = 0;
+    HSTEP(hipMemsetAsync(flag, 0, sizeof(int), st));
+  }
   s->ymode = env_int("NAJ_YMODE", s->layout == 1 ? 1 : 0) ? 1 : 0;
   if (jblock) {   // eq. (J-blkdiag): inverse blocks from the caller's CSR
     s->ymode = 0;
@@ -1740,7 +1786,8 @@ static naj_status create_system_impl(int64_t n, int64_t nnz, const int32_t* rowp
     // the Section 4.1 system n = 6000: 95.5 -> 89.4 us; Chung-Lu n = 2^22: 911 -> 892 us).  A pass that
     // fits keeps ordinary loads: the whole pass then stays in the MALL between passes (128^3: 36.9 us;
     // 46.5 us with non-temporal loads).
-    const int64_t pass_bytes = 8 * s->stored + 4 * (s->stored - s->off_nnz) + 32 * n + 8 * (int64_t)jblock * n;
+    const int64_t pass_bytes = (s->val_exact32 ? 4 : 8) * s->stored + 4 * (s->stored - s->off_nnz) + 32 * n +
+                               8 * (int64_t)jblock * n;
     s->nt = env_int("NAJ_NT", pass_bytes > kMallBytes ? 1 : 0) ? 1 : 0;
     // the same rule for the float32 inner pass of mixed solves (4-byte values, float32 vectors and r32)
     const int64_t inner_bytes = 4 * s->stored + 4 * (s->stored - s->off_nnz) + 20 * n + 4 * (int64_t)jblock * n;
@@ -1817,6 +1864,12 @@ naj_status naj_system_info(const naj_system* s, int64_t* n, int64_t* nnz, int64_
   if (device_bytes) *device_bytes = s->bytes;
   if (layout) *layout = s->layout;
   if (stored_entries) *stored_entries = s->stored;
+  return NAJ_OK;
+}
+
+naj_status naj_system_value_bytes(const naj_system* s, int32_t* bytes) {
+  if (!s || !bytes) return fail(NAJ_EINVAL, "system and bytes are required");
+  *bytes = s->val_exact32 ? 4 : 8;
   return NAJ_OK;
 }
 

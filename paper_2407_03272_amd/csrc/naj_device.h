@@ -18,6 +18,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "naj_partition.h"
 
 namespace naj {
@@ -298,14 +300,15 @@ __device__ __forceinline__ T abs_of(T v) {
 // acc = sum_k v_k y_{c_k} and asum = sum_k |v_k|, with y = P + beta (P - R) (two-iterate form),
 // y = R (materialized form), y = P (bz) or y = 0 (zy).  OFF: the slice's columns come from its
 // offsets.  The two column sources are separate instances so each keeps its own register budget.
-template <bool OFF, bool YM, bool NT, typename T>
+template <bool OFF, bool YM, bool NT, typename T, typename V = T>
 __device__ __forceinline__ void fused_row_sums(const int32_t* __restrict__ cp, OffPtr so,
-                                               int32_t row, const T* __restrict__ vp, int width,
+                                               int32_t row, const V* __restrict__ vp, int width,
                                                const T* __restrict__ P, const T* __restrict__ R, T beta, bool bz,
                                                bool zy, T& acc, T& asum) {
   for (int k0 = 0; k0 < width; k0 += kUnroll) {
     int c[kUnroll];
-    T v[kUnroll], y[kUnroll];
+    V v[kUnroll];   // stored values (float with the float32 copy of a float64 pass), widened where used
+    T y[kUnroll];
 #pragma unroll
     for (int j = 0; j < kUnroll; ++j)
       if (k0 + j < width) {
@@ -338,22 +341,24 @@ __device__ __forceinline__ void fused_row_sums(const int32_t* __restrict__ cp, O
 #pragma unroll
     for (int j = 0; j < kUnroll; ++j)
       if (k0 + j < width) {
-        acc = acc + v[j] * y[j];
-        asum = asum + abs_of(v[j]);
+        const T vj = (T)v[j];
+        acc = acc + vj * y[j];
+        asum = asum + abs_of(vj);
       }
   }
 }
 
 // One lane's sum_k v_k x_{c_k} over its slice (OFF as above); with D, x = X + (double)D at every
 // gathered column.
-template <bool OFF>
+template <bool OFF, typename V = double>
 __device__ __forceinline__ double resid_row_sum(const int32_t* __restrict__ cp, OffPtr so,
-                                                int32_t row, const double* __restrict__ vp, int width,
+                                                int32_t row, const V* __restrict__ vp, int width,
                                                 const double* __restrict__ X, const float* __restrict__ D) {
   double acc = 0.0;
   for (int k0 = 0; k0 < width; k0 += kUnroll) {
     int c[kUnroll];
-    double v[kUnroll], xj[kUnroll];
+    V v[kUnroll];
+    double xj[kUnroll];
 #pragma unroll
     for (int j = 0; j < kUnroll; ++j)
       if (k0 + j < width) {
@@ -378,14 +383,16 @@ __device__ __forceinline__ double resid_row_sum(const int32_t* __restrict__ cp, 
     }
 #pragma unroll
     for (int j = 0; j < kUnroll; ++j)
-      if (k0 + j < width) acc = acc + v[j] * xj[j];
+      if (k0 + j < width) acc = acc + (double)v[j] * xj[j];
   }
   return acc;
 }
 
 // One slice of the fused pass: u = Q y, g = u - b, x = y - J^{-1} g, d = x - P,
 // with y = P + beta (P - R) formed at every gathered column (y = P when bz).
-template <int JM, bool YM, bool NT = false>
+// V32: the values are read from the float32 copy, which holds every value exactly (checked when the
+// system is created), and widened to float64 where they are used: the same arithmetic on 4-byte loads.
+template <int JM, bool YM, bool NT = false, bool V32 = false>
 __device__ __forceinline__ void iter_slice(const SolveArgs& a, int64_t s, int lane, const double* __restrict__ P,
                                            const Momentum<double>& m, double* __restrict__ W, double& ps, double& pgg,
                                            double& psabs) {
@@ -405,12 +412,20 @@ __device__ __forceinline__ void iter_slice(const SolveArgs& a, int64_t s, int la
   const double di = (JM == 1) ? a.dinv[rr] : 0.0;
   const int32_t* __restrict__ cp = a.A.col + base + lane;
   const OffPtr so = slice_offsets(a.A, s);
-  const double* __restrict__ vp = a.A.val + base + lane;
   double acc = 0.0, asum = 0.0;
-  if (so)
-    fused_row_sums<true, YM, NT>(cp, so, (int32_t)rr, vp, width, P, R, beta, bz, false, acc, asum);
-  else
-    fused_row_sums<false, YM, NT>(cp, so, (int32_t)rr, vp, width, P, R, beta, bz, false, acc, asum);
+  if constexpr (V32) {
+    const float* __restrict__ vp = a.A.val32 + base + lane;
+    if (so)
+      fused_row_sums<true, YM, NT, double, float>(cp, so, (int32_t)rr, vp, width, P, R, beta, bz, false, acc, asum);
+    else
+      fused_row_sums<false, YM, NT, double, float>(cp, so, (int32_t)rr, vp, width, P, R, beta, bz, false, acc, asum);
+  } else {
+    const double* __restrict__ vp = a.A.val + base + lane;
+    if (so)
+      fused_row_sums<true, YM, NT>(cp, so, (int32_t)rr, vp, width, P, R, beta, bz, false, acc, asum);
+    else
+      fused_row_sums<false, YM, NT>(cp, so, (int32_t)rr, vp, width, P, R, beta, bz, false, acc, asum);
+  }
   double z = 0.0;
   if constexpr (JM == kJBlock) z = block_apply(a.jinv, s, lane, a.jblock, live ? acc - bi : 0.0);
   if (live) {
@@ -430,7 +445,8 @@ __device__ __forceinline__ void iter_slice(const SolveArgs& a, int64_t s, int la
 }
 
 // One slice of r = b - Q x; accumulates ||r||^2 (with obj: f(x) = sum_i x_i ((Q x)_i / 2 - b_i))
-// and optionally stores r.
+// and optionally stores r.  V32 as in iter_slice.
+template <bool V32 = false>
 __device__ __forceinline__ void resid_slice(const Sell& A, int64_t s, int lane, const double* __restrict__ X,
                                             const double* __restrict__ b, double* __restrict__ out, double& prr,
                                             bool obj = false) {
@@ -441,10 +457,16 @@ __device__ __forceinline__ void resid_slice(const Sell& A, int64_t s, int lane, 
   const double bi = b[live ? row : 0];
   const int32_t* __restrict__ cp = A.col + base + lane;
   const OffPtr so = slice_offsets(A, s);
-  const double* __restrict__ vp = A.val + base + lane;
   const int32_t rw = (int32_t)(live ? row : 0);
-  const double acc = so ? resid_row_sum<true>(cp, so, rw, vp, width, X, nullptr)
-                        : resid_row_sum<false>(cp, so, rw, vp, width, X, nullptr);
+  double acc;
+  if constexpr (V32) {
+    const float* __restrict__ vp = A.val32 + base + lane;
+    acc = so ? resid_row_sum<true, float>(cp, so, rw, vp, width, X, nullptr)
+             : resid_row_sum<false, float>(cp, so, rw, vp, width, X, nullptr);
+  } else {
+    const double* __restrict__ vp = A.val + base + lane;
+    acc = so ? resid_row_sum<true>(cp, so, rw, vp, width, X, nullptr) : resid_row_sum<false>(cp, so, rw, vp, width, X, nullptr);
+  }
   if (live) {
     const double r = bi - acc;
     if (out) out[row] = r;
@@ -502,7 +524,8 @@ __device__ __forceinline__ void inner_slice(const SolveArgs& a, int64_t s, int l
 // One slice of the float64 residual pass of the refinement loop: with D != null
 // the iterate is first updated, x_new = X + (double)D (formed at every gathered
 // column, stored for the own rows in Xn); then r = b - Q x_new in float64,
-// r32 = fl32(r), and ||r||^2, ||r32||^2 are accumulated.
+// r32 = fl32(r), and ||r||^2, ||r32||^2 are accumulated.  V32 as in iter_slice.
+template <bool V32 = false>
 __device__ __forceinline__ void resid_mixed_slice(const SolveArgs& a, int64_t s, int lane, const double* __restrict__ X,
                                                   const float* __restrict__ D, double* __restrict__ Xn, double& prr,
                                                   double& pr32) {
@@ -516,9 +539,16 @@ __device__ __forceinline__ void resid_mixed_slice(const SolveArgs& a, int64_t s,
   const float di0 = D ? D[rr] : 0.0f;
   const int32_t* __restrict__ cp = a.A.col + base + lane;
   const OffPtr so = slice_offsets(a.A, s);
-  const double* __restrict__ vp = a.A.val + base + lane;
-  const double acc = so ? resid_row_sum<true>(cp, so, (int32_t)rr, vp, width, X, D)
-                        : resid_row_sum<false>(cp, so, (int32_t)rr, vp, width, X, D);
+  double acc;
+  if constexpr (V32) {
+    const float* __restrict__ vp = a.A.val32 + base + lane;
+    acc = so ? resid_row_sum<true, float>(cp, so, (int32_t)rr, vp, width, X, D)
+             : resid_row_sum<false, float>(cp, so, (int32_t)rr, vp, width, X, D);
+  } else {
+    const double* __restrict__ vp = a.A.val + base + lane;
+    acc = so ? resid_row_sum<true>(cp, so, (int32_t)rr, vp, width, X, D)
+             : resid_row_sum<false>(cp, so, (int32_t)rr, vp, width, X, D);
+  }
   if (live) {
     if (D) Xn[row] = xi0 + (double)di0;
     const double r = bi - acc;
@@ -551,12 +581,13 @@ __device__ __forceinline__ void long_row_sums(const int32_t* __restrict__ col, c
   asum = (T)0;
   for (int64_t k = s + lane; k < e; k += (int64_t)kWave * kLongUnroll) {
     int c[kLongUnroll];
-    T v[kLongUnroll], y[kLongUnroll];
+    VT v[kLongUnroll];   // widened where used, so the loads stay in flight together
+    T y[kLongUnroll];
 #pragma unroll
     for (int q = 0; q < kLongUnroll; ++q)
       if (k + q * kWave < e) {
         c[q] = mat_ld<NT>(col + k + q * kWave);
-        v[q] = (T)mat_ld<NT>(val + k + q * kWave);
+        v[q] = mat_ld<NT>(val + k + q * kWave);
       }
 #pragma unroll
     for (int q = 0; q < kLongUnroll; ++q)
@@ -564,13 +595,14 @@ __device__ __forceinline__ void long_row_sums(const int32_t* __restrict__ col, c
 #pragma unroll
     for (int q = 0; q < kLongUnroll; ++q)
       if (k + q * kWave < e) {
-        acc = acc + v[q] * y[q];
-        asum = asum + (v[q] < (T)0 ? -v[q] : v[q]);
+        const T vq = (T)v[q];
+        acc = acc + vq * y[q];
+        asum = asum + (vq < (T)0 ? -vq : vq);
       }
   }
 }
 
-template <int JM, bool YM, bool NT = false>
+template <int JM, bool YM, bool NT = false, bool V32 = false>
 __device__ __forceinline__ void iter_long(const SolveArgs& a, int64_t r, int lane, const double* __restrict__ P,
                                           const Momentum<double>& m, double* __restrict__ W, double& ps, double& pgg,
                                           double& psabs) {
@@ -583,12 +615,18 @@ __device__ __forceinline__ void iter_long(const SolveArgs& a, int64_t r, int lan
   auto fP = [&](int c) { return P[c]; };
   auto fR = [&](int c) { return R[c]; };
   auto fY = [&](int c) { const double p = P[c]; return p + beta * (p - R[c]); };
-  if (bz)
-    long_row_sums<double, double, decltype(fP), NT>(a.A.lcol, a.A.lval, s, e, lane, fP, acc, asum);
-  else if (ym)
-    long_row_sums<double, double, decltype(fR), NT>(a.A.lcol, a.A.lval, s, e, lane, fR, acc, asum);
+  using VT = std::conditional_t<V32, float, double>;
+  const VT* __restrict__ lv;
+  if constexpr (V32)
+    lv = a.A.lval32;
   else
-    long_row_sums<double, double, decltype(fY), NT>(a.A.lcol, a.A.lval, s, e, lane, fY, acc, asum);
+    lv = a.A.lval;
+  if (bz)
+    long_row_sums<double, VT, decltype(fP), NT>(a.A.lcol, lv, s, e, lane, fP, acc, asum);
+  else if (ym)
+    long_row_sums<double, VT, decltype(fR), NT>(a.A.lcol, lv, s, e, lane, fR, acc, asum);
+  else
+    long_row_sums<double, VT, decltype(fY), NT>(a.A.lcol, lv, s, e, lane, fY, acc, asum);
   acc = wave_sum(acc);
   asum = wave_sum(asum);
   if (lane == 0) {
@@ -607,11 +645,16 @@ __device__ __forceinline__ void iter_long(const SolveArgs& a, int64_t r, int lan
   }
 }
 
+template <bool V32 = false>
 __device__ __forceinline__ void resid_long(const Sell& A, int64_t r, int lane, const double* __restrict__ X,
                                            const double* __restrict__ b, double* __restrict__ out, double& prr,
                                            bool obj = false) {
   double acc, asum;
-  long_row_sums<double>(A.lcol, A.lval, A.lrowptr[r], A.lrowptr[r + 1], lane, [&](int c) { return X[c]; }, acc, asum);
+  if constexpr (V32)
+    long_row_sums<double>(A.lcol, A.lval32, A.lrowptr[r], A.lrowptr[r + 1], lane, [&](int c) { return X[c]; }, acc,
+                          asum);
+  else
+    long_row_sums<double>(A.lcol, A.lval, A.lrowptr[r], A.lrowptr[r + 1], lane, [&](int c) { return X[c]; }, acc, asum);
   acc = wave_sum(acc);
   if (lane == 0) {
     const double res = b[r] - acc;
@@ -661,15 +704,22 @@ __device__ __forceinline__ void inner_long(const SolveArgs& a, int64_t r, int la
   }
 }
 
+template <bool V32 = false>
 __device__ __forceinline__ void resid_mixed_long(const SolveArgs& a, int64_t r, int lane, const double* __restrict__ X,
                                                  const float* __restrict__ D, double* __restrict__ Xn, double& prr,
                                                  double& pr32) {
   double acc, asum;
   const int64_t s = a.A.lrowptr[r], e = a.A.lrowptr[r + 1];
-  if (D)
-    long_row_sums<double>(a.A.lcol, a.A.lval, s, e, lane, [&](int c) { return X[c] + (double)D[c]; }, acc, asum);
+  using VT = std::conditional_t<V32, float, double>;
+  const VT* __restrict__ lv;
+  if constexpr (V32)
+    lv = a.A.lval32;
   else
-    long_row_sums<double>(a.A.lcol, a.A.lval, s, e, lane, [&](int c) { return X[c]; }, acc, asum);
+    lv = a.A.lval;
+  if (D)
+    long_row_sums<double>(a.A.lcol, lv, s, e, lane, [&](int c) { return X[c] + (double)D[c]; }, acc, asum);
+  else
+    long_row_sums<double>(a.A.lcol, lv, s, e, lane, [&](int c) { return X[c]; }, acc, asum);
   acc = wave_sum(acc);
   if (lane == 0) {
     if (D) Xn[r] = X[r] + (double)D[r];

@@ -396,7 +396,7 @@ __device__ __forceinline__ void for_wave_items(const Sell& A, int nxcd, bool lon
   for (int64_t s = wr.first; s < wr.end; s += wr.step) fs(s);
 }
 
-template <int JM, int BS, bool YM, bool NT = false>
+template <int JM, int BS, bool YM, bool NT = false, bool V32 = false>
 __device__ __forceinline__ void pass_iter64(const SolveArgs& a, const double* P, const Momentum<double>& m, double* W,
                                             double& p0, double& p1, double& p2) {
   const int lane = threadIdx.x % kWave;
@@ -404,19 +404,19 @@ __device__ __forceinline__ void pass_iter64(const SolveArgs& a, const double* P,
   for_wave_items<BS, YM>(
       a.A, a.nxcd, JM != kJBlock,
       [&](int64_t r) {
-        if constexpr (JM != kJBlock) iter_long<JM, YM, NT>(a, r, lane, P, m, W, p0, p1, p2);
+        if constexpr (JM != kJBlock) iter_long<JM, YM, NT, V32>(a, r, lane, P, m, W, p0, p1, p2);
       },
-      [&](int64_t s) { iter_slice<JM, YM, NT>(a, s, lane, P, m, W, p0, p1, p2); });
+      [&](int64_t s) { iter_slice<JM, YM, NT, V32>(a, s, lane, P, m, W, p0, p1, p2); });
 }
 
 // The workgroup's share of r = b - Q X (float64); ||r||^2 in p0 (with obj: f(X)).
-template <int BS, bool LISTS = false>
+template <int BS, bool LISTS = false, bool V32 = false>
 __device__ __forceinline__ void pass_resid64(const Sell& A, int nxcd, const double* X, const double* b, double* out,
                                              double& p0, bool obj = false) {
   const int lane = threadIdx.x % kWave;
   for_wave_items<BS, LISTS>(
-      A, nxcd, true, [&](int64_t r) { resid_long(A, r, lane, X, b, out, p0, obj); },
-      [&](int64_t s) { resid_slice(A, s, lane, X, b, out, p0, obj); });
+      A, nxcd, true, [&](int64_t r) { resid_long<V32>(A, r, lane, X, b, out, p0, obj); },
+      [&](int64_t s) { resid_slice<V32>(A, s, lane, X, b, out, p0, obj); });
 }
 
 // Phases a kernel instance carries (template parameter PS of run_pass and k_pass64): every phase, or
@@ -426,7 +426,7 @@ __device__ __forceinline__ void pass_resid64(const Sell& A, int nxcd, const doub
 constexpr int kPhasesAll = 0, kPhasesFp64 = 1, kPhasesMixed = 2;
 
 // The workgroup's share of one pass; partial sums in p0..p2 (per thread).
-template <int JM, int BS, bool YM, bool NT = false, int PS = kPhasesAll>
+template <int JM, int BS, bool YM, bool NT = false, int PS = kPhasesAll, bool V32 = false>
 __device__ __forceinline__ void run_pass(const SolveArgs& a, const PassView& v, double& p0, double& p1,
                                          double& p2) {
   const int lane = threadIdx.x % kWave;
@@ -439,9 +439,9 @@ __device__ __forceinline__ void run_pass(const SolveArgs& a, const PassView& v, 
     m.beta_next = v.beta_next;
     m.bz = v.bz != 0;
     m.ym = YM;
-    pass_iter64<JM, BS, YM, NT>(a, pick(a, v.iP), m, pick(a, v.iW), p0, p1, p2);
+    pass_iter64<JM, BS, YM, NT, V32>(a, pick(a, v.iP), m, pick(a, v.iW), p0, p1, p2);
   } else if (F64 && v.phase == PH_CONFIRM) {
-    pass_resid64<BS, YM>(a.A, a.nxcd, pick(a, v.iW), a.b, nullptr, p0, a.stop_obj != 0);
+    pass_resid64<BS, YM, V32>(a.A, a.nxcd, pick(a, v.iW), a.b, nullptr, p0, a.stop_obj != 0);
   } else if (MX && v.phase == PH_INNER32) {
     const float* P = pickf(a, v.iP);
     float* W = pickf(a, v.iW);
@@ -464,8 +464,8 @@ __device__ __forceinline__ void run_pass(const SolveArgs& a, const PassView& v, 
     const float* D = v.update ? pickf(a, v.iD) : nullptr;
     double* Xn = v.update ? pick(a, v.iXn) : nullptr;
     for_wave_items<BS, YM>(
-        a.A, a.nxcd, true, [&](int64_t r) { resid_mixed_long(a, r, lane, X, D, Xn, p0, p1); },
-        [&](int64_t s) { resid_mixed_slice(a, s, lane, X, D, Xn, p0, p1); });
+        a.A, a.nxcd, true, [&](int64_t r) { resid_mixed_long<V32>(a, r, lane, X, D, Xn, p0, p1); },
+        [&](int64_t s) { resid_mixed_slice<V32>(a, s, lane, X, D, Xn, p0, p1); });
   } else if (v.phase == PH_NORMB) {  // every row, flat
     for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < a.A.n; i += (int64_t)gridDim.x * BS) {
       const double x = a.b[i];
@@ -548,7 +548,7 @@ struct PartSums {
 // The launch passes k itself for k < 3 and any value of the same parity above 0 beyond (only k > 0
 // and k & 1 matter).  With `flag` set, workgroup 0 also stores the phase of C_k there (a host-visible
 // word the host polls instead of copying the control block back).
-template <int JM, int BS, bool YM, bool NT = false, int PS = kPhasesAll>
+template <int JM, int BS, bool YM, bool NT = false, int PS = kPhasesAll, bool V32 = false>
 __global__ void __launch_bounds__(BS) k_pass64(SolveArgs a, int k, int* flag) {
   __shared__ double sh[3][BS / kWave];
   __shared__ PassView v;
@@ -580,7 +580,7 @@ __global__ void __launch_bounds__(BS) k_pass64(SolveArgs a, int k, int* flag) {
   }
   if (v.phase == PH_DONE) return;
   double p0 = 0.0, p1 = 0.0, p2 = 0.0;
-  run_pass<JM, BS, YM, NT, PS>(a, v, p0, p1, p2);
+  run_pass<JM, BS, YM, NT, PS, V32>(a, v, p0, p1, p2);
   block_sum3<BS>(p0, p1, p2, sh);
   if (threadIdx.x == 0) {
     double* slot = a.part + ((size_t)(k & 1) * G + blockIdx.x) * kPartStride;

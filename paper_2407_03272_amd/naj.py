@@ -71,6 +71,7 @@ _SIGS = {
     "naj_destroy_system": (None, [_P]),
     "naj_system_info": (ctypes.c_int, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I64),
                                        ctypes.POINTER(_I32), ctypes.POINTER(_I64)]),
+    "naj_system_value_bytes": (ctypes.c_int, [_P, ctypes.POINTER(_I32)]),
     "naj_system_offset_slices": (ctypes.c_int, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64),
                                                 ctypes.POINTER(_I64)]),
     "naj_solve": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(NajOpts), _P, ctypes.POINTER(NajResult), _P, _I32,
@@ -258,8 +259,10 @@ class System:
                                       ctypes.byref(lay), ctypes.byref(st)))
         of, ns, onz = _I64(), _I64(), _I64()
         _check(load().naj_system_offset_slices(self._h, ctypes.byref(of), ctypes.byref(ns), ctypes.byref(onz)))
+        vb = _I32()
+        _check(load().naj_system_value_bytes(self._h, ctypes.byref(vb)))
         return dict(n=n.value, nnz=nnz.value, device_bytes=by.value, layout=lay.value, stored_entries=st.value,
-                    offset_slices=of.value, nslices=ns.value, offset_nnz=onz.value)
+                    offset_slices=of.value, nslices=ns.value, offset_nnz=onz.value, value_bytes=vb.value)
 
     def solve(self, b, x0=None, *, out=None, hist_cap: int | None = None, trace: bool = False, stream=None,
               **opts) -> tuple:

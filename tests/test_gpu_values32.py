@@ -1,0 +1,99 @@
+"""Systems whose stored values are all exact in float32 run their float64 passes on the float32 copy of the
+values (4-byte loads, widened to float64 where used).  That computes exactly what the 8-byte values do:
+every solve equals the same solve with NAJ_VALUES32=0 bit for bit (iterate, schedule, residual), with the
+launch shape held equal so that the value storage is the only difference.  Systems with any value that
+float32 does not hold keep 8 bytes.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2407_03272_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def naj():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2407_03272_amd import naj as N
+    N.load()
+    return N
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+def _make(naj, monkeypatch, s, values32, layout=None):
+    monkeypatch.setenv("NAJ_VALUES32", "1" if values32 else "0")
+    monkeypatch.setenv("NAJ_BS", "256")
+    monkeypatch.setenv("NAJ_BS_MIXED", "256")
+    if layout is not None:
+        monkeypatch.setenv("NAJ_LAYOUT", str(layout))
+    sysm = naj.System(s.rowptr, s.colidx, s.vals)
+    for v in ("NAJ_VALUES32", "NAJ_BS", "NAJ_BS_MIXED", "NAJ_LAYOUT"):
+        monkeypatch.delenv(v, raising=False)
+    return sysm
+
+
+def _pair_solves(naj, monkeypatch, s, layout=None, **opts):
+    out = []
+    for v32 in (True, False):
+        sysm = _make(naj, monkeypatch, s, v32, layout)
+        assert sysm.info()["value_bytes"] == (4 if v32 else 8)
+        x, info = sysm.solve(s.b, **opts)
+        out.append((x.cpu().numpy(), info))
+        sysm.close()
+    (x4, i4), (x8, i8) = out
+    assert i4.status == i8.status and i4.iterations == i8.iterations and i4.restart_log == i8.restart_log
+    assert i4.relres == i8.relres or (np.isnan(i4.relres) and np.isnan(i8.relres))
+    assert np.array_equal(x4, x8)
+    return x4, i4
+
+
+CASES = {
+    "poisson2d_64": lambda: W.poisson2d_64(),
+    "laplace3d_40": lambda: W.poisson_system((40, 40, 40), 12),
+    "chunglu_2e15": lambda: W.chung_lu_laplacian(1 << 15, 16, 2.5, seed=81, b_seed=82),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("precision", [0, 1])
+def test_values32_is_bitwise(naj, monkeypatch, case, precision):
+    _say("float32-stored values against 8-byte values:", case, "precision", precision)
+    s = CASES[case]()
+    x, info = _pair_solves(naj, monkeypatch, s, tol=1e-8, max_iter=20000, precision=precision, hist_cap=0)
+    assert info.status == 0
+    if case != "chunglu_2e15" and precision == 0:
+        # regular layouts: the oracle's answer, bit for bit
+        orc = O.accelerated_jacobi(s.rowptr, s.colidx, s.vals, s.b, tol=1e-8, max_iter=20000)
+        assert info.iterations == orc.iterations and np.array_equal(x, orc.x)
+
+
+def test_values32_long_rows_and_cap(naj, monkeypatch):
+    """The Section 4.1 system on the sorted layout (every row long: the long-row path reads the float32
+    copy), then an iteration cap (the residual of the last iterate on the confirmation path)."""
+    _say("float32-stored values, SDD n=600 all rows long")
+    s = W.sdd_system(600)
+    _pair_solves(naj, monkeypatch, s, layout=1, tol=1e-8, max_iter=5000)
+    _pair_solves(naj, monkeypatch, s, layout=1, tol=1e-12, max_iter=7)
+
+
+def test_inexact_values_keep_8_bytes(naj, monkeypatch):
+    _say("values that float32 does not hold")
+    rowptr, colidx, vals = W.random_spd(1003, 0.01, 5)
+    sysm = naj.System(rowptr, colidx, vals)
+    assert sysm.info()["value_bytes"] == 8
+    sysm.close()
+    s = W.poisson_system((40, 40, 40), 12)
+    vals = s.vals.copy()
+    vals[12345] += 1e-9                     # one value with no float32 twin
+    sysm = naj.System(s.rowptr, s.colidx, vals)
+    assert sysm.info()["value_bytes"] == 8
+    sysm.close()
+    sysm = naj.System(s.rowptr, s.colidx, s.vals)
+    assert sysm.info()["value_bytes"] == 4
+    sysm.close()
