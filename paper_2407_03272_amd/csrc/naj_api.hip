@@ -835,8 +835,13 @@ naj_status choose_grid(naj_system* s, hipStream_t st) {
   s->nxcd = nxcd;
   // 256 threads x 3 per CU measured best for 8-byte values on the 128^3 Laplacian; with 4-byte values
   // (exact in float32) 512 x 3 on regular layouts: 128^3 31.4 against 33.2 us per pass, 160^3 54.0
-  // against 72.1 (more waves in flight for the smaller loads, as for the float32 inner pass)
-  const int bs_default = (s->val_exact32 && s->layout == 0) ? 512 : 256;
+  // against 72.1 (more waves in flight for the smaller loads, as for the float32 inner pass).  512
+  // threads only once their grid is full (a wave per slice or long row at three workgroups per CU):
+  // below that, 256-thread workgroups spread the same waves over twice as many workgroups and CUs.
+  // Measured, float64 solves/s with 256 / 512 threads: 64x64 301 / 272, 32^3 455 / 407, 64^3 (4096
+  // slices) 198 / 195, 96^3 (13,824 slices) 84 / 88; mixed: 324 / 296, 550 / 495, 219 / 208, 88 / 109.
+  const bool full512 = s->nslices + s->n_long >= (int64_t)3 * s->cus * (512 / kWave);
+  const int bs_default = (s->val_exact32 && s->layout == 0 && full512) ? 512 : 256;
   int bs = env_int("NAJ_BS", bs_default);
   if (bs != 256 && bs != 512 && bs != 1024) bs = bs_default;
   s->pass_bs = bs;
@@ -869,8 +874,9 @@ naj_status choose_grid(naj_system* s, hipStream_t st) {
     // (4 with the column-offset form) and needs more waves in flight on regular layouts: 512 threads
     // x 3 per CU measured best on the 128^3 Laplacian (25.8 against 35.4 us per pass with the float64
     // shape) and on 160^3 (40.7 against 61.4 us).  The sorted layout's gather-bound pass keeps the
-    // float64 shape (Chung-Lu n = 2^22: 728 against 800 us per pass).
-    const int bsm_default = s->layout == 0 ? 512 : 256;
+    // float64 shape (Chung-Lu n = 2^22: 728 against 800 us per pass).  Small systems keep 256 threads
+    // (the float64 rule above).
+    const int bsm_default = (s->layout == 0 && full512) ? 512 : 256;
     int bsm = env_int("NAJ_BS_MIXED", bsm_default);
     if (bsm != 256 && bsm != 512 && bsm != 1024) bsm = bsm_default;
     s->pass_bs_mx = bsm;
