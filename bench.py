@@ -12,7 +12,7 @@ per launch / its mean launch duration from HIP events on the solve's stream),
 the HBM traffic per launch from the committed counter runs (null when the
 kernel sources changed since), and the CPU oracle baseline.
 
-    python bench.py [--steps K] [--warmup W] [--workload laplace3d_128|poisson2d_64|laplace3d_160]
+    python bench.py [--steps K] [--warmup W] [--workload laplace3d_128|poisson2d_64|laplace3d_160|laplace3d_192]
 """
 from __future__ import annotations
 
@@ -117,6 +117,8 @@ def make_workload(name: str):
         return W.poisson3d_128()
     if name == "laplace3d_160":
         return W.poisson_system((160, 160, 160), 1006, name="laplace3d_160")
+    if name == "laplace3d_192":
+        return W.poisson_system((192, 192, 192), 1007, name="laplace3d_192")
     if name == "poisson2d_64":
         return W.poisson2d_64()
     if name == "chunglu_4m":
@@ -676,12 +678,24 @@ def _sub(line: dict) -> dict:
             if k not in ("metric", "n_gpus", "higher_is_better", "scaling", "vs_baseline", "data")}
 
 
+MALL_BYTES = 256 << 20      # MI355X Infinity Cache
+
+
+def residency(rf: dict) -> str:
+    """Whether a pass's own bytes fit the MALL, which can then serve part of them between passes."""
+    mb = rf["layout_bytes_per_launch"] / 1e6
+    if rf["layout_bytes_per_launch"] <= MALL_BYTES:
+        return (f"MALL-resident: the pass moves about {mb:.0f} MB, under the 256 MiB MALL, so part of its "
+                "bytes may come from the MALL rather than HBM")
+    return f"beyond the MALL: about {mb:.0f} MB moved per pass"
+
+
 def bench_default(args, progress) -> dict:
     """The default run.  Top level: the 128^3 Laplacian in float64, one solve per step (value, latency,
     the fused pass's roofline, the mixed-precision comparison, the CPU oracle), and the measured copy
     bandwidth.  Sub-results, each with its own fixed step counts: the 64x64 Poisson system in float64
-    (against mixed and the CPU oracle), 160^3 in float64 (the pass beyond the
-    256 MB MALL), the Chung-Lu graph Laplacian n = 2^22 in mixed precision against float64, the
+    (against mixed and the CPU oracle), 160^3 and 192^3 in float64 (with 4-byte values the 160^3 pass
+    fits the 256 MiB MALL, the 192^3 pass does not), the Chung-Lu graph Laplacian n = 2^22 in mixed precision against float64, the
     512-system finite-element batch (mixed batch against float64 batch and float64 one system at a
     time), and the serving loop (p50/p99 latency, offered and saturated solves/s, float64 one request
     at a time)."""
@@ -709,17 +723,16 @@ def bench_default(args, progress) -> dict:
     rf["attainable_gbps"] = ab["best_gbps"]
     rf["frac_of_attainable"] = rf["achieved"] / ab["best_gbps"]
     rf["layout_frac_of_attainable"] = rf["layout_gbps"] / ab["best_gbps"]
-    rf["residency"] = ("MALL-resident: the pass moves about 192 MB, under the 256 MB MALL, so part of its "
-                       "bytes may come from the MALL rather than HBM; workloads.laplace3d_160 is the pass "
-                       "beyond the MALL")
+    rf["residency"] = residency(rf)
     subs = {}
     # the small configuration: 64x64 Poisson in float64 beside the CPU oracle (all host threads), and mixed
     subs["poisson2d_64"] = _sub(bench_single(args, "poisson2d_64", progress, 50, 5, "fp64", True,
                                              not args.no_cpu_baseline))
     progress(f"64x64 done at {time.perf_counter() - t_start:.0f} s")
-    subs["laplace3d_160"] = _sub(bench_single(args, "laplace3d_160", progress, 3, 1, "fp64", True, False))
-    subs["laplace3d_160"]["roofline"]["residency"] = "beyond the MALL: about 376 MB moved per pass"
-    progress(f"160^3 done at {time.perf_counter() - t_start:.0f} s")
+    for w in ("laplace3d_160", "laplace3d_192"):
+        subs[w] = _sub(bench_single(args, w, progress, 3, 1, "fp64", True, False))
+        subs[w]["roofline"]["residency"] = residency(subs[w]["roofline"])
+        progress(f"{w} done at {time.perf_counter() - t_start:.0f} s")
     subs["chunglu_4m"] = _sub(bench_single(args, "chunglu_4m", progress, 3, 1, "mixed", True, False))
     progress(f"Chung-Lu done at {time.perf_counter() - t_start:.0f} s")
     a2 = copy.copy(args)

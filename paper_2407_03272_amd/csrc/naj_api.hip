@@ -783,6 +783,11 @@ const void* pass_kernel_ym(int jm, int bs) {
 
 template <int PS, bool V32>
 const void* pass_kernel_ps(int jm, int bs, bool ym, bool nt) {
+  if constexpr (V32) {
+    if (nt && bs == 512 && !ym)
+      return jm ? (const void*)k_pass64<kJUser, 512, false, true, PS, true>
+                : (const void*)k_pass64<kJRowSum, 512, false, true, PS, true>;
+  }
   if (nt && bs == 256) {
     if (jm == kJBlock) return (const void*)k_pass64<kJBlock, 256, false, true, PS>;
     if (ym)
@@ -800,7 +805,8 @@ const void* pass_kernel_ps(int jm, int bs, bool ym, bool nt) {
 }
 
 // A block-J system always uses the regular layout in the two-iterate form, with its 8-byte values.
-// nt: the iteration passes load matrix entries non-temporally (instances for the 256-thread pass only).
+// nt: the iteration passes load matrix entries non-temporally (instances for the 256-thread pass, and
+// for the 512-thread two-iterate pass with 4-byte values; other shapes load them as usual).
 // v32: the float64 passes read the float32 copy of the values, which holds every value exactly.
 const void* pass_kernel(int jm, int bs, bool ym, bool nt, bool mixed, bool v32) {
   if (v32 && jm != kJBlock)
@@ -1789,9 +1795,10 @@ static naj_status create_system_impl(int64_t n, int64_t nnz, const int32_t* rowp
   {
     // A float64 iteration pass larger than the 256 MB MALL streams its matrix entries with
     // non-temporal loads, so they do not evict the gathered vectors (160^3: 92.7 -> 83.1 us per pass;
-    // the Section 4.1 system n = 6000: 95.5 -> 89.4 us; Chung-Lu n = 2^22: 911 -> 892 us).  A pass that
-    // fits keeps ordinary loads: the whole pass then stays in the MALL between passes (128^3: 36.9 us;
-    // 46.5 us with non-temporal loads).
+    // the Section 4.1 system n = 6000: 95.5 -> 89.4 us; Chung-Lu n = 2^22: 911 -> 892 us; 192^3 with
+    // 4-byte values, 512 threads: 124.7 -> 111.6 us).  A pass that fits keeps ordinary loads: the whole
+    // pass then stays in the MALL between passes (128^3: 36.9 us, 46.5 us with non-temporal loads;
+    // with 4-byte values 128^3 31.2 against 38.3 us, 160^3 54.3 against 67.7 us).
     const int64_t pass_bytes = (s->val_exact32 ? 4 : 8) * s->stored + 4 * (s->stored - s->off_nnz) + 32 * n +
                                8 * (int64_t)jblock * n;
     s->nt = env_int("NAJ_NT", pass_bytes > kMallBytes ? 1 : 0) ? 1 : 0;

@@ -97,3 +97,25 @@ def test_inexact_values_keep_8_bytes(naj, monkeypatch):
     sysm = naj.System(s.rowptr, s.colidx, s.vals)
     assert sysm.info()["value_bytes"] == 4
     sysm.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_values32_nontemporal_512(naj, monkeypatch, precision):
+    """The 512-thread pass with 4-byte values and non-temporal matrix loads (taken by regular systems whose
+    pass exceeds the MALL) against the same launch with ordinary loads: bit for bit."""
+    _say("float32-stored values, 512 threads, non-temporal loads, precision", precision)
+    s = W.poisson_system((40, 40, 40), 12)
+    out = []
+    for nt in ("1", "0"):
+        monkeypatch.setenv("NAJ_NT", nt)
+        monkeypatch.setenv("NAJ_BS", "512")
+        sysm = naj.System(s.rowptr, s.colidx, s.vals)
+        monkeypatch.delenv("NAJ_NT")
+        monkeypatch.delenv("NAJ_BS")
+        assert sysm.info()["value_bytes"] == 4
+        x, info = sysm.solve(s.b, tol=1e-8, max_iter=20000, precision=precision, hist_cap=0)
+        out.append((x.cpu().numpy(), info))
+        sysm.close()
+    (x1, i1), (x0, i0) = out
+    assert i1.status == 0 and i1.iterations == i0.iterations and i1.restart_log == i0.restart_log
+    assert np.array_equal(x1, x0)
