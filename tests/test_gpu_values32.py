@@ -107,11 +107,11 @@ def test_values32_nontemporal_512(naj, monkeypatch, precision):
     s = W.poisson_system((40, 40, 40), 12)
     out = []
     for nt in ("1", "0"):
-        monkeypatch.setenv("NAJ_NT", nt)
-        monkeypatch.setenv("NAJ_BS", "512")
+        for v, val in (("NAJ_NT", nt), ("NAJ_NT_MIXED", nt), ("NAJ_BS", "512"), ("NAJ_BS_MIXED", "512")):
+            monkeypatch.setenv(v, val)
         sysm = naj.System(s.rowptr, s.colidx, s.vals)
-        monkeypatch.delenv("NAJ_NT")
-        monkeypatch.delenv("NAJ_BS")
+        for v in ("NAJ_NT", "NAJ_NT_MIXED", "NAJ_BS", "NAJ_BS_MIXED"):
+            monkeypatch.delenv(v)
         assert sysm.info()["value_bytes"] == 4
         x, info = sysm.solve(s.b, tol=1e-8, max_iter=20000, precision=precision, hist_cap=0)
         out.append((x.cpu().numpy(), info))
