@@ -683,11 +683,11 @@ MALL_BYTES = 256 << 20      # MI355X Infinity Cache
 
 def residency(rf: dict) -> str:
     """Whether a pass's own bytes fit the MALL, which can then serve part of them between passes."""
-    mb = rf["layout_bytes_per_launch"] / 1e6
+    mib = rf["layout_bytes_per_launch"] / (1 << 20)
     if rf["layout_bytes_per_launch"] <= MALL_BYTES:
-        return (f"MALL-resident: the pass moves about {mb:.0f} MB, under the 256 MiB MALL, so part of its "
+        return (f"MALL-resident: the pass moves about {mib:.0f} MiB, under the 256 MiB MALL, so part of its "
                 "bytes may come from the MALL rather than HBM")
-    return f"beyond the MALL: about {mb:.0f} MB moved per pass"
+    return f"beyond the MALL: about {mib:.0f} MiB moved per pass"
 
 
 def bench_default(args, progress) -> dict:
