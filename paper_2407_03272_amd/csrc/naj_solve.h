@@ -362,15 +362,13 @@ __device__ __forceinline__ void load_view(const Ctrl* c, PassView* v) {
   v->beta_next = c->beta_next;
 }
 
-// The workgroup's share of one float64 iteration pass (long rows, then slices).  YM: the
-// materialized momentum form (a compile-time choice, so the two-iterate kernel carries none
-// of the materialized form's code).
-// The rows one wave takes in a pass.  With a balanced item list (A.witem, built for this launch shape
-// on the sorted layout) the wave sweeps its own list of long rows and slices; otherwise the long rows
-// are strided over every wave of the grid, then the wave takes its slice range.  `longs` is false
-// where the kernel instance has no long-row path (block J, whose layout has no long rows).  LISTS:
-// the instance carries the list path; only the materialized-momentum instances do, which are the
-// ones the sorted layout runs (the others keep their register budget and ignore the lists).
+// The rows one wave takes in a pass.  With an item list (A.witem, built for this launch shape: balanced
+// lists on the sorted layout, blocked slice orders on the regular layout) the wave sweeps its own list
+// of long rows and slices; otherwise the long rows are strided over every wave of the grid, then the
+// wave takes its slice range.  `longs` is false where the kernel instance has no long-row path (block
+// J, whose layout has no long rows).  LISTS: the instance carries the list path: the materialized-
+// momentum instances, which the sorted layout runs, and the float64 passes of the instances that read
+// 4-byte values (the others keep their register budget and ignore the lists).
 template <int BS, bool LISTS, class LongFn, class SliceFn>
 __device__ __forceinline__ void for_wave_items(const Sell& A, int nxcd, bool longs, LongFn&& fl, SliceFn&& fs) {
   if (LISTS && A.witem) {
@@ -396,12 +394,15 @@ __device__ __forceinline__ void for_wave_items(const Sell& A, int nxcd, bool lon
   for (int64_t s = wr.first; s < wr.end; s += wr.step) fs(s);
 }
 
+// The workgroup's share of one float64 iteration pass (long rows, then slices).  YM: the
+// materialized momentum form (a compile-time choice, so the two-iterate kernel carries none
+// of the materialized form's code).
 template <int JM, int BS, bool YM, bool NT = false, bool V32 = false>
 __device__ __forceinline__ void pass_iter64(const SolveArgs& a, const double* P, const Momentum<double>& m, double* W,
                                             double& p0, double& p1, double& p2) {
   const int lane = threadIdx.x % kWave;
   // a block J uses the regular layout: no long rows
-  for_wave_items<BS, YM>(
+  for_wave_items<BS, YM || V32>(
       a.A, a.nxcd, JM != kJBlock,
       [&](int64_t r) {
         if constexpr (JM != kJBlock) iter_long<JM, YM, NT, V32>(a, r, lane, P, m, W, p0, p1, p2);
@@ -441,7 +442,7 @@ __device__ __forceinline__ void run_pass(const SolveArgs& a, const PassView& v, 
     m.ym = YM;
     pass_iter64<JM, BS, YM, NT, V32>(a, pick(a, v.iP), m, pick(a, v.iW), p0, p1, p2);
   } else if (F64 && v.phase == PH_CONFIRM) {
-    pass_resid64<BS, YM, V32>(a.A, a.nxcd, pick(a, v.iW), a.b, nullptr, p0, a.stop_obj != 0);
+    pass_resid64<BS, YM || V32, V32>(a.A, a.nxcd, pick(a, v.iW), a.b, nullptr, p0, a.stop_obj != 0);
   } else if (MX && v.phase == PH_INNER32) {
     const float* P = pickf(a, v.iP);
     float* W = pickf(a, v.iW);

@@ -119,3 +119,39 @@ def test_values32_nontemporal_512(naj, monkeypatch, precision):
     (x1, i1), (x0, i0) = out
     assert i1.status == 0 and i1.iterations == i0.iterations and i1.restart_log == i0.restart_log
     assert np.array_equal(x1, x0)
+
+
+def _blocked_pair(naj, monkeypatch, s, blk, **opts):
+    out = []
+    for b in (blk, 0):
+        monkeypatch.setenv("NAJ_BLOCK", str(b))
+        sysm = naj.System(s.rowptr, s.colidx, s.vals)
+        monkeypatch.delenv("NAJ_BLOCK")
+        x, info = sysm.solve(s.b, **opts)
+        out.append((x.cpu().numpy(), info, sysm.info()["device_bytes"]))
+        sysm.close()
+    (xb, ib, db), (x0, i0, d0) = out
+    assert db > d0, "the blocked item lists were not built"
+    assert ib.status == i0.status and ib.iterations == i0.iterations and ib.restart_log == i0.restart_log
+    assert ib.relres == i0.relres
+    assert np.array_equal(xb, x0)
+    return xb, ib
+
+
+@pytest.mark.parametrize("shape", [(40, 40, 40), (37, 29, 48)])
+def test_blocked_slice_order_is_bitwise(naj, monkeypatch, shape):
+    """Float64 passes that visit the slices in column blocks through the planes (item lists on the
+    regular layout) compute every row as the slice order does: the same solve bit for bit, through the
+    relres stop, the objective stop and an iteration cap (confirmation on the last iterate); a mixed solve
+    of a system that holds such lists runs its own order and is unchanged."""
+    _say("blocked slice order against slice order:", shape)
+    s = W.poisson_system(shape, 13)
+    x, info = _blocked_pair(naj, monkeypatch, s, 8, tol=1e-8, max_iter=20000, hist_cap=0)
+    assert info.status == 0
+    orc = O.accelerated_jacobi(s.rowptr, s.colidx, s.vals, s.b, tol=1e-8, max_iter=20000)
+    assert info.iterations == orc.iterations and np.array_equal(x, orc.x)
+    _blocked_pair(naj, monkeypatch, s, 8, tol=1e-12, max_iter=9, hist_cap=0)
+    # f* = -<b, x*>/2 from the oracle's answer (any value serves: both solves take the same one)
+    _blocked_pair(naj, monkeypatch, s, 5, tol=1e-10, max_iter=20000, hist_cap=0, stop=naj.NAJ_STOP_OBJECTIVE,
+                  fstar=-0.5 * float(s.b @ orc.x))
+    _blocked_pair(naj, monkeypatch, s, 8, tol=1e-8, max_iter=20000, hist_cap=0, precision=1)
