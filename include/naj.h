@@ -172,7 +172,7 @@ naj_status naj_system_info(const naj_system *sys, int64_t *n, int64_t *nnz, int6
  * they compute exactly what they compute from the 8-byte values (every result is the same bit for
  * bit) on half the value bytes; J of eq. (J-diag), the absolute row sum, comes from the same values.
  * NAJ_VALUES32=0 in the environment at creation keeps 8 bytes.  A block-J system (eq. (J-blkdiag))
- * always reads 8.
+ * reads its inverse blocks in float64 either way.
  *   bytes : host, 4 or 8
  * Errors: NAJ_EINVAL for a NULL argument.
  */

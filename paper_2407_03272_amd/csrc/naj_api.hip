@@ -790,7 +790,7 @@ const void* pass_kernel_ps(int jm, int bs, bool ym, bool nt) {
                 : (const void*)k_pass64<kJRowSum, 512, false, true, PS, true>;
   }
   if (nt && bs == 256) {
-    if (jm == kJBlock) return (const void*)k_pass64<kJBlock, 256, false, true, PS>;
+    if (jm == kJBlock) return (const void*)k_pass64<kJBlock, 256, false, true, PS, V32>;
     if (ym)
       return jm ? (const void*)k_pass64<kJUser, 256, true, true, PS, V32>
                 : (const void*)k_pass64<kJRowSum, 256, true, true, PS, V32>;
@@ -798,19 +798,19 @@ const void* pass_kernel_ps(int jm, int bs, bool ym, bool nt) {
               : (const void*)k_pass64<kJRowSum, 256, false, true, PS, V32>;
   }
   if (jm == kJBlock) {
-    if (bs == 1024) return (const void*)k_pass64<kJBlock, 1024, false, false, PS>;
-    if (bs == 512) return (const void*)k_pass64<kJBlock, 512, false, false, PS>;
-    return (const void*)k_pass64<kJBlock, 256, false, false, PS>;
+    if (bs == 1024) return (const void*)k_pass64<kJBlock, 1024, false, false, PS, V32>;
+    if (bs == 512) return (const void*)k_pass64<kJBlock, 512, false, false, PS, V32>;
+    return (const void*)k_pass64<kJBlock, 256, false, false, PS, V32>;
   }
   return ym ? pass_kernel_ym<true, PS, V32>(jm, bs) : pass_kernel_ym<false, PS, V32>(jm, bs);
 }
 
-// A block-J system always uses the regular layout in the two-iterate form, with its 8-byte values.
+// A block-J system always uses the regular layout in the two-iterate form.
 // nt: the iteration passes load matrix entries non-temporally (instances for the 256-thread pass, and
 // for the 512-thread two-iterate pass with 4-byte values; other shapes load them as usual).
 // v32: the float64 passes read the float32 copy of the values, which holds every value exactly.
 const void* pass_kernel(int jm, int bs, bool ym, bool nt, bool mixed, bool v32) {
-  if (v32 && jm != kJBlock)
+  if (v32)
     return mixed ? pass_kernel_ps<kPhasesMixed, true>(jm, bs, ym, nt) : pass_kernel_ps<kPhasesFp64, true>(jm, bs, ym, nt);
   return mixed ? pass_kernel_ps<kPhasesMixed, false>(jm, bs, ym, nt) : pass_kernel_ps<kPhasesFp64, false>(jm, bs, ym, nt);
 }
@@ -847,14 +847,16 @@ naj_status choose_grid(naj_system* s, hipStream_t st) {
   // below that, 256-thread workgroups spread the same waves over twice as many workgroups and CUs.
   // Measured, float64 solves/s with 256 / 512 threads: 64x64 301 / 272, 32^3 455 / 407, 64^3 (4096
   // slices) 198 / 195, 96^3 (13,824 slices) 84 / 88; mixed: 324 / 296, 550 / 495, 219 / 208, 88 / 109.
+  // A block-J pass (89 VGPRs: five waves per SIMD) cannot hold three 512-thread workgroups per CU.
   const bool full512 = s->nslices + s->n_long >= (int64_t)3 * s->cus * (512 / kWave);
-  const int bs_default = (s->val_exact32 && s->layout == 0 && full512) ? 512 : 256;
+  const int bs_default = (s->val_exact32 && s->layout == 0 && full512 && !s->jblock) ? 512 : 256;
   int bs = env_int("NAJ_BS", bs_default);
   if (bs != 256 && bs != 512 && bs != 1024) bs = bs_default;
   s->pass_bs = bs;
   // three workgroups per CU for 256 threads, and for 512 threads with 4-byte values (the measured
   // shapes above); otherwise 512 x 1 or 1024 x 1
-  const int per_cu_default = (bs == 256 || (bs == 512 && s->val_exact32 && s->layout == 0)) ? 3 : 2 * 256 / bs;
+  const int per_cu_default =
+      (bs == 256 || (bs == 512 && s->val_exact32 && s->layout == 0 && !s->jblock)) ? 3 : 2 * 256 / bs;
   const int per_cu = std::max(1, env_int("NAJ_WG_PER_CU", per_cu_default));
   int g = per_cu * s->cus;
   // NAJ_GRID: an explicit float64 grid (at most the resident limit of the launch shape), for sweeps
@@ -1811,8 +1813,9 @@ static naj_status create_system_impl(int64_t n, int64_t nnz, const int32_t* rowp
   STEP(build_layout(s, rowptr, colidx, vals, st));
   // 4-byte values for the float64 passes when every stored value is exact in float32 (graph Laplacians
   // with integer weights, stencils, the Section 4.1 matrix): the same products and sums on half the
-  // value bytes.  NAJ_VALUES32=0 keeps the 8-byte values.
-  if (env_int("NAJ_VALUES32", 1) && !jblock) {
+  // value bytes.  NAJ_VALUES32=0 keeps the 8-byte values.  A block J keeps its inverse blocks in float64
+  // (128^3, 8-row blocks: 59.4 -> 45.8 us per float64 pass, the pass then fitting the MALL).
+  if (env_int("NAJ_VALUES32", 1)) {
     HSTEP(hipMemsetAsync(flag, 0, sizeof(int), st));
     const int64_t ns = s->nslices > 0 ? (int64_t)s->hslice[s->nslices] : 0;
     if (ns > 0) {
@@ -1872,6 +1875,7 @@ static naj_status create_system_impl(int64_t n, int64_t nnz, const int32_t* rowp
     }
     // float64 passes only: the float32 inner pass of mixed solves measured no faster with the blocked
     // order (128^3 25.8 -> 25.6 us, 160^3 41.5 -> 42.0, 192^3 81.5 -> 82.2)
+    // not with a block J: its 128^3 pass (8-row blocks) measured 45.8 us in slice order, 47.1 blocked
     if (s->layout == 0 && s->mode == kModePass && s->val_exact32 && !jblock)
       STEP(build_blocked_items(s, 0, s->grid, s->pass_bs, env_int("NAJ_BLOCK", 32), st));
     for (int i = 0; i < 3 + s->ymode; ++i) STEP(dev_alloc(s, &s->vec[i], (size_t)n));

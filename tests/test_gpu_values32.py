@@ -155,3 +155,24 @@ def test_blocked_slice_order_is_bitwise(naj, monkeypatch, shape):
     _blocked_pair(naj, monkeypatch, s, 5, tol=1e-10, max_iter=20000, hist_cap=0, stop=naj.NAJ_STOP_OBJECTIVE,
                   fstar=-0.5 * float(s.b @ orc.x))
     _blocked_pair(naj, monkeypatch, s, 8, tol=1e-8, max_iter=20000, hist_cap=0, precision=1)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_values32_block_j(naj, monkeypatch, precision):
+    """A block-diagonal J (eq. (J-blkdiag), 8-row blocks) on 4-byte values: its inverse blocks stay float64,
+    and the solve equals the 8-byte one bit for bit."""
+    _say("float32-stored values with a block J, precision", precision)
+    s = W.poisson_system((32, 24, 40), 17)
+    out = []
+    for v32 in ("1", "0"):
+        monkeypatch.setenv("NAJ_VALUES32", v32)
+        sysm = naj.System(s.rowptr, s.colidx, s.vals, jblock=8)
+        monkeypatch.delenv("NAJ_VALUES32")
+        assert sysm.info()["value_bytes"] == (4 if v32 == "1" else 8)
+        x, info = sysm.solve(s.b, tol=1e-8, max_iter=20000, precision=precision, hist_cap=0)
+        out.append((x.cpu().numpy(), info, sysm.block_inverse().cpu().numpy()))
+        sysm.close()
+    (x4, i4, j4), (x8, i8, j8) = out
+    assert i4.status == 0 and i4.iterations == i8.iterations and i4.restart_log == i8.restart_log
+    assert np.array_equal(j4, j8)
+    assert np.array_equal(x4, x8)
