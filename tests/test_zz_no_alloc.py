@@ -62,6 +62,23 @@ def test_noalloc_float64_large_then_small(naj):
     ss.close()
 
 
+def test_noalloc_blocked_slice_order(naj):
+    """A 3D grid whose planes (2288 rows) exceed a 32-slice block: its float64 passes sweep the blocked
+    item lists, which the allocation-free solve reads from the system as naj_solve does."""
+    blk = W.poisson_system((52, 44, 48), 16)
+    small = W.poisson_system((24, 24), 5)
+    sb = naj.System(blk.rowptr, blk.colidx, blk.vals)
+    ss = naj.System(small.rowptr, small.colidx, small.vals)
+    for rep in range(2):
+        _say(f"noalloc float64 52x44x48 (blocked slice order), round {rep}")
+        ib = _same(naj, sb, blk, tol=1e-8, max_iter=20000)
+        assert ib.status == 0 and ib.relres <= 1e-8
+        _say(f"noalloc float64 24x24 after it, round {rep}")
+        _same(naj, ss, small, tol=1e-8, max_iter=20000)
+    sb.close()
+    ss.close()
+
+
 def test_noalloc_sorted_layout_and_x0(naj):
     c = W.chung_lu_laplacian(1 << 15, 16, 2.5, seed=81, b_seed=82)
     d = W.chung_lu_laplacian(1 << 12, 16, 2.5, seed=83, b_seed=84)
