@@ -186,10 +186,13 @@ naj_status naj_system_value_bytes(const naj_system *sys, int32_t *bytes);
  * them (4 bytes less per stored entry).  A row lacking an offset stores an explicit zero there,
  * which leaves every sum, and so every result, unchanged.  The form is taken where S is no longer
  * than the slice's longest row (so no more entries are stored); NAJ_OFFSETS=0 in the environment at
- * creation disables it.
+ * creation disables it.  The long rows of layout 1 (one wavefront per row) whose columns, in stored
+ * order, are one run c0, c0 + 1, ... (dense rows) likewise form their column indices from c0;
+ * NAJ_LONG_RUNS=0 disables that.
  *   offset_slices : slices in the column-offset form (0 with layout 1)
  *   nslices       : slices of the layout
- *   offset_nnz    : the caller's nonzeros held in those slices (no column index is read for them)
+ *   offset_nnz    : the caller's nonzeros whose column index the passes form instead of reading: those
+ *                   held in the column-offset slices and in the dense-run long rows
  * Any output may be NULL.  Errors: NAJ_EINVAL for a NULL system.
  */
 naj_status naj_system_offset_slices(const naj_system *sys, int64_t *offset_slices, int64_t *nslices,

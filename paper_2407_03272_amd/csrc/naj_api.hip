@@ -261,6 +261,21 @@ __device__ __forceinline__ long long wave_min_ll(long long v) {
   return v;
 }
 
+// Dense runs of the long rows: lrun[r] = c0 when row r's columns, in stored order, are c0, c0 + 1, ...,
+// else -1.  One wavefront per row (blockDim is a multiple of 64, so r is the same across a wavefront).
+__global__ void k_long_runs(const int64_t* lrowptr, const int32_t* lcol, int64_t nlong, int32_t* lrun) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t r = t / kWave;
+  if (r >= nlong) return;
+  const int lane = (int)(t % kWave);
+  const int64_t s = lrowptr[r], e = lrowptr[r + 1];
+  const int32_t c0 = lcol[s];   // a long row holds more than 128 entries
+  bool run = true;
+  for (int64_t k = s + lane; k < e; k += kWave) run = run && (int64_t)lcol[k] - c0 == k - s;
+  run = __all(run) != 0;
+  if (lane == 0) lrun[r] = run ? c0 : -1;
+}
+
 // Column-offset records of the slices of the regular layout (rows 64 s + lane).  One wavefront per
 // slice merges its rows' offsets (column - row) into the increasing list S.  The slice qualifies when
 // all 64 rows exist, every row's offsets increase strictly (so its entries, in stored order, take
@@ -396,7 +411,8 @@ __global__ void k_long_abs_sum(Sell A, double* out) {
   const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
   for (int64_t r = w0; r < A.n_long; r += nw) {
     double acc, asum;
-    long_row_sums<double>(A.lcol, A.lval, A.lrowptr[r], A.lrowptr[r + 1], lane, [](int) { return 0.0; }, acc, asum);
+    long_row_sums<double>(A.lcol, A.lval, A.lrowptr[r], A.lrowptr[r + 1], lane, [](int) { return 0.0; }, acc, asum,
+                          long_run(A, r));
     asum = wave_sum(asum);
     if (lane == 0) out[r] = asum == 0.0 ? 1.0 : asum;
   }
@@ -663,6 +679,8 @@ struct naj_system {
   int64_t n_long = 0;              // rows handled one wavefront per row
   int64_t* lrowptr = nullptr;
   int32_t* lcol = nullptr;
+  int32_t* lrun = nullptr;         // [n_long] dense-run starts of the long rows (see Sell::lrun), or null
+  int64_t run_nnz = 0;             // nonzeros of the dense-run long rows
   double* lval = nullptr;
   float* lval32 = nullptr;
   int layout = 0;                  // 0 = slices in caller order; 1 = sorted slices + long rows
@@ -742,7 +760,7 @@ naj_status dev_alloc(naj_system* s, T** p, size_t count) {
 void free_system(naj_system* s) {
   if (!s) return;
   for (void* p : {(void*)s->slice_ptr, (void*)s->col, (void*)s->val, (void*)s->val32, (void*)s->dinv, (void*)s->jinv, (void*)s->jinv32, (void*)s->perm,
-                  (void*)s->dom_bounds, (void*)s->bperm, (void*)s->lrowptr, (void*)s->lcol, (void*)s->lval,
+                  (void*)s->dom_bounds, (void*)s->bperm, (void*)s->lrowptr, (void*)s->lcol, (void*)s->lrun, (void*)s->lval,
                   (void*)s->lval32, (void*)s->part, (void*)s->ctrl, (void*)s->bar, (void*)s->counters, (void*)s->hist,
                   (void*)s->trace, (void*)s->scal, (void*)s->soff, (void*)s->woff[0], (void*)s->witem[0],
                   (void*)s->woff[1], (void*)s->witem[1]})
@@ -977,6 +995,7 @@ Sell sell_of(const naj_system* s) {
   A.n_long = s->n_long;
   A.lrowptr = s->lrowptr;
   A.lcol = s->lcol;
+  A.lrun = s->lrun;
   A.lval = s->lval;
   A.lval32 = s->lval32;
   A.soff = s->soff;
@@ -1220,6 +1239,18 @@ naj_status build_layout(naj_system* s, const int32_t* rowptr, const int32_t* col
       HIP_TRY(hipMemcpyAsync(s->lval, tmp.tmp_val, sizeof(double) * lnnz, hipMemcpyDeviceToDevice, st));
       hipLaunchKernelGGL(k_to_float, dim3(blocks_for(lnnz, kAux)), dim3(kAux), 0, st, s->lval, s->lval32, lnnz);
       HIP_TRY(hipGetLastError());
+      if (nlong > 0 && env_int("NAJ_LONG_RUNS", 1)) {
+        rc = dev_alloc(s, &s->lrun, (size_t)nlong);
+        if (rc != NAJ_OK) return rc;
+        hipLaunchKernelGGL(k_long_runs, dim3(blocks_for(nlong * kWave, kAux)), dim3(kAux), 0, st, s->lrowptr, s->lcol,
+                           nlong, s->lrun);
+        HIP_TRY(hipGetLastError());
+        std::vector<int32_t> hrun((size_t)nlong);
+        HIP_TRY(hipMemcpyAsync(hrun.data(), s->lrun, sizeof(int32_t) * nlong, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        for (int64_t r = 0; r < nlong; ++r)
+          if (hrun[(size_t)r] >= 0) s->run_nnz += nrp[r + 1] - nrp[r];
+      }
     }
     src_rp = tmp.tmp_rp32;
     src_col = tmp.tmp_col;
@@ -1860,11 +1891,12 @@ static naj_status create_system_impl(int64_t n, int64_t nnz, const int32_t* rowp
     // 4-byte values, 512 threads: 124.7 -> 111.6 us).  A pass that fits keeps ordinary loads: the whole
     // pass then stays in the MALL between passes (128^3: 36.9 us, 46.5 us with non-temporal loads;
     // with 4-byte values 128^3 31.2 against 38.3 us, 160^3 54.3 against 67.7 us).
-    const int64_t pass_bytes = (s->val_exact32 ? 4 : 8) * s->stored + 4 * (s->stored - s->off_nnz) + 32 * n +
+    const int64_t pass_bytes = (s->val_exact32 ? 4 : 8) * s->stored + 4 * (s->stored - s->off_nnz - s->run_nnz) + 32 * n +
                                8 * (int64_t)jblock * n;
     s->nt = env_int("NAJ_NT", pass_bytes > kMallBytes ? 1 : 0) ? 1 : 0;
     // the same rule for the float32 inner pass of mixed solves (4-byte values, float32 vectors and r32)
-    const int64_t inner_bytes = 4 * s->stored + 4 * (s->stored - s->off_nnz) + 20 * n + 4 * (int64_t)jblock * n;
+    const int64_t inner_bytes =
+        4 * s->stored + 4 * (s->stored - s->off_nnz - s->run_nnz) + 20 * n + 4 * (int64_t)jblock * n;
     s->nt_mx = env_int("NAJ_NT_MIXED", inner_bytes > kMallBytes ? 1 : 0) ? 1 : 0;
   }
   if (!lean) {   // workspace of the single-solve drivers
@@ -1957,7 +1989,7 @@ naj_status naj_system_offset_slices(const naj_system* s, int64_t* offset_slices,
   if (!s) return fail(NAJ_EINVAL, "system is NULL");
   if (offset_slices) *offset_slices = s->off_slices;
   if (nslices) *nslices = s->nslices;
-  if (offset_nnz) *offset_nnz = s->off_nnz;
+  if (offset_nnz) *offset_nnz = s->off_nnz + s->run_nnz;
   return NAJ_OK;
 }
 

@@ -133,6 +133,8 @@ struct Sell {
   const int64_t* dom_bounds;  // [nxcd+1] slice ranges of the L2 domains balanced by stored entries, or null
   const int64_t* lrowptr;     // [n_long+1]
   const int32_t* lcol;
+  const int32_t* lrun;        // [n_long] c0 when a long row's columns are c0, c0 + 1, ... in stored order
+                              // (a dense run: the passes form them instead of loading lcol), else -1; or null
   const double* lval;
   const float* lval32;
   const int32_t* soff;        // [nslices * kOffRec] column-offset records of the slices, or null
@@ -572,11 +574,16 @@ __device__ __forceinline__ float wave_sum_f(float v) {
   return v;
 }
 
+// The dense-run start of long row r (see Sell::lrun), or -1.
+__device__ __forceinline__ int32_t long_run(const Sell& A, int64_t r) { return A.lrun ? A.lrun[r] : -1; }
+
 // sum_k v_k * y(c_k) and sum_k |v_k| over [s, e); Y maps a column to its (already formed) y value.
-// NT: the row's entries are loaded non-temporally (see mat_ld).
-template <typename T, typename VT, typename YF, bool NT = false>
-__device__ __forceinline__ void long_row_sums(const int32_t* __restrict__ col, const VT* __restrict__ val, int64_t s,
-                                              int64_t e, int lane, YF yof, T& acc, T& asum) {
+// NT: the row's entries are loaded non-temporally (see mat_ld).  RUN: the columns are run + (k - s)
+// (a dense run), formed instead of loaded; the products and their order are the same either way.
+template <bool RUN, typename T, typename VT, typename YF, bool NT>
+__device__ __forceinline__ void long_row_sums_in(const int32_t* __restrict__ col, const VT* __restrict__ val,
+                                                 int64_t s, int64_t e, int lane, YF yof, T& acc, T& asum,
+                                                 int32_t run) {
   acc = (T)0;
   asum = (T)0;
   for (int64_t k = s + lane; k < e; k += (int64_t)kWave * kLongUnroll) {
@@ -586,7 +593,8 @@ __device__ __forceinline__ void long_row_sums(const int32_t* __restrict__ col, c
 #pragma unroll
     for (int q = 0; q < kLongUnroll; ++q)
       if (k + q * kWave < e) {
-        c[q] = mat_ld<NT>(col + k + q * kWave);
+        if constexpr (RUN) c[q] = run + (int)(k + q * kWave - s);
+        else c[q] = mat_ld<NT>(col + k + q * kWave);
         v[q] = mat_ld<NT>(val + k + q * kWave);
       }
 #pragma unroll
@@ -600,6 +608,13 @@ __device__ __forceinline__ void long_row_sums(const int32_t* __restrict__ col, c
         asum = asum + (vq < (T)0 ? -vq : vq);
       }
   }
+}
+
+template <typename T, typename VT, typename YF, bool NT = false>
+__device__ __forceinline__ void long_row_sums(const int32_t* __restrict__ col, const VT* __restrict__ val, int64_t s,
+                                              int64_t e, int lane, YF yof, T& acc, T& asum, int32_t run = -1) {
+  if (run >= 0) long_row_sums_in<true, T, VT, YF, NT>(col, val, s, e, lane, yof, acc, asum, run);
+  else long_row_sums_in<false, T, VT, YF, NT>(col, val, s, e, lane, yof, acc, asum, run);
 }
 
 template <int JM, bool YM, bool NT = false, bool V32 = false>
@@ -622,11 +637,11 @@ __device__ __forceinline__ void iter_long(const SolveArgs& a, int64_t r, int lan
   else
     lv = a.A.lval;
   if (bz)
-    long_row_sums<double, VT, decltype(fP), NT>(a.A.lcol, lv, s, e, lane, fP, acc, asum);
+    long_row_sums<double, VT, decltype(fP), NT>(a.A.lcol, lv, s, e, lane, fP, acc, asum, long_run(a.A, r));
   else if (ym)
-    long_row_sums<double, VT, decltype(fR), NT>(a.A.lcol, lv, s, e, lane, fR, acc, asum);
+    long_row_sums<double, VT, decltype(fR), NT>(a.A.lcol, lv, s, e, lane, fR, acc, asum, long_run(a.A, r));
   else
-    long_row_sums<double, VT, decltype(fY), NT>(a.A.lcol, lv, s, e, lane, fY, acc, asum);
+    long_row_sums<double, VT, decltype(fY), NT>(a.A.lcol, lv, s, e, lane, fY, acc, asum, long_run(a.A, r));
   acc = wave_sum(acc);
   asum = wave_sum(asum);
   if (lane == 0) {
@@ -652,9 +667,10 @@ __device__ __forceinline__ void resid_long(const Sell& A, int64_t r, int lane, c
   double acc, asum;
   if constexpr (V32)
     long_row_sums<double>(A.lcol, A.lval32, A.lrowptr[r], A.lrowptr[r + 1], lane, [&](int c) { return X[c]; }, acc,
-                          asum);
+                          asum, long_run(A, r));
   else
-    long_row_sums<double>(A.lcol, A.lval, A.lrowptr[r], A.lrowptr[r + 1], lane, [&](int c) { return X[c]; }, acc, asum);
+    long_row_sums<double>(A.lcol, A.lval, A.lrowptr[r], A.lrowptr[r + 1], lane, [&](int c) { return X[c]; }, acc, asum,
+                          long_run(A, r));
   acc = wave_sum(acc);
   if (lane == 0) {
     const double res = b[r] - acc;
@@ -678,13 +694,13 @@ __device__ __forceinline__ void inner_long(const SolveArgs& a, int64_t r, int la
   auto fR = [&](int c) { return R[c]; };
   auto fY = [&](int c) { const float p = P[c]; return p + beta * (p - R[c]); };
   if (zp)
-    long_row_sums<float, float, decltype(f0), NT>(a.A.lcol, a.A.lval32, s, e, lane, f0, acc, asum);
+    long_row_sums<float, float, decltype(f0), NT>(a.A.lcol, a.A.lval32, s, e, lane, f0, acc, asum, long_run(a.A, r));
   else if (bz)
-    long_row_sums<float, float, decltype(fP), NT>(a.A.lcol, a.A.lval32, s, e, lane, fP, acc, asum);
+    long_row_sums<float, float, decltype(fP), NT>(a.A.lcol, a.A.lval32, s, e, lane, fP, acc, asum, long_run(a.A, r));
   else if (ym)
-    long_row_sums<float, float, decltype(fR), NT>(a.A.lcol, a.A.lval32, s, e, lane, fR, acc, asum);
+    long_row_sums<float, float, decltype(fR), NT>(a.A.lcol, a.A.lval32, s, e, lane, fR, acc, asum, long_run(a.A, r));
   else
-    long_row_sums<float, float, decltype(fY), NT>(a.A.lcol, a.A.lval32, s, e, lane, fY, acc, asum);
+    long_row_sums<float, float, decltype(fY), NT>(a.A.lcol, a.A.lval32, s, e, lane, fY, acc, asum, long_run(a.A, r));
   acc = wave_sum_f(acc);
   asum = wave_sum_f(asum);
   if (lane == 0) {
@@ -717,9 +733,10 @@ __device__ __forceinline__ void resid_mixed_long(const SolveArgs& a, int64_t r, 
   else
     lv = a.A.lval;
   if (D)
-    long_row_sums<double>(a.A.lcol, lv, s, e, lane, [&](int c) { return X[c] + (double)D[c]; }, acc, asum);
+    long_row_sums<double>(a.A.lcol, lv, s, e, lane, [&](int c) { return X[c] + (double)D[c]; }, acc, asum,
+                          long_run(a.A, r));
   else
-    long_row_sums<double>(a.A.lcol, lv, s, e, lane, [&](int c) { return X[c]; }, acc, asum);
+    long_row_sums<double>(a.A.lcol, lv, s, e, lane, [&](int c) { return X[c]; }, acc, asum, long_run(a.A, r));
   acc = wave_sum(acc);
   if (lane == 0) {
     if (D) Xn[r] = X[r] + (double)D[r];
