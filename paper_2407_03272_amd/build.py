@@ -13,7 +13,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libnaj.so")
 SOURCES = ["naj_api.hip"]
-HEADERS = ["naj_device.h", "naj_solve.h", "naj_partition.h", "naj_batch.h", "naj_server_impl.h"]
+HEADERS = ["naj_device.h", "naj_solve.h", "naj_partition.h", "naj_batch.h", "naj_server_impl.h", "naj_lists.h"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -20,6 +20,7 @@
 #include "naj_device.h"
 #include "naj_solve.h"
 #include "naj_batch.h"
+#include "naj_lists.h"
 #include <map>
 #include <mutex>
 #include <queue>
@@ -1343,25 +1344,8 @@ naj_status build_wave_items(naj_system* s, int which, int grid, int bs, hipStrea
     const int64_t width = (s->hslice[sl + 1] - s->hslice[sl]) / kWave;
     cost[(size_t)(nlong + sl)] = (width + kUnroll - 1) / kUnroll + 1;
   }
-  std::vector<int32_t> order((size_t)nitems);
-  for (int64_t i = 0; i < nitems; ++i) order[(size_t)i] = (int32_t)i;
-  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return cost[(size_t)x] > cost[(size_t)y]; });
-  using Load = std::pair<int64_t, int32_t>;   // (work so far, wave)
-  std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
-  for (int32_t w = 0; w < waves; ++w) heap.push({0, w});
-  std::vector<int32_t> owner((size_t)nitems);
-  for (const int32_t it : order) {
-    Load l = heap.top();
-    heap.pop();
-    owner[(size_t)it] = l.second;
-    l.first += cost[(size_t)it];
-    heap.push(l);
-  }
-  std::vector<int32_t> off((size_t)waves + 1, 0), items((size_t)nitems);
-  for (int64_t i = 0; i < nitems; ++i) off[(size_t)owner[(size_t)i] + 1] += 1;
-  for (int w = 0; w < waves; ++w) off[(size_t)w + 1] += off[(size_t)w];
-  std::vector<int32_t> pos(off.begin(), off.end() - 1);
-  for (int64_t i = 0; i < nitems; ++i) items[(size_t)pos[(size_t)owner[(size_t)i]]++] = (int32_t)i;
+  std::vector<int32_t> off, items;
+  balanced_wave_lists(cost, waves, off, items);
   naj_status rc = dev_alloc(s, &s->woff[which], (size_t)waves + 1);
   if (rc == NAJ_OK) rc = dev_alloc(s, &s->witem[which], (size_t)nitems);
   if (rc != NAJ_OK) return rc;
@@ -1391,29 +1375,8 @@ naj_status build_blocked_items(naj_system* s, int which, int grid, int bs, int64
   const int64_t ns = s->nslices;
   const int64_t band = (s->reach + kWave - 1) / kWave;
   if (ns <= 0 || ns + s->n_long >= INT32_MAX || blk <= 0 || band <= blk || s->n_long != 0) return NAJ_OK;
-  const int ndom = effective_domains(grid, s->nxcd);
-  const int per_dom = grid / ndom;
-  const int nwd = per_dom * wpb;   // waves of one domain
-  std::vector<std::vector<int32_t>> lists((size_t)waves);
-  for (int d = 0; d < ndom; ++d) {
-    const int64_t lo = ns * d / ndom, hi = ns * (d + 1) / ndom;
-    int64_t k = 0;   // position in the domain's blocked order
-    for (int64_t c = 0; c * blk < band; ++c)
-      for (int64_t z = lo / band; z * band < hi; ++z) {
-        const int64_t a = std::max(lo, z * band + c * blk), b = std::min(hi, std::min(z * band + (c + 1) * blk, (z + 1) * band));
-        for (int64_t sl = a; sl < b; ++sl, ++k) {
-          const int q = (int)(k % nwd);                  // the domain's wave that takes it
-          const int w = (q / wpb) * ndom + d;            // its workgroup (workgroup w runs on domain w mod ndom)
-          lists[(size_t)w * wpb + q % wpb].push_back((int32_t)(s->n_long + sl));
-        }
-      }
-  }
-  std::vector<int32_t> off((size_t)waves + 1, 0), items;
-  items.reserve((size_t)ns);
-  for (int w = 0; w < waves; ++w) {
-    items.insert(items.end(), lists[(size_t)w].begin(), lists[(size_t)w].end());
-    off[(size_t)w + 1] = (int32_t)items.size();
-  }
+  std::vector<int32_t> off, items;
+  if (!blocked_wave_lists(ns, s->n_long, band, blk, s->nxcd, grid, wpb, off, items)) return NAJ_OK;
   if ((int64_t)items.size() != ns) return fail(NAJ_EDEVICE, "blocked item lists cover %lld of %lld slices",
                                               (long long)items.size(), (long long)ns);
   naj_status rc = dev_alloc(s, &s->woff[which], (size_t)waves + 1);
