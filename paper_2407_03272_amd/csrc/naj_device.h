@@ -138,9 +138,10 @@ struct Sell {
   const double* lval;
   const float* lval32;
   const int32_t* soff;        // [nslices * kOffRec] column-offset records of the slices, or null
-  // Balanced per-wave item lists of the per-pass kernel (sorted layout), or null: wave w of the launch
-  // takes items witem[woff[w] .. woff[w+1]), an item being long row r (< n_long) or slice it - n_long.
-  // Built for one launch shape; null for every other kernel.
+  // Per-wave item lists of the per-pass kernel (balanced on the sorted layout, a blocked slice order on
+  // the regular layout), or null: wave w of the launch takes items witem[woff[w] .. woff[w+1]), an item
+  // being long row r (< n_long) or slice it - n_long.  Built for one launch shape; null for every other
+  // kernel.
   const int32_t* woff;
   const int32_t* witem;
 };

@@ -549,6 +549,9 @@ struct PartSums {
 // The launch passes k itself for k < 3 and any value of the same parity above 0 beyond (only k > 0
 // and k & 1 matter).  With `flag` set, workgroup 0 also stores the phase of C_k there (a host-visible
 // word the host polls instead of copying the control block back).
+// Instances: J mode, block size, momentum form (YM), non-temporal matrix loads (NT), the phases carried
+// (PS), and V32: the float64 passes read the float32 copy of the values, which the host uses only when
+// that copy holds every value exactly (the products are then those of the 8-byte values).
 template <int JM, int BS, bool YM, bool NT = false, int PS = kPhasesAll, bool V32 = false>
 __global__ void __launch_bounds__(BS) k_pass64(SolveArgs a, int k, int* flag) {
   __shared__ double sh[3][BS / kWave];
