@@ -33,6 +33,40 @@ def test_layout_bytes_drop_the_offset_slices_columns():
     assert bench.bytes_per_refinement_residual(n, nnz) == 12 * nnz + 4 * (n + 1) + 32 * n
 
 
+def test_value_bytes_as_read():
+    """With the float32 copy of exact values the float64 passes read 4 bytes per value: the yardstick's s_v
+    is those 4 bytes (vectors stay 8), for the iteration and residual passes and for whole solves."""
+    n, nnz = 128 ** 3, 14_581_760
+    assert bench.bytes_per_iteration(n, nnz, s_v=4) == 192_151_556
+    assert bench.bytes_per_iteration(n, nnz, s_v=4, nnz_off=14_581_122) == 133_827_068
+    n2, nnz2 = 192 ** 3, 192 ** 3 + 6 * 191 * 192 ** 2
+    assert nnz2 == 49_324_032
+    assert bench.bytes_per_iteration(n2, nnz2, s_v=4) == 649_396_228
+    assert bench.bytes_per_residual(n, nnz) - bench.bytes_per_residual(n, nnz, s_v=4) == 4 * nnz
+
+    class Info:
+        iterations, passes, confirmations = 731, 733, 1
+    assert (bench.solve_bytes(n, nnz, Info, mixed=False, vb=4)
+            == 8 * n + 731 * 192_151_556 + bench.bytes_per_residual(n, nnz, s_v=4))
+
+
+def test_traffic_records_match_their_keys():
+    """A committed counter record is reported only for the pass kernel sources, grid and value size it was
+    taken with."""
+    import json
+    path = os.path.join(ROOT, "profiles", "k_pass64_laplace3d_128_traffic.json")
+    rec = json.load(open(path))
+    assert bench.measured_traffic("laplace3d_128", rec["grid"], rec["value_bytes"]) == (
+        rec["traffic_bytes_per_pass"] if rec["kernel_source_sha256"] == bench.kernel_source_hash() else None)
+    assert bench.measured_traffic("laplace3d_128", rec["grid"] + 8, rec["value_bytes"]) is None
+    assert bench.measured_traffic("laplace3d_128", rec["grid"], 12 - rec["value_bytes"]) is None
+    assert bench.measured_traffic("no_such_workload") is None
+    # comments do not enter the key
+    src = {"naj_device.h": "int a; // x\n/* y */ int b;\n", "naj_solve.h": "", "naj_partition.h": ""}
+    src2 = {"naj_device.h": "int a; // changed\n/* also changed */ int b;\n", "naj_solve.h": "", "naj_partition.h": ""}
+    assert bench.kernel_source_hash(src.__getitem__) == bench.kernel_source_hash(src2.__getitem__)
+
+
 def test_solve_bytes_count_every_pass():
     class Info:
         iterations, passes, confirmations = 731, 733, 3
