@@ -10,6 +10,10 @@
   4096 instances reaches relres 1e-8 by an independent float64 product, and sampled regular-layout
   instances equal the mixed oracle bit for bit (the oracle computes them one by one).
 
+* The 192^3 Laplacian (beyond the MALL, too large for the oracle's complete run): relres by an independent
+  host product, and bit-for-bit agreement between the benchmark configuration and the 8-byte slice-order
+  solve.
+
 The 128^3 Laplacian at full size is covered in test_gpu_parity.py against a stored oracle run.
 """
 import os
@@ -124,3 +128,30 @@ def test_fe_batch_512_full_size(naj):
     bt.close()
     for sm in syss:
         sm.close()
+
+
+def test_laplace3d_192_beyond_the_mall(naj, monkeypatch):
+    """The 192^3 Laplacian (7.08 M rows, the pass beyond the 256 MiB MALL) in the configuration bench.py
+    times (4-byte value reads, blocked slice order, non-temporal matrix loads, 512 x 3): relres <= 1e-8 by
+    an independent host product of the caller's CSR, and the same iterates and schedule, bit for bit, as
+    the solve that reads 8-byte values in slice order (its own launch shape and loads)."""
+    import scipy.sparse as sp
+    _say("192^3 float64 at full size, bench configuration")
+    s = W.poisson_system((192, 192, 192), 1007)
+    sysm = naj.System(s.rowptr, s.colidx, s.vals)
+    assert sysm.info()["value_bytes"] == 4
+    x, info = sysm.solve(s.b, tol=1e-8, max_iter=20000, hist_cap=0)
+    x = x.cpu().numpy()
+    sysm.close()
+    assert info.status == 0 and info.grid == 768
+    q = sp.csr_matrix((s.vals, s.colidx, s.rowptr), shape=(s.n, s.n))
+    assert np.linalg.norm(s.b - q @ x) / np.linalg.norm(s.b) <= 1e-8 * (1 + 1e-6)
+    _say("192^3 float64 with 8-byte values in slice order")
+    monkeypatch.setenv("NAJ_VALUES32", "0")
+    sysm = naj.System(s.rowptr, s.colidx, s.vals)
+    monkeypatch.delenv("NAJ_VALUES32")
+    assert sysm.info()["value_bytes"] == 8
+    x8, i8 = sysm.solve(s.b, tol=1e-8, max_iter=20000, hist_cap=0)
+    sysm.close()
+    assert i8.iterations == info.iterations and i8.restart_log == info.restart_log
+    assert np.array_equal(x8.cpu().numpy(), x)
