@@ -67,6 +67,15 @@ def test_traffic_records_match_their_keys():
     assert bench.kernel_source_hash(src.__getitem__) == bench.kernel_source_hash(src2.__getitem__)
 
 
+def test_residency_label():
+    """A pass is called MALL-resident when the bytes it moves fit the 256 MiB MALL."""
+    assert bench.residency({"layout_bytes_per_launch": 133_827_068}).startswith("MALL-resident")
+    assert bench.residency({"layout_bytes_per_launch": 261_534_956}).startswith("MALL-resident")
+    assert bench.residency({"layout_bytes_per_launch": 452_102_652}).startswith("beyond the MALL")
+    assert bench.residency({"layout_bytes_per_launch": 256 << 20}).startswith("MALL-resident")
+    assert bench.residency({"layout_bytes_per_launch": (256 << 20) + 1}).startswith("beyond")
+
+
 def test_solve_bytes_count_every_pass():
     class Info:
         iterations, passes, confirmations = 731, 733, 3

@@ -10,9 +10,9 @@
   4096 instances reaches relres 1e-8 by an independent float64 product, and sampled regular-layout
   instances equal the mixed oracle bit for bit (the oracle computes them one by one).
 
-* The 192^3 Laplacian (beyond the MALL, too large for the oracle's complete run): relres by an independent
-  host product, and bit-for-bit agreement between the benchmark configuration and the 8-byte slice-order
-  solve.
+* The 160^3 and 192^3 Laplacians (in and beyond the MALL, too large for the oracle's complete run): relres
+  by an independent host product, and bit-for-bit agreement of the iterates with the slice order (160^3)
+  and with the 8-byte slice-order solve (192^3).
 
 The 128^3 Laplacian at full size is covered in test_gpu_parity.py against a stored oracle run.
 """
@@ -128,6 +128,30 @@ def test_fe_batch_512_full_size(naj):
     bt.close()
     for sm in syss:
         sm.close()
+
+
+def test_laplace3d_160_in_the_mall(naj):
+    """The 160^3 Laplacian (4.1 M rows; with 4-byte values its pass fits the MALL and keeps ordinary loads)
+    in the configuration bench.py times: relres <= 1e-8 by an independent host product, and the blocked
+    slice order's iterates equal the slice order's bit for bit."""
+    import scipy.sparse as sp
+    _say("160^3 float64 at full size, bench configuration")
+    s = W.poisson_system((160, 160, 160), 1006)
+    out = []
+    for blk in ("32", "0"):
+        os.environ["NAJ_BLOCK"] = blk
+        try:
+            sysm = naj.System(s.rowptr, s.colidx, s.vals)
+        finally:
+            del os.environ["NAJ_BLOCK"]
+        x, info = sysm.solve(s.b, tol=1e-8, max_iter=20000, hist_cap=0)
+        out.append((x.cpu().numpy(), info))
+        sysm.close()
+    (xb, ib), (x0, i0) = out
+    assert ib.status == 0 and ib.grid == 768 and ib.iterations == i0.iterations and ib.restart_log == i0.restart_log
+    assert np.array_equal(xb, x0)
+    q = sp.csr_matrix((s.vals, s.colidx, s.rowptr), shape=(s.n, s.n))
+    assert np.linalg.norm(s.b - q @ xb) / np.linalg.norm(s.b) <= 1e-8 * (1 + 1e-6)
 
 
 def test_laplace3d_192_beyond_the_mall(naj, monkeypatch):
