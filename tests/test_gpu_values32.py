@@ -157,6 +157,9 @@ def test_blocked_slice_order_is_bitwise(naj, monkeypatch, shape):
     _blocked_pair(naj, monkeypatch, s, 5, tol=1e-10, max_iter=20000, hist_cap=0, stop=naj.NAJ_STOP_OBJECTIVE,
                   fstar=-0.5 * float(s.b @ orc.x))
     _blocked_pair(naj, monkeypatch, s, 8, tol=1e-8, max_iter=20000, hist_cap=0, precision=1)
+    # a caller's starting point (seeded, not the iterate of another solve)
+    x0 = np.random.default_rng(29).standard_normal(s.n)
+    _blocked_pair(naj, monkeypatch, s, 8, x0=x0, tol=1e-8, max_iter=20000, hist_cap=0)
 
 
 @pytest.mark.parametrize("precision", [0, 1])
